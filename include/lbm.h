@@ -1,0 +1,182 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the thermal pseudopotential lattice
+ * Boltzmann model of L. Wang, J. Huang, K. He, "A new thermal lattice Boltzmann model for
+ * liquid-vapor phase change" (arXiv:2205.00686).
+ *
+ * One time step is the fused D2Q9 MRT pseudopotential flow step (Section 2, Eqs. 1-11:
+ * Peng-Robinson pressure, pseudopotential, interaction/wetting/buoyancy forces, Li et al.'s
+ * forcing in moment space, streaming) coupled to the D2Q5 MRT temperature step with the
+ * rho*c_v-modified collision and linear equilibrium (Section 3.2, Eqs. 20-26 and 39-53).
+ *
+ * Conventions shared by every entry point:
+ *   - Lattice units, dx = dt = 1.  Grid nx x ny nodes; host fields are FP64, row-major
+ *     [ny][nx] with x fastest, owned by the caller.
+ *   - Device memory is owned by the caller: one allocation of lbm_footprint_bytes() bytes
+ *     (any 256-byte aligned device pointer, e.g. a torch uint8 tensor), which must outlive
+ *     the context.  The library allocates no device memory of its own.
+ *   - Work is enqueued on the HIP stream given at creation (hipStream_t passed as void*;
+ *     NULL = the null stream).  lbm_step is asynchronous; calls that return host data
+ *     synchronise the stream.
+ *   - Every call returns an lbm_status; lbm_last_error() gives the text of the last error on
+ *     a context.  A numerical failure detected on the device (density <= 0, temperature
+ *     <= 0, a pseudopotential argument < 0, NaN/Inf) is sticky: it is reported as
+ *     LBM_E_NUMERIC by the next synchronising call and every later call on the context.
+ *   - One context per stream; calls on one context are not thread-safe.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_INVAL = -1,   /* invalid argument or parameter set */
+  LBM_E_NOMEM = -2,   /* device buffer smaller than the footprint */
+  LBM_E_DEVICE = -3,  /* a HIP runtime call failed */
+  LBM_E_NUMERIC = -4, /* the device flagged a numerical failure (sticky) */
+  LBM_E_STATE = -5    /* call out of order (step before init) or context already failed */
+} lbm_status;
+
+enum { LBM_FP32 = 0, LBM_FP64 = 1 };
+
+/* test-only flags: they zero terms inside the one step kernel, they add no code path */
+enum {
+  LBM_FREEZE_FLOW = 1u, /* populations f are not updated; u = (sum c_i f_i)/rho, no force */
+  LBM_NO_S = 2u         /* correction term S_i of Eq. (24) switched off */
+};
+
+/* Parameters of the problem statement.  lbm_params_default() fills the paper's values. */
+typedef struct {
+  int32_t nx, ny;        /* grid size, each >= 3 */
+  int32_t precision;     /* LBM_FP32: populations stored and collided in FP32; LBM_FP64 */
+  int32_t reserved0;
+  /* Peng-Robinson EOS (Eq. 10): a = 3/49, b = 2/21, R = 1, acentric factor 0.344;
+     interaction strength G = -1 (Eq. 9) */
+  double a, b, R, acentric, G;
+  /* D2Q9 MRT (Eq. 5): kinematic viscosity nu gives s_p = 1/(3 nu + 1/2); s_e, s_eps, s_q;
+     sigma of Li et al.'s forcing (Eq. 8); all rates not tied to nu are 1 (Section 4) */
+  double nu, s_e, s_eps, s_q, sigma;
+  /* D2Q5 MRT (Eqs. 26, 39, 53): conductivity lambda gives varsigma_1 = varsigma_2 =
+     1/(lambda/chat_s^2 + 1/2) with chat_s^2 = wdot/2; heat capacity c_v; weight parameter
+     wdot in (0,1); relaxation rates varsigma_3, varsigma_4 */
+  double lambda, cv, wdot, vs3, vs4;
+  /* buoyancy F_b = (rho - rho_ave) g (Section 4.3); rho_ave = NaN -> FP64 mean of the
+     initial density, computed by lbm_init */
+  double gx, gy, rho_ave;
+  int32_t y_walls;       /* 0: periodic in y; 1: no-slip halfway walls at y=-1/2 and ny-1/2 */
+  int32_t thermal_box;   /* 1: Dirichlet T = T_box on all four edges (flow stays periodic) */
+  /* wall temperatures (y_walls = 1): T_bot(x) = T_bot + hot_dT exp(-(x-hot_x0)^2/(2 hot_sigma^2)),
+     T_top; applied by halfway anti-bounce-back */
+  double T_box, T_top, T_bot, hot_dT, hot_x0, hot_sigma;
+  double theta_bot_deg, theta_top_deg; /* contact angles of the geometric wetting rule (Eq. 54) */
+  uint32_t flags;        /* LBM_FREEZE_FLOW | LBM_NO_S, tests only */
+  uint32_t reserved1;
+} lbm_params;
+
+/* Fill *p with the paper's parameter values (Sections 2 and 4) for an nx x ny FP32 grid. */
+void lbm_params_default(lbm_params* p, int32_t nx, int32_t ny);
+
+/* Check a parameter set without touching the device.  LBM_E_INVAL if nx or ny < 3, the grid
+   has more than 2^31 nodes, a relaxation rate is outside (0, 2), wdot outside (0, 1),
+   c_v <= 0, nu <= 0 or lambda <= 0. */
+lbm_status lbm_validate(const lbm_params* p);
+
+/* Exact device bytes a context needs (populations f and g in two copies, the temperature
+   history, and a small control block); 0 if lbm_validate fails. */
+size_t lbm_footprint_bytes(const lbm_params* p);
+
+/* Create a context on the current HIP device over caller-owned device memory dev_mem of
+   `bytes` bytes (256-byte aligned), enqueueing on hip_stream.  *out receives the handle.
+   LBM_E_INVAL on bad parameters or a misaligned pointer, LBM_E_NOMEM if bytes is smaller than
+   lbm_footprint_bytes(p). */
+lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hip_stream, lbm_ctx** out);
+
+/* Initial state from host FP64 fields (each nx*ny): f_i = f_i^eq(rho, u) (Eq. 3),
+   g_i = what_i T (Eq. 22), temperature history = T.  Computes rho_ave if it is NaN.
+   LBM_E_INVAL if rho or T is not positive and finite, or min(rho) * c_v < 1 (the modified
+   collision of Eq. 39 weights the old population by 1 - 1/(rho c_v), which must not be
+   negative).  Synchronises the stream. */
+lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const double* uy, const double* T);
+
+/* Enqueue n time steps (Eqs. 1-11 then 20-53, one fused kernel per step).  Asynchronous.
+   LBM_E_STATE before lbm_init or after a failure. */
+lbm_status lbm_step(lbm_ctx* h, int64_t n);
+
+/* Number of steps taken since lbm_init (or the count restored by lbm_load_state). */
+int64_t lbm_steps_done(const lbm_ctx* h);
+
+/* Wait for the stream and report any device-side numerical failure. */
+lbm_status lbm_sync(lbm_ctx* h);
+
+/* Current macroscopic fields to host FP64 arrays (each nx*ny, any may be NULL):
+   rho = sum f_i, u = (sum c_i f_i + F_n/2)/rho with the force of the current state (Eq. 11),
+   T = sum g_i (Eq. 25).  Synchronises. */
+lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, double* T);
+
+/* Mass sum(rho) and thermal energy sum(rho c_v T) of the current state, accumulated in FP64
+   in a fixed order (deterministic).  Synchronises. */
+lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy);
+
+/* Raw state to / from a host buffer of lbm_state_bytes() bytes: f[9][ny][nx], g[5][ny][nx],
+   history[2][ny][nx] in the context's precision, then three 8-byte words: the step count
+   (int64), rho_ave and T_ref (FP64).  The temperature populations are stored relative to
+   T_ref (the mean initial temperature): the buffer holds g_i - what_i T_ref and T - T_ref for
+   the history.  Resuming from a saved state reproduces an uninterrupted run bit for bit. */
+size_t lbm_state_bytes(const lbm_ctx* h);
+lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes);
+lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes);
+
+/* Maxwell equal-area coexistence of the Peng-Robinson EOS at temperature T (host, FP64):
+   rho_l, rho_g, p_sat.  LBM_E_INVAL if T is at or above the critical temperature. */
+lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_l, double* rho_g, double* p_sat);
+
+/* Critical temperature 0.0778 a / (0.45724 b R) implied by a and b (text after Eq. 10). */
+double lbm_critical_temperature(const lbm_params* p);
+
+/* Release the context (host metadata only; the caller frees the device memory). */
+lbm_status lbm_destroy(lbm_ctx* h);
+
+const char* lbm_strerror(lbm_status s);
+const char* lbm_last_error(const lbm_ctx* h);
+
+/* ------------------------------------------------------------------------------------
+ * Batched execution: many initialised contexts (uneven grids and parameters, same precision,
+ * same device) advanced together, each step one kernel launch over the tiles of every
+ * active instance; launches are captured in a HIP graph and replayed.  Each instance's
+ * arithmetic is exactly that of its own lbm_step, so results are bit-identical to running it
+ * alone.  A batch needs lbm_batch_footprint_bytes(n) bytes of caller-owned device memory.
+ */
+size_t lbm_batch_footprint_bytes(int n);
+
+/* Build a batch over ctxs[0..n) (all initialised, same precision), enqueueing on hip_stream. */
+lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t bytes, void* hip_stream,
+                            lbm_batch** out);
+
+/* Give instance i a budget of `steps` more steps (0 parks it).  Takes effect at the next
+   lbm_batch_step. */
+lbm_status lbm_batch_set_budget(lbm_batch* b, int i, int64_t steps);
+
+/* Advance every instance with budget left by up to k steps (each stops at its own budget). */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t k);
+
+/* Steps still budgeted for instance i. */
+int64_t lbm_batch_remaining(const lbm_batch* b, int i);
+
+/* Wait for the batch's stream; report per-instance numerical failures in status[n] (may be
+   NULL).  The contexts' step counters are brought up to date. */
+lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status);
+
+lbm_status lbm_batch_destroy(lbm_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

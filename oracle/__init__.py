@@ -103,6 +103,7 @@ def lib():
         L.orc_diagnostics.argtypes = [vp, dp, dp, dp, dp]; L.orc_diagnostics.restype = None
         L.orc_rho_ave.argtypes = [vp]; L.orc_rho_ave.restype = d
         L.orc_steps.argtypes = [vp]; L.orc_steps.restype = ctypes.c_long
+        L.orc_num_threads.argtypes = []; L.orc_num_threads.restype = ctypes.c_int
         L.orc_matrices.argtypes = [vp, dp, dp, dp, dp]; L.orc_matrices.restype = None
         L.orc_relaxation.argtypes = [vp, dp, dp]; L.orc_relaxation.restype = None
         _lib = L
@@ -249,6 +250,11 @@ class Oracle:
         return S, L
 
 
+def num_threads() -> int:
+    """Number of threads the oracle's grid loops use (OpenMP)."""
+    return int(lib().orc_num_threads())
+
+
 def run(prm, rho, ux, uy, T, steps: int):
     """Convenience: initialise, run ``steps`` steps, return (rho, ux, uy, T)."""
     o = Oracle(prm).init(rho, ux, uy, T)
@@ -256,5 +262,5 @@ def run(prm, rho, ux, uy, T, steps: int):
     return o.fields()
 
 
-__all__ = ["build", "Tc", "eos_p", "eos_dpdT", "psi", "maxwell", "feq", "meq", "force_moments",
+__all__ = ["build", "num_threads", "Tc", "eos_p", "eos_dpdT", "psi", "maxwell", "feq", "meq", "force_moments",
            "Oracle", "OracleError", "run", "FREEZE_FLOW", "NO_S"]

@@ -42,6 +42,9 @@
  *         conserved on the closed and periodic domains used here), unless given.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -676,6 +679,15 @@ void orc_diagnostics(const orc_state* s, double* mass, double* energy, double* s
 }
 
 double orc_rho_ave(const orc_state* s) { return s->rho_ave; }
+
+/* threads the grid loops run on */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 long orc_steps(const orc_state* s) { return s->steps; }
 
 /* The matrices in use (for the identity checks of the tests). */

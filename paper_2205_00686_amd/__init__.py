@@ -1,0 +1,232 @@
+"""MI355X (gfx950) library for the thermal pseudopotential lattice Boltzmann model of
+Wang, Huang & He, "A new thermal lattice Boltzmann model for liquid-vapor phase change"
+(arXiv:2205.00686).
+
+The hot path (one fused D2Q9 + D2Q5 time step per kernel launch) lives in the HIP library
+``liblbm.so`` behind the C ABI of ``include/lbm.h``.  This package only marshals arguments:
+``Solver`` wraps one simulation (device memory from a torch uint8 tensor, work on the current
+torch stream), ``Batch`` advances many simulations per launch, ``serve.Server`` runs the
+continuous-batching request loop.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import _native
+from ._native import LBM_FP32, LBM_FP64, LBM_FREEZE_FLOW, LBM_NO_S, NativeLibraryMissing
+
+__all__ = ["Solver", "Batch", "LbmError", "params_struct", "coexistence", "critical_temperature",
+           "footprint_bytes", "LBM_FP32", "LBM_FP64", "LBM_FREEZE_FLOW", "LBM_NO_S", "NativeLibraryMissing"]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+def _check(status: int, handle=None):
+    if status != 0:
+        L = _native.lib()
+        text = L.lbm_strerror(status).decode()
+        if handle:
+            text += ": " + (L.lbm_last_error(handle) or b"").decode()
+        raise LbmError(status, text)
+
+
+_FIELDS = [name for name, _ in _native.LbmParams._fields_ if not name.startswith("reserved")]
+
+
+def params_struct(prm, precision: int = LBM_FP32) -> _native.LbmParams:
+    """lbm_params from any object carrying the parameter names (e.g. workloads.Params)."""
+    c = _native.LbmParams()
+    _native.lib().lbm_params_default(ctypes.byref(c), int(prm.nx), int(prm.ny))
+    for name in _FIELDS:
+        if name == "precision":
+            continue
+        if hasattr(prm, name):
+            setattr(c, name, getattr(prm, name))
+    c.precision = int(precision)
+    return c
+
+
+def critical_temperature(prm) -> float:
+    c = params_struct(prm)
+    return _native.lib().lbm_critical_temperature(ctypes.byref(c))
+
+
+def coexistence(prm, T: float):
+    """(rho_l, rho_g, p_sat) of the Maxwell construction of the EOS at T (library, FP64 host)."""
+    c = params_struct(prm)
+    rl, rg, ps = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(_native.lib().lbm_eos_coexistence(ctypes.byref(c), float(T), ctypes.byref(rl), ctypes.byref(rg),
+                                             ctypes.byref(ps)))
+    return rl.value, rg.value, ps.value
+
+
+def footprint_bytes(prm, precision: int = LBM_FP32) -> int:
+    c = params_struct(prm, precision)
+    return int(_native.lib().lbm_footprint_bytes(ctypes.byref(c)))
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+_streams = {}
+
+
+def default_stream(device):
+    """A per-device torch stream (default priority) for the library's work.  The legacy null
+    stream cannot be captured into a graph, so the library is given a stream of its own."""
+    import torch
+    key = torch.device(device).index
+    if key not in _streams:
+        _streams[key] = torch.cuda.Stream(device=device)
+    return _streams[key]
+
+
+class Solver:
+    """One simulation on the current GPU.  Device memory is a torch uint8 tensor owned here; work
+    is enqueued on ``stream`` (default: a library stream per device, see default_stream)."""
+
+    def __init__(self, prm, precision: int = LBM_FP32, device=None, stream=None):
+        import torch
+
+        L = _native.lib()
+        self.prm = prm
+        self.precision = precision
+        self.params = params_struct(prm, precision)
+        self.nx, self.ny = int(prm.nx), int(prm.ny)
+        nbytes = int(L.lbm_footprint_bytes(ctypes.byref(self.params)))
+        if nbytes == 0:
+            raise LbmError(-1, "invalid parameters (lbm_validate)")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else default_stream(dev)
+        self.mem.record_stream(self.stream)  # the allocator must not reuse it while the stream runs
+        h = ctypes.c_void_p()
+        _check(L.lbm_create(ctypes.byref(self.params), ctypes.c_void_p(self.mem.data_ptr()), nbytes,
+                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        self.footprint = nbytes
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.stream.synchronize()
+            _native.lib().lbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, rho, ux, uy, T):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64).reshape(self.ny, self.nx) for a in (rho, ux, uy, T)]
+        _check(_native.lib().lbm_init(self.handle, *(_dptr(a) for a in arrs)), self.handle)
+        return self
+
+    def step(self, n: int = 1):
+        _check(_native.lib().lbm_step(self.handle, int(n)), self.handle)
+        return self
+
+    def sync(self):
+        _check(_native.lib().lbm_sync(self.handle), self.handle)
+
+    @property
+    def steps(self) -> int:
+        return int(_native.lib().lbm_steps_done(self.handle))
+
+    def fields(self):
+        out = [np.empty((self.ny, self.nx)) for _ in range(4)]
+        _check(_native.lib().lbm_read_fields(self.handle, *(_dptr(a) for a in out)), self.handle)
+        return tuple(out)
+
+    def diagnostics(self):
+        m, e = ctypes.c_double(), ctypes.c_double()
+        _check(_native.lib().lbm_diagnostics(self.handle, ctypes.byref(m), ctypes.byref(e)), self.handle)
+        return m.value, e.value
+
+    def state_bytes(self) -> int:
+        return int(_native.lib().lbm_state_bytes(self.handle))
+
+    def save_state(self) -> bytes:
+        buf = ctypes.create_string_buffer(self.state_bytes())
+        _check(_native.lib().lbm_save_state(self.handle, buf, len(buf)), self.handle)
+        return buf.raw
+
+    def load_state(self, data: bytes):
+        buf = ctypes.create_string_buffer(data, len(data))
+        _check(_native.lib().lbm_load_state(self.handle, buf, len(data)), self.handle)
+
+    def state(self, absolute: bool = True):
+        """(f[9], g[5], history[2]) host copies.  The library stores g_i - what_i T_ref and
+        T - T_ref; with absolute=True they are shifted back (FP64), otherwise returned raw in the
+        working precision together with nothing else changed."""
+        raw = self.save_state()
+        dt = np.float64 if self.precision == LBM_FP64 else np.float32
+        n = self.nx * self.ny
+        a = np.frombuffer(raw, dtype=dt, count=16 * n)
+        f = a[:9 * n].reshape(9, self.ny, self.nx)
+        g = a[9 * n:14 * n].reshape(5, self.ny, self.nx)
+        h = a[14 * n:16 * n].reshape(2, self.ny, self.nx)
+        if not absolute:
+            return f, g, h
+        T_ref = float(np.frombuffer(raw, dtype=np.float64, count=1, offset=16 * n * a.itemsize + 16)[0])
+        wd = float(self.params.wdot)
+        w = np.array([1.0 - wd] + [wd / 4.0] * 4)[:, None, None]
+        return f.astype(np.float64), g.astype(np.float64) + w * T_ref, h.astype(np.float64) + T_ref
+
+
+class Batch:
+    """Many initialised Solvers (same precision) advanced together: one kernel launch per step
+    covers the tiles of every instance with budget left."""
+
+    def __init__(self, solvers, stream=None):
+        import torch
+
+        L = _native.lib()
+        self.solvers = list(solvers)
+        n = len(self.solvers)
+        nbytes = int(L.lbm_batch_footprint_bytes(n))
+        dev = self.solvers[0].mem.device
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else self.solvers[0].stream
+        self.mem.record_stream(self.stream)
+        arr = (ctypes.c_void_p * n)(*[s.handle.value for s in self.solvers])
+        h = ctypes.c_void_p()
+        _check(L.lbm_batch_create(arr, n, ctypes.c_void_p(self.mem.data_ptr()), nbytes,
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def set_budget(self, i: int, steps: int):
+        _check(_native.lib().lbm_batch_set_budget(self.handle, int(i), int(steps)))
+
+    def step(self, k: int):
+        _check(_native.lib().lbm_batch_step(self.handle, int(k)))
+
+    def remaining(self, i: int) -> int:
+        return int(_native.lib().lbm_batch_remaining(self.handle, int(i)))
+
+    def sync(self):
+        n = len(self.solvers)
+        st = (ctypes.c_int * n)()
+        _native.lib().lbm_batch_sync(self.handle, st)
+        return list(st)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.stream.synchronize()
+            _native.lib().lbm_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,849 @@
+// Host runtime and C ABI of the thermal pseudopotential LBM library (declared in include/lbm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_aux.hpp"
+#include "lbm_step.hpp"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr size_t CTRL_BYTES = 16384;  // descriptor, clock, error word, diagnostics result
+constexpr int MAX_RED_BLOCKS = 2048;
+constexpr int GRAPH_STEPS = 64;       // steps captured per replayed graph
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// offsets inside the control block
+constexpr size_t OFF_DESC = 0;        // InstDesc<real> (single-run table)
+constexpr size_t OFF_CLOCK = 4096;    // long long
+constexpr size_t OFF_ERR = 4352;      // unsigned
+constexpr size_t OFF_DIAG = 4608;     // 2 doubles
+constexpr size_t OFF_PART = 8192;     // partial sums follow the control block
+
+size_t partial_bytes() { return align_up((size_t)MAX_RED_BLOCKS * 2 * sizeof(double)); }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+double pr_kappa(const lbm_params* p) {
+  const double w = p->acentric;
+  return 0.37464 + 1.54226 * w - 0.26992 * w * w;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+  lbm_params prm{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  char* base = nullptr;  // caller memory
+  size_t bytes = 0;
+  size_t N = 0;
+  size_t rsz = 4;        // bytes per real
+  void* fA = nullptr;
+  void* gA = nullptr;
+  void* fB = nullptr;
+  void* gB = nullptr;
+  void* Th = nullptr;
+  long long* d_clock = nullptr;
+  unsigned* d_err = nullptr;
+  double* d_diag = nullptr;
+  double* d_part = nullptr;
+  void* d_desc = nullptr;
+  InstDesc<float> desc32{};
+  InstDesc<double> desc64{};
+  bool initialised = false;
+  bool failed = false;
+  bool clock_dirty = false;
+  int64_t steps = 0;
+  double rho_ave = 0.0;
+  double T_ref = 0.0;  // storage offset of g and the history (exact in the working precision)
+  int ntiles = 0;
+  hipGraphExec_t graph = nullptr;
+  std::string last_error;
+};
+
+struct lbm_batch {
+  std::vector<lbm_ctx*> ctx;
+  std::vector<int64_t> remaining;
+  std::vector<int64_t> pending;  // steps enqueued since the last sync, per instance
+  hipStream_t stream = nullptr;
+  int precision = 0;
+  char* base = nullptr;
+  size_t bytes = 0;
+  void* d_table = nullptr;
+  long long* d_clock = nullptr;
+  long long clock = 0;           // host mirror of the device clock
+  int total_tiles = 0;
+  bool table_dirty = true;
+  hipGraphExec_t graph = nullptr;
+  int graph_steps = 0;
+};
+
+// ------------------------------------------------------------------------------ helpers
+static lbm_status fail(lbm_ctx* h, lbm_status s, const std::string& msg) {
+  if (h) h->last_error = msg;
+  return s;
+}
+
+#define HIP_OR_FAIL(h, call)                                                               \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail((h), LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename real>
+static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref) {
+  DevParams<real> d{};
+  const double Tc = lbm_critical_temperature(p);
+  d.a = (real)p->a;
+  d.b = (real)p->b;
+  d.R = (real)p->R;
+  d.G = (real)p->G;
+  d.Tc = (real)Tc;
+  d.kappa = (real)pr_kappa(p);
+  d.s_e = (real)p->s_e;
+  d.s_eps = (real)p->s_eps;
+  d.s_q = (real)p->s_q;
+  d.s_p = (real)(1.0 / (3.0 * p->nu + 0.5));
+  d.corr_e = (real)(p->sigma / (1.0 / p->s_e - 0.5));
+  d.corr_eps = (real)(p->sigma / (1.0 / p->s_eps - 0.5));
+  d.cv = (real)p->cv;
+  d.wdot = (real)p->wdot;
+  d.w0h = (real)(1.0 - p->wdot);
+  d.w1h = (real)(p->wdot / 4.0);
+  d.vs1 = (real)(1.0 / (p->lambda / (p->wdot / 2.0) + 0.5));
+  d.vs3 = (real)p->vs3;
+  d.vs4 = (real)p->vs4;
+  d.inv_cs2h = (real)(2.0 / p->wdot);
+  d.gx = (real)p->gx;
+  d.gy = (real)p->gy;
+  d.rho_ave = (real)rho_ave;
+  d.T_box = (real)p->T_box;
+  d.T_top = (real)p->T_top;
+  d.T_bot = (real)p->T_bot;
+  const bool bump = p->hot_sigma > 0.0;
+  d.hot_dT = (real)(bump ? p->hot_dT : 0.0);
+  d.hot_x0 = (real)p->hot_x0;
+  d.inv_2s2 = (real)(bump ? 1.0 / (2.0 * p->hot_sigma * p->hot_sigma) : 0.0);
+  d.tan_bot = (real)std::tan(M_PI / 2.0 - p->theta_bot_deg * M_PI / 180.0);
+  d.tan_top = (real)std::tan(M_PI / 2.0 - p->theta_top_deg * M_PI / 180.0);
+  d.y_walls = p->y_walls ? 1 : 0;
+  d.thermal_box = p->thermal_box ? 1 : 0;
+  d.flags = p->flags;
+  d.T_ref = (real)T_ref;
+  return d;
+}
+
+template <typename real>
+static InstDesc<real> make_desc(lbm_ctx* h) {
+  InstDesc<real> D{};
+  D.fA = (real*)h->fA;
+  D.gA = (real*)h->gA;
+  D.fB = (real*)h->fB;
+  D.gB = (real*)h->gB;
+  D.Th = (real*)h->Th;
+  D.err = h->d_err;
+  D.nx = h->prm.nx;
+  D.ny = h->prm.ny;
+  D.ntx = (h->prm.nx + TX - 1) / TX;
+  D.nty = (h->prm.ny + TY - 1) / TY;
+  D.tile_begin = 0;
+  D.t_start = 0;
+  D.t_end = std::numeric_limits<long long>::max();
+  D.p = derive<real>(&h->prm, h->rho_ave, h->T_ref);
+  return D;
+}
+
+static lbm_status check_device_error(lbm_ctx* h) {
+  unsigned e = 0;
+  HIP_OR_FAIL(h, hipMemcpyAsync(&e, h->d_err, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  if (e) {
+    h->failed = true;
+    std::string m = "numerical failure on the device:";
+    if (e & ERR_RHO) m += " density not positive/finite;";
+    if (e & ERR_T) m += " temperature not positive/finite;";
+    if (e & ERR_PSI) m += " pseudopotential argument negative (density above the EOS limit);";
+    return fail(h, LBM_E_NUMERIC, m);
+  }
+  return LBM_OK;
+}
+
+static bool set_device(lbm_ctx* h) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return false;
+  if (cur != h->device) return hipSetDevice(h->device) == hipSuccess;
+  return true;
+}
+
+// ------------------------------------------------------------------------------ C ABI
+extern "C" {
+
+void lbm_params_default(lbm_params* p, int32_t nx, int32_t ny) {
+  std::memset(p, 0, sizeof(*p));
+  p->nx = nx;
+  p->ny = ny;
+  p->precision = LBM_FP32;
+  p->a = 3.0 / 49.0;
+  p->b = 2.0 / 21.0;
+  p->R = 1.0;
+  p->acentric = 0.344;
+  p->G = -1.0;
+  p->nu = 0.1;
+  p->s_e = p->s_eps = p->s_q = 1.0;
+  p->sigma = 1.25;
+  p->lambda = 1.0 / 3.0;
+  p->cv = 5.0;
+  p->wdot = 2.0 / 3.0;
+  p->vs3 = p->vs4 = 1.0;
+  p->rho_ave = std::numeric_limits<double>::quiet_NaN();
+  p->theta_bot_deg = p->theta_top_deg = 90.0;
+}
+
+double lbm_critical_temperature(const lbm_params* p) { return 0.0778 * p->a / (0.45724 * p->b * p->R); }
+
+lbm_status lbm_validate(const lbm_params* p) {
+  if (!p) return LBM_E_INVAL;
+  if (p->nx < 3 || p->ny < 3) return LBM_E_INVAL;
+  if ((double)p->nx * (double)p->ny > 2147483647.0) return LBM_E_INVAL;
+  if (p->precision != LBM_FP32 && p->precision != LBM_FP64) return LBM_E_INVAL;
+  auto rate_ok = [](double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; };
+  if (!(p->nu > 0.0) || !(p->lambda > 0.0) || !(p->cv > 0.0)) return LBM_E_INVAL;
+  if (!(p->wdot > 0.0 && p->wdot < 1.0)) return LBM_E_INVAL;
+  const double sp = 1.0 / (3.0 * p->nu + 0.5);
+  const double vs1 = 1.0 / (p->lambda / (p->wdot / 2.0) + 0.5);
+  if (!rate_ok(p->s_e) || !rate_ok(p->s_eps) || !rate_ok(p->s_q) || !rate_ok(sp) || !rate_ok(vs1) ||
+      !rate_ok(p->vs3) || !rate_ok(p->vs4))
+    return LBM_E_INVAL;
+  if (!(p->a > 0.0) || !(p->b > 0.0) || !(p->R > 0.0) || !(p->G < 0.0)) return LBM_E_INVAL;
+  if (!std::isfinite(p->sigma) || !std::isfinite(p->gx) || !std::isfinite(p->gy)) return LBM_E_INVAL;
+  if (p->y_walls) {
+    if (!finite_pos(p->T_bot) || !finite_pos(p->T_top)) return LBM_E_INVAL;
+    if (!(p->theta_bot_deg > 0.0 && p->theta_bot_deg < 180.0 && p->theta_top_deg > 0.0 &&
+          p->theta_top_deg < 180.0))
+      return LBM_E_INVAL;
+  }
+  if (p->thermal_box && !finite_pos(p->T_box)) return LBM_E_INVAL;
+  return LBM_OK;
+}
+
+size_t lbm_footprint_bytes(const lbm_params* p) {
+  if (lbm_validate(p) != LBM_OK) return 0;
+  const size_t N = (size_t)p->nx * (size_t)p->ny;
+  const size_t r = p->precision == LBM_FP64 ? 8 : 4;
+  return CTRL_BYTES + partial_bytes() + 2 * align_up(9 * N * r) + 2 * align_up(5 * N * r) + align_up(2 * N * r);
+}
+
+lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hip_stream, lbm_ctx** out) {
+  if (!out) return LBM_E_INVAL;
+  *out = nullptr;
+  if (lbm_validate(p) != LBM_OK) return LBM_E_INVAL;
+  if (!dev_mem || ((uintptr_t)dev_mem % ALIGN) != 0) return LBM_E_INVAL;
+  if (bytes < lbm_footprint_bytes(p)) return LBM_E_NOMEM;
+  lbm_ctx* h = new (std::nothrow) lbm_ctx();
+  if (!h) return LBM_E_NOMEM;
+  h->prm = *p;
+  h->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return LBM_E_DEVICE;
+  }
+  h->base = (char*)dev_mem;
+  h->bytes = bytes;
+  h->N = (size_t)p->nx * (size_t)p->ny;
+  h->rsz = p->precision == LBM_FP64 ? 8 : 4;
+  char* q = h->base;
+  h->d_desc = q + OFF_DESC;
+  h->d_clock = (long long*)(q + OFF_CLOCK);
+  h->d_err = (unsigned*)(q + OFF_ERR);
+  h->d_diag = (double*)(q + OFF_DIAG);
+  q += CTRL_BYTES;
+  h->d_part = (double*)q;
+  q += partial_bytes();
+  h->fA = q; q += align_up(9 * h->N * h->rsz);
+  h->gA = q; q += align_up(5 * h->N * h->rsz);
+  h->fB = q; q += align_up(9 * h->N * h->rsz);
+  h->gB = q; q += align_up(5 * h->N * h->rsz);
+  h->Th = q;
+  h->ntiles = ((p->nx + TX - 1) / TX) * ((p->ny + TY - 1) / TY);
+  *out = h;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* h) {
+  if (!h) return LBM_E_INVAL;
+  if (h->graph) (void)hipGraphExecDestroy(h->graph);
+  delete h;
+  return LBM_OK;
+}
+
+static lbm_status upload_desc(lbm_ctx* h) {
+  if (h->prm.precision == LBM_FP64) {
+    h->desc64 = make_desc<double>(h);
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_desc, &h->desc64, sizeof(h->desc64), hipMemcpyHostToDevice, h->stream));
+  } else {
+    h->desc32 = make_desc<float>(h);
+    HIP_OR_FAIL(h, hipMemcpyAsync(h->d_desc, &h->desc32, sizeof(h->desc32), hipMemcpyHostToDevice, h->stream));
+  }
+  return LBM_OK;
+}
+
+static lbm_status write_clock(lbm_ctx* h) {
+  long long c = (long long)h->steps;
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_clock, &c, sizeof(c), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  h->clock_dirty = false;
+  return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const double* uy, const double* T) {
+  if (!h || !rho || !ux || !uy || !T) return LBM_E_INVAL;
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  const size_t N = h->N;
+  double sum = 0.0, sumT = 0.0, rmin = std::numeric_limits<double>::infinity();
+  for (size_t k = 0; k < N; ++k) {
+    if (!finite_pos(rho[k]) || !finite_pos(T[k]) || !std::isfinite(ux[k]) || !std::isfinite(uy[k]))
+      return fail(h, LBM_E_INVAL, "initial fields must be finite with rho > 0 and T > 0");
+    sum += rho[k];
+    sumT += T[k];
+    rmin = std::min(rmin, rho[k]);
+  }
+  // storage offset of the temperature populations, exactly representable in the working precision
+  h->T_ref = h->prm.precision == LBM_FP64 ? sumT / (double)N : (double)(float)(sumT / (double)N);
+  if (rmin * h->prm.cv < 1.0)
+    return fail(h, LBM_E_INVAL, "min(rho) * c_v < 1: the modified collision would weight old populations negatively");
+  h->rho_ave = std::isnan(h->prm.rho_ave) ? sum / (double)N : h->prm.rho_ave;
+  // stage the FP64 fields in the B copy of f (at least 4 N doubles in either precision)
+  double* stage = (double*)h->fB;
+  HIP_OR_FAIL(h, hipMemcpyAsync(stage, rho, N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(stage + N, ux, N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(stage + 2 * N, uy, N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(stage + 3 * N, T, N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  const int nb = (int)((N + 255) / 256);
+  if (h->prm.precision == LBM_FP64) {
+    init_kernel<double><<<nb, 256, 0, h->stream>>>(stage, (double*)h->fA, (double*)h->gA, (double*)h->Th, N,
+                                                    1.0 - h->prm.wdot, h->prm.wdot / 4.0, h->T_ref);
+  } else {
+    init_kernel<float><<<nb, 256, 0, h->stream>>>(stage, (float*)h->fA, (float*)h->gA, (float*)h->Th, N,
+                                                   1.0 - h->prm.wdot, h->prm.wdot / 4.0, h->T_ref);
+  }
+  HIP_OR_FAIL(h, hipGetLastError());
+  unsigned zero = 0;
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+  h->steps = 0;
+  lbm_status s = upload_desc(h);
+  if (s != LBM_OK) return s;
+  s = write_clock(h);
+  if (s != LBM_OK) return s;
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  h->initialised = true;
+  h->failed = false;
+  return LBM_OK;
+}
+
+static lbm_status launch_steps(lbm_ctx* h, int n) {
+  const long long* clk = h->d_clock;
+  for (int k = 0; k < n; ++k) {
+    if (h->prm.precision == LBM_FP64)
+      step_kernel<double><<<h->ntiles, NT, 0, h->stream>>>((const InstDesc<double>*)h->d_desc, 1, clk, k);
+    else
+      step_kernel<float><<<h->ntiles, NT, 0, h->stream>>>((const InstDesc<float>*)h->d_desc, 1, clk, k);
+  }
+  clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n);
+  HIP_OR_FAIL(h, hipGetLastError());
+  return LBM_OK;
+}
+
+static lbm_status build_graph(lbm_ctx* h) {
+  hipGraph_t g = nullptr;
+  HIP_OR_FAIL(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  lbm_status s = launch_steps(h, GRAPH_STEPS);
+  hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (s != LBM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  if (e != hipSuccess) return fail(h, LBM_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->graph = nullptr;
+    return fail(h, LBM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* h, int64_t n) {
+  if (!h || n < 0) return LBM_E_INVAL;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_step before lbm_init");
+  if (h->failed) return fail(h, LBM_E_STATE, "context has failed: " + h->last_error);
+  if (n == 0) return LBM_OK;
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  if (h->clock_dirty) {
+    lbm_status s = write_clock(h);
+    if (s != LBM_OK) return s;
+  }
+  int64_t left = n;
+  if (left >= GRAPH_STEPS && h->stream != nullptr) {  // the legacy null stream cannot be captured
+    if (!h->graph) {
+      lbm_status s = build_graph(h);
+      if (s != LBM_OK) return s;
+    }
+    while (left >= GRAPH_STEPS) {
+      HIP_OR_FAIL(h, hipGraphLaunch(h->graph, h->stream));
+      left -= GRAPH_STEPS;
+    }
+  }
+  if (left > 0) {
+    lbm_status s = launch_steps(h, (int)left);
+    if (s != LBM_OK) return s;
+  }
+  h->steps += n;
+  return LBM_OK;
+}
+
+int64_t lbm_steps_done(const lbm_ctx* h) { return h ? h->steps : -1; }
+
+lbm_status lbm_sync(lbm_ctx* h) {
+  if (!h) return LBM_E_INVAL;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_sync before lbm_init");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  return check_device_error(h);
+}
+
+// current source buffers (A after an even number of steps)
+static void current_buffers(lbm_ctx* h, void*& f, void*& g, void*& fo) {
+  const bool odd = (h->steps & 1) != 0;
+  f = odd ? h->fB : h->fA;
+  g = odd ? h->gB : h->gA;
+  fo = odd ? h->fA : h->fB;
+}
+
+lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, double* T) {
+  if (!h) return LBM_E_INVAL;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_read_fields before lbm_init");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  lbm_status s = check_device_error(h);
+  if (s != LBM_OK) return s;
+  void *f, *g, *fo;
+  current_buffers(h, f, g, fo);
+  double* stage = (double*)fo;
+  const size_t N = h->N;
+  const int nb = (int)((N + 255) / 256);
+  if (h->prm.precision == LBM_FP64)
+    fields_kernel<double><<<nb, 256, 0, h->stream>>>(h->desc64.p, (const double*)f, (const double*)g, h->prm.nx,
+                                                      h->prm.ny, stage, h->d_err);
+  else
+    fields_kernel<float><<<nb, 256, 0, h->stream>>>(h->desc32.p, (const float*)f, (const float*)g, h->prm.nx,
+                                                     h->prm.ny, stage, h->d_err);
+  HIP_OR_FAIL(h, hipGetLastError());
+  double* outs[4] = {rho, ux, uy, T};
+  for (int c = 0; c < 4; ++c)
+    if (outs[c])
+      HIP_OR_FAIL(h, hipMemcpyAsync(outs[c], stage + c * N, N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  return check_device_error(h);
+}
+
+lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy) {
+  if (!h) return LBM_E_INVAL;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_diagnostics before lbm_init");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  void *f, *g, *fo;
+  current_buffers(h, f, g, fo);
+  const size_t N = h->N;
+  size_t per = (N + MAX_RED_BLOCKS - 1) / MAX_RED_BLOCKS;
+  per = std::max<size_t>(per, RED_NT);
+  const int nparts = (int)((N + per - 1) / per);
+  if (h->prm.precision == LBM_FP64)
+    diag_partial_kernel<double><<<nparts, RED_NT, 0, h->stream>>>((const double*)f, (const double*)g, N, h->prm.cv,
+                                                                   h->T_ref, per, h->d_part);
+  else
+    diag_partial_kernel<float><<<nparts, RED_NT, 0, h->stream>>>((const float*)f, (const float*)g, N, h->prm.cv,
+                                                                  h->T_ref, per, h->d_part);
+  diag_final_kernel<<<1, RED_NT, 0, h->stream>>>(h->d_part, nparts, h->d_diag);
+  HIP_OR_FAIL(h, hipGetLastError());
+  double out[2];
+  HIP_OR_FAIL(h, hipMemcpyAsync(out, h->d_diag, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  if (mass) *mass = out[0];
+  if (energy) *energy = out[1];
+  return check_device_error(h);
+}
+
+size_t lbm_state_bytes(const lbm_ctx* h) { return h ? 16 * h->N * h->rsz + 3 * sizeof(int64_t) : 0; }
+
+lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
+  if (!h || !host) return LBM_E_INVAL;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_save_state before lbm_init");
+  if (bytes < lbm_state_bytes(h)) return fail(h, LBM_E_INVAL, "host buffer smaller than lbm_state_bytes");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  void *f, *g, *fo;
+  current_buffers(h, f, g, fo);
+  char* q = (char*)host;
+  const size_t N = h->N, r = h->rsz;
+  HIP_OR_FAIL(h, hipMemcpyAsync(q, f, 9 * N * r, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(q + 9 * N * r, g, 5 * N * r, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(q + 14 * N * r, h->Th, 2 * N * r, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  int64_t meta[3] = {h->steps, 0, 0};
+  std::memcpy(&meta[1], &h->rho_ave, sizeof(double));
+  std::memcpy(&meta[2], &h->T_ref, sizeof(double));
+  std::memcpy(q + 16 * N * r, meta, sizeof(meta));
+  return check_device_error(h);
+}
+
+lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
+  if (!h || !host) return LBM_E_INVAL;
+  if (bytes < lbm_state_bytes(h)) return fail(h, LBM_E_INVAL, "host buffer smaller than lbm_state_bytes");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  const char* q = (const char*)host;
+  const size_t N = h->N, r = h->rsz;
+  int64_t meta[3];
+  std::memcpy(meta, q + 16 * N * r, sizeof(meta));
+  if (meta[0] < 0) return fail(h, LBM_E_INVAL, "corrupt state: negative step count");
+  h->steps = meta[0];
+  std::memcpy(&h->rho_ave, &meta[1], sizeof(double));
+  std::memcpy(&h->T_ref, &meta[2], sizeof(double));
+  void *f, *g, *fo;
+  current_buffers(h, f, g, fo);
+  HIP_OR_FAIL(h, hipMemcpyAsync(f, q, 9 * N * r, hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(g, q + 9 * N * r, 5 * N * r, hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->Th, q + 14 * N * r, 2 * N * r, hipMemcpyHostToDevice, h->stream));
+  unsigned zero = 0;
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+  lbm_status s = upload_desc(h);
+  if (s != LBM_OK) return s;
+  s = write_clock(h);
+  if (s != LBM_OK) return s;
+  h->initialised = true;
+  h->failed = false;
+  return LBM_OK;
+}
+
+// Maxwell equal-area construction (host, FP64): p(rho_g) = p(rho_l) = p_sat and
+// integral_{rho_g}^{rho_l} (p - p_sat)/rho^2 drho = 0.  The spinodal points are found by
+// golden-section search of p on either side, the integral is done analytically per piece
+// with adaptive Gauss-Legendre quadrature, p_sat by bisection.
+static double pr_p(const lbm_params* p, double rho, double T) {
+  const double Tc = lbm_critical_temperature(p);
+  const double s = 1.0 + pr_kappa(p) * (1.0 - std::sqrt(T / Tc));
+  const double b = p->b;
+  return rho * p->R * T / (1.0 - b * rho) - p->a * s * s * rho * rho / (1.0 + 2.0 * b * rho - b * b * rho * rho);
+}
+
+static double gl_integral(const lbm_params* p, double T, double ps, double lo, double hi) {
+  // 16-point Gauss-Legendre on 64 panels of (p - ps)/rho^2
+  static const double xg[8] = {0.0950125098376374, 0.2816035507792589, 0.4580167776572274, 0.6178762444026438,
+                               0.7554044083550030, 0.8656312023878318, 0.9445750230732326, 0.9894009349916499};
+  static const double wg[8] = {0.1894506104550685, 0.1826034150449236, 0.1691565193950025, 0.1495959888165767,
+                               0.1246289712555339, 0.0951585116824928, 0.0622535239386479, 0.0271524594117541};
+  const int panels = 64;
+  const double h = (hi - lo) / panels;
+  double s = 0.0;
+  for (int k = 0; k < panels; ++k) {
+    const double c = lo + (k + 0.5) * h, r = 0.5 * h;
+    for (int j = 0; j < 8; ++j) {
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        const double x = c + sgn * r * xg[j];
+        s += wg[j] * r * (pr_p(p, x, T) - ps) / (x * x);
+      }
+    }
+  }
+  return s;
+}
+
+static double golden_extremum(const lbm_params* p, double T, double lo, double hi, bool maximum) {
+  const double gr = 0.5 * (std::sqrt(5.0) - 1.0);
+  double a = lo, b = hi;
+  double c = b - gr * (b - a), d = a + gr * (b - a);
+  for (int it = 0; it < 200; ++it) {
+    const double fc = pr_p(p, c, T), fd = pr_p(p, d, T);
+    const bool left = maximum ? (fc > fd) : (fc < fd);
+    if (left) b = d;
+    else a = c;
+    c = b - gr * (b - a);
+    d = a + gr * (b - a);
+  }
+  return 0.5 * (a + b);
+}
+
+static double bisect_root(const lbm_params* p, double T, double target, double lo, double hi) {
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (pr_p(p, mid, T) < target) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+lbm_status lbm_eos_coexistence(const lbm_params* p, double T, double* rho_l, double* rho_g, double* p_sat) {
+  if (!p || !rho_l || !rho_g || !p_sat || !(T > 0.0)) return LBM_E_INVAL;
+  const double rmax = (1.0 / p->b) * (1.0 - 1e-9);
+  // coarse scan to bracket the local maximum and minimum of the subcritical isotherm
+  const int NS = 4000;
+  const double h = rmax / NS;
+  int kmax = -1, kmin = -1;
+  double prev = pr_p(p, h, T);
+  bool rising = true;
+  for (int k = 2; k < NS; ++k) {
+    const double cur = pr_p(p, k * h, T);
+    if (rising && cur < prev) {
+      kmax = k - 1;
+      rising = false;
+    } else if (!rising && cur > prev) {
+      kmin = k - 1;
+      break;
+    }
+    prev = cur;
+  }
+  if (kmax < 0 || kmin < 0) return LBM_E_INVAL;
+  const double rs_max = golden_extremum(p, T, (kmax - 1) * h, (kmax + 1) * h, true);
+  const double rs_min = golden_extremum(p, T, (kmin - 1) * h, (kmin + 1) * h, false);
+  double lo = std::max(pr_p(p, rs_min, T), 1e-14), hi = pr_p(p, rs_max, T);
+  for (int it = 0; it < 200; ++it) {
+    const double ps = 0.5 * (lo + hi);
+    const double rg = bisect_root(p, T, ps, 1e-12, rs_max);
+    const double rl = bisect_root(p, T, ps, rs_min, rmax);
+    if (gl_integral(p, T, ps, rg, rl) > 0) lo = ps;
+    else hi = ps;
+  }
+  *p_sat = 0.5 * (lo + hi);
+  *rho_g = bisect_root(p, T, *p_sat, 1e-12, rs_max);
+  *rho_l = bisect_root(p, T, *p_sat, rs_min, rmax);
+  return LBM_OK;
+}
+
+const char* lbm_strerror(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_E_INVAL: return "invalid argument";
+    case LBM_E_NOMEM: return "device buffer too small";
+    case LBM_E_DEVICE: return "HIP runtime error";
+    case LBM_E_NUMERIC: return "numerical failure on the device";
+    case LBM_E_STATE: return "call out of order or context failed";
+  }
+  return "unknown status";
+}
+
+const char* lbm_last_error(const lbm_ctx* h) { return h ? h->last_error.c_str() : "null context"; }
+
+// ------------------------------------------------------------------------------ batches
+size_t lbm_batch_footprint_bytes(int n) {
+  if (n <= 0) return 0;
+  return align_up(ALIGN + (size_t)n * sizeof(InstDesc<double>));
+}
+
+lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t bytes, void* hip_stream,
+                            lbm_batch** out) {
+  if (!out || !ctxs || n <= 0) return LBM_E_INVAL;
+  *out = nullptr;
+  if (!dev_mem || ((uintptr_t)dev_mem % ALIGN) != 0) return LBM_E_INVAL;
+  if (bytes < lbm_batch_footprint_bytes(n)) return LBM_E_NOMEM;
+  const int prec = ctxs[0] ? ctxs[0]->prm.precision : -1;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i] || !ctxs[i]->initialised || ctxs[i]->prm.precision != prec) return LBM_E_INVAL;
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_E_NOMEM;
+  b->ctx.assign(ctxs, ctxs + n);
+  b->remaining.assign(n, 0);
+  b->pending.assign(n, 0);
+  b->stream = (hipStream_t)hip_stream;
+  b->precision = prec;
+  b->base = (char*)dev_mem;
+  b->bytes = bytes;
+  b->d_clock = (long long*)b->base;
+  b->d_table = b->base + ALIGN;
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_budget(lbm_batch* b, int i, int64_t steps) {
+  if (!b || i < 0 || i >= (int)b->ctx.size() || steps < 0) return LBM_E_INVAL;
+  if (b->ctx[i]->failed) return LBM_E_STATE;
+  b->remaining[i] = steps;
+  b->table_dirty = true;
+  return LBM_OK;
+}
+
+int64_t lbm_batch_remaining(const lbm_batch* b, int i) {
+  if (!b || i < 0 || i >= (int)b->ctx.size()) return -1;
+  return b->remaining[i];
+}
+
+}  // extern "C"
+
+// Table of the batch: active instances first (in the caller's order), then parked ones, so
+// that tile_begin is non-decreasing along the table as the kernel's binary search needs.
+template <typename real>
+static void fill_table(lbm_batch* b, std::vector<InstDesc<real>>& tab) {
+  const int n = (int)b->ctx.size();
+  std::vector<int> order;
+  for (int i = 0; i < n; ++i)
+    if (b->remaining[i] > 0) order.push_back(i);
+  for (int i = 0; i < n; ++i)
+    if (b->remaining[i] <= 0) order.push_back(i);
+  int tiles = 0;
+  tab.resize(n);
+  for (int j = 0; j < n; ++j) {
+    const int i = order[j];
+    lbm_ctx* h = b->ctx[i];
+    InstDesc<real> D = make_desc<real>(h);
+    // parity continues from the context's own step count: clock - t_start = steps done
+    D.t_start = b->clock - (long long)(h->steps + b->pending[i]);
+    if (b->remaining[i] > 0) {
+      D.tile_begin = tiles;
+      D.t_end = b->clock + (long long)b->remaining[i];
+      tiles += D.ntx * D.nty;
+    } else {
+      D.tile_begin = -1;  // fixed up below: parked instances own no workgroups
+      D.t_end = D.t_start;
+    }
+    tab[j] = D;
+  }
+  for (int j = 0; j < n; ++j)
+    if (tab[j].tile_begin < 0) tab[j].tile_begin = tiles;
+  b->total_tiles = tiles;
+}
+
+extern "C" {
+
+static lbm_status batch_upload(lbm_batch* b) {
+  lbm_ctx* h0 = b->ctx[0];
+  const size_t n = b->ctx.size();
+  long long c = b->clock;
+  if (b->precision == LBM_FP64) {
+    std::vector<InstDesc<double>> tab;
+    fill_table(b, tab);
+    HIP_OR_FAIL(h0, hipMemcpyAsync(b->d_table, tab.data(), n * sizeof(tab[0]), hipMemcpyHostToDevice, b->stream));
+    HIP_OR_FAIL(h0, hipMemcpyAsync(b->d_clock, &c, sizeof(c), hipMemcpyHostToDevice, b->stream));
+    HIP_OR_FAIL(h0, hipStreamSynchronize(b->stream));
+  } else {
+    std::vector<InstDesc<float>> tab;
+    fill_table(b, tab);
+    HIP_OR_FAIL(h0, hipMemcpyAsync(b->d_table, tab.data(), n * sizeof(tab[0]), hipMemcpyHostToDevice, b->stream));
+    HIP_OR_FAIL(h0, hipMemcpyAsync(b->d_clock, &c, sizeof(c), hipMemcpyHostToDevice, b->stream));
+    HIP_OR_FAIL(h0, hipStreamSynchronize(b->stream));
+  }
+  if (b->graph) {
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  b->table_dirty = false;
+  return LBM_OK;
+}
+
+static lbm_status batch_launch(lbm_batch* b, int k) {
+  const int n = (int)b->ctx.size();
+  for (int s = 0; s < k; ++s) {
+    if (b->precision == LBM_FP64)
+      step_kernel<double><<<b->total_tiles, NT, 0, b->stream>>>((const InstDesc<double>*)b->d_table, n, b->d_clock, s);
+    else
+      step_kernel<float><<<b->total_tiles, NT, 0, b->stream>>>((const InstDesc<float>*)b->d_table, n, b->d_clock, s);
+  }
+  clock_advance_kernel<<<1, 64, 0, b->stream>>>(b->d_clock, (long long)k);
+  HIP_OR_FAIL(b->ctx[0], hipGetLastError());
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
+  if (!b || k < 0) return LBM_E_INVAL;
+  if (k == 0) return LBM_OK;
+  lbm_ctx* h0 = b->ctx[0];
+  for (lbm_ctx* h : b->ctx)
+    if (h->failed) return LBM_E_STATE;
+  if (b->table_dirty) {
+    lbm_status s = batch_upload(b);
+    if (s != LBM_OK) return s;
+  }
+  int64_t maxrem = 0;
+  for (int64_t r : b->remaining) maxrem = std::max(maxrem, r);
+  int64_t todo = std::min(k, maxrem);
+  if (todo == 0 || b->total_tiles == 0) return LBM_OK;
+  int64_t left = todo;
+  while (left >= GRAPH_STEPS && b->stream != nullptr) {
+    if (!b->graph) {
+      hipGraph_t g = nullptr;
+      HIP_OR_FAIL(h0, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      lbm_status s = batch_launch(b, GRAPH_STEPS);
+      hipError_t e = hipStreamEndCapture(b->stream, &g);
+      if (s != LBM_OK) return s;
+      if (e != hipSuccess) return fail(h0, LBM_E_DEVICE, "hipStreamEndCapture failed");
+      e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) {
+        b->graph = nullptr;
+        return fail(h0, LBM_E_DEVICE, "hipGraphInstantiate failed");
+      }
+    }
+    HIP_OR_FAIL(h0, hipGraphLaunch(b->graph, b->stream));
+    left -= GRAPH_STEPS;
+  }
+  if (left > 0) {
+    lbm_status s = batch_launch(b, (int)left);
+    if (s != LBM_OK) return s;
+  }
+  b->clock += todo;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    const int64_t ran = std::min<int64_t>(todo, b->remaining[i]);
+    b->pending[i] += ran;
+    b->remaining[i] -= ran;
+  }
+  // instances whose budget ran out inside this call leave the launch at the next call
+  for (int64_t r : b->remaining)
+    if (r == 0) {
+      b->table_dirty = true;
+      break;
+    }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status) {
+  if (!b) return LBM_E_INVAL;
+  lbm_ctx* h0 = b->ctx[0];
+  HIP_OR_FAIL(h0, hipStreamSynchronize(b->stream));
+  lbm_status worst = LBM_OK;
+  for (size_t i = 0; i < b->ctx.size(); ++i) {
+    lbm_ctx* h = b->ctx[i];
+    h->steps += b->pending[i];
+    b->pending[i] = 0;
+    h->clock_dirty = true;
+    unsigned e = 0;
+    HIP_OR_FAIL(h, hipMemcpy(&e, h->d_err, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (e) {
+      h->failed = true;
+      h->last_error = "numerical failure on the device (batched run)";
+      b->remaining[i] = 0;
+      b->table_dirty = true;
+      worst = LBM_E_NUMERIC;
+    }
+  }
+  if (status)
+    for (size_t i = 0; i < b->ctx.size(); ++i) status[i] = b->ctx[i]->failed ? LBM_E_NUMERIC : LBM_OK;
+  return worst;
+}
+
+lbm_status lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_E_INVAL;
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  delete b;
+  return LBM_OK;
+}
+
+}  // extern "C"

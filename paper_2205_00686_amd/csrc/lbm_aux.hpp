@@ -1,0 +1,160 @@
+// Per-call kernels around the step: initial state, field readout, FP64 diagnostics.
+#pragma once
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+// f_i = f_i^eq(rho, u) (Eq. 3), g_i = what_i T (Eq. 22), both history levels = T.
+// Inputs are FP64 fields staged in device memory: in[0..N) rho, [N..2N) ux, [2N..3N) uy,
+// [3N..4N) T.
+template <typename real>
+__global__ void init_kernel(const double* __restrict__ in, real* __restrict__ f, real* __restrict__ g,
+                            real* __restrict__ Th, size_t N, double w0h, double w1h, double T_ref) {
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const double rho = in[k], ux = in[N + k], uy = in[2 * N + k], T = in[3 * N + k];
+  const double uu = ux * ux + uy * uy;
+  const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  const int cx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int cy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double cu = cx[i] * ux + cy[i] * uy;
+    f[i * N + k] = (real)(w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+  }
+  const double Tr = T - T_ref;  // stored relative to T_ref
+  g[k] = (real)(w0h * Tr);
+#pragma unroll
+  for (int i = 1; i < 5; ++i) g[i * N + k] = (real)(w1h * Tr);
+  Th[k] = (real)Tr;
+  Th[N + k] = (real)Tr;
+}
+
+// rho and T - T_ref at a fluid node (already wrapped)
+template <typename real>
+__device__ __forceinline__ void rho_T(const real* __restrict__ f, const real* __restrict__ g, size_t N, int o,
+                                      real& rho, real& Tr) {
+  rho = ((f[o] + f[N + o]) + (f[2 * N + o] + f[3 * N + o])) +
+        ((f[4 * N + o] + f[5 * N + o]) + (f[6 * N + o] + f[7 * N + o])) + f[8 * N + o];
+  Tr = ((g[o] + g[N + o]) + (g[2 * N + o] + g[3 * N + o])) + g[4 * N + o];
+}
+
+// psi at (x, y) with wrapping and, in walled domains, the wetting ghost rows (Eq. 54)
+template <typename real>
+__device__ real psi_any(const DevParams<real>& p, const real* __restrict__ f, const real* __restrict__ g, int nx,
+                        int ny, size_t N, int x, int y, unsigned& err) {
+  x = wrapi(x, nx);
+  if (!p.y_walls) y = wrapi(y, ny);
+  real rho, T;
+  if (y == -1 || y == ny) {
+    const int top = y == ny;
+    const int y1 = top ? ny - 1 : 0, y2 = top ? ny - 2 : 1;
+    real r2, r1p, r1m, tt;
+    rho_T(f, g, N, y2 * nx + x, r2, tt);
+    rho_T(f, g, N, y1 * nx + wrapi(x + 1, nx), r1p, tt);
+    rho_T(f, g, N, y1 * nx + wrapi(x - 1, nx), r1m, tt);
+    rho = r2 + (top ? p.tan_top : p.tan_bot) * fabs(r1p - r1m);
+    T = wall_temperature(p, top, x);
+  } else {
+    rho_T(f, g, N, y * nx + x, rho, T);
+    T = p.T_ref + T;
+  }
+  return pseudo(p, rho, T, err);
+}
+
+// rho, u (with half the force of the current state, Eq. 11) and T to FP64 staging:
+// out[0..N) rho, [N..2N) ux, [2N..3N) uy, [3N..4N) T.
+template <typename real>
+__global__ void fields_kernel(DevParams<real> p, const real* __restrict__ f, const real* __restrict__ g, int nx, int ny,
+                              double* __restrict__ out, unsigned* __restrict__ errw) {
+  const size_t N = (size_t)nx * ny;
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  const int x = (int)(k % nx), y = (int)(k / nx);
+  unsigned err = 0u;
+  const int o = (int)k;
+  real rho, Tr;
+  rho_T(f, g, N, o, rho, Tr);
+  real jx = (f[N + o] - f[3 * N + o]) + ((f[5 * N + o] - f[6 * N + o]) + (f[8 * N + o] - f[7 * N + o]));
+  real jy = (f[2 * N + o] - f[4 * N + o]) + ((f[5 * N + o] + f[6 * N + o]) - (f[7 * N + o] + f[8 * N + o]));
+  real fx = real(0), fy = real(0);
+  if (!(p.flags & FL_FREEZE_FLOW)) {
+    const real pc = psi_any(p, f, g, nx, ny, N, x, y, err);
+    const real pE = psi_any(p, f, g, nx, ny, N, x + 1, y, err), pW = psi_any(p, f, g, nx, ny, N, x - 1, y, err);
+    const real pN = psi_any(p, f, g, nx, ny, N, x, y + 1, err), pS = psi_any(p, f, g, nx, ny, N, x, y - 1, err);
+    const real pNE = psi_any(p, f, g, nx, ny, N, x + 1, y + 1, err);
+    const real pNW = psi_any(p, f, g, nx, ny, N, x - 1, y + 1, err);
+    const real pSW = psi_any(p, f, g, nx, ny, N, x - 1, y - 1, err);
+    const real pSE = psi_any(p, f, g, nx, ny, N, x + 1, y - 1, err);
+    const real sx = real(1.0 / 3.0) * (pE - pW) + real(1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));
+    const real sy = real(1.0 / 3.0) * (pN - pS) + real(1.0 / 12.0) * ((pNE + pNW) - (pSE + pSW));
+    fx = -p.G * pc * sx + (rho - p.rho_ave) * p.gx;
+    fy = -p.G * pc * sy + (rho - p.rho_ave) * p.gy;
+  }
+  out[k] = (double)rho;
+  out[N + k] = (double)((jx + real(0.5) * fx) / rho);
+  out[2 * N + k] = (double)((jy + real(0.5) * fy) / rho);
+  out[3 * N + k] = (double)p.T_ref + (double)Tr;
+  if (err) atomicOr(errw, err);
+}
+
+// Deterministic FP64 sums of rho and rho c_v T: each workgroup reduces a fixed contiguous
+// range in a fixed tree order into partials[2*block], a second single-workgroup pass adds the
+// partials in a fixed tree order.
+constexpr int RED_NT = 256;
+
+template <typename real>
+__global__ __launch_bounds__(RED_NT) void diag_partial_kernel(const real* __restrict__ f, const real* __restrict__ g,
+                                                              size_t N, double cv, double T_ref, size_t per_block,
+                                                              double* __restrict__ partials) {
+  __shared__ double sm[RED_NT], se[RED_NT];
+  const size_t begin = (size_t)blockIdx.x * per_block;
+  const size_t end = begin + per_block < N ? begin + per_block : N;
+  double m = 0.0, e = 0.0;
+  for (size_t k = begin + threadIdx.x; k < end; k += RED_NT) {
+    real rho, Tr;
+    rho_T(f, g, N, (int)k, rho, Tr);
+    m += (double)rho;
+    e += (double)rho * cv * (T_ref + (double)Tr);
+  }
+  sm[threadIdx.x] = m;
+  se[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = RED_NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[threadIdx.x] += sm[threadIdx.x + s];
+      se[threadIdx.x] += se[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = sm[0];
+    partials[2 * blockIdx.x + 1] = se[0];
+  }
+}
+
+__global__ __launch_bounds__(RED_NT) void diag_final_kernel(const double* __restrict__ partials, int nparts,
+                                                            double* __restrict__ out) {
+  __shared__ double sm[RED_NT], se[RED_NT];
+  double m = 0.0, e = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += RED_NT) {
+    m += partials[2 * k];
+    e += partials[2 * k + 1];
+  }
+  sm[threadIdx.x] = m;
+  se[threadIdx.x] = e;
+  __syncthreads();
+  for (int s = RED_NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[threadIdx.x] += sm[threadIdx.x + s];
+      se[threadIdx.x] += se[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sm[0];
+    out[1] = se[0];
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,122 @@
+// Device-side pieces of the fused thermal pseudopotential LBM step for gfx950.
+//
+// Data layout in HBM (structure of arrays, x fastest, so that a wavefront of 64 lanes along
+// x reads and writes 64 consecutive values of one population):
+//   f[9][ny][nx], g[5][ny][nx]  in two copies A/B (read one, write the other, swap per step)
+//   Th[2][ny][nx]               temperature history T(t-1), T(t-2), updated in place
+//
+// Temperature storage: g_i is kept as g_i - what_i T_ref and the history as T - T_ref, with T_ref
+// a per-simulation constant (the mean initial temperature).  Relaxation, grad T, the
+// rho c_v blend, the second time difference and anti-bounce-back are all invariant under this
+// shift; only the EOS and Q use the absolute T = T_ref + sum_i g_i.  In FP32 it keeps the
+// resolution of T where it matters (T varies by a few percent around T_ref).
+//
+// Velocity sets (Eqs. 2 and 26): D2Q9 c_0 = (0,0), c_1..4 = (1,0),(0,1),(-1,0),(0,-1),
+// c_5..8 = (1,1),(-1,1),(-1,-1),(1,-1); the D2Q5 set is c_0..c_4 of the same list.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int TX = 64;        // tile width  (one wavefront along x)
+constexpr int TY = 16;        // tile height
+constexpr int NT = 256;       // threads per workgroup: 64 x 4, each thread owns 4 rows
+constexpr int RPT = TY / 4;   // rows per thread
+constexpr int HXW = 3;        // halo columns per side (wetting ghost needs rho at radius 3)
+constexpr int HYW = 2;        // halo rows per side (psi at radius 2 for div u)
+constexpr int EXW = TX + 2 * HXW;
+constexpr int EYW = TY + 2 * HYW;
+constexpr int RING = EXW * EYW - TX * TY;                       // halo cells of the load region
+constexpr int URING = (TX + 2) * (TY + 2) - TX * TY;            // halo cells of the velocity region
+
+// error bits of the device error word
+constexpr unsigned ERR_RHO = 1u;   // density <= 0 or not finite
+constexpr unsigned ERR_T = 2u;     // temperature <= 0 or not finite
+constexpr unsigned ERR_PSI = 4u;   // pseudopotential argument < 0
+
+constexpr unsigned FL_FREEZE_FLOW = 1u;
+constexpr unsigned FL_NO_S = 2u;
+
+// Constants of one simulation, derived once on the host in FP64 and stored in the working
+// precision.
+template <typename real>
+struct DevParams {
+  real a, b, R, G, Tc, kappa;       // Peng-Robinson EOS (Eq. 10), interaction strength (Eq. 9)
+  real s_e, s_eps, s_q, s_p;        // D2Q9 MRT rates (Eq. 5)
+  real corr_e, corr_eps;            // sigma / (1/s - 1/2) of Li's forcing (Eq. 8)
+  real cv, wdot, w0h, w1h;          // D2Q5 weights (Eq. 26)
+  real vs1, vs3, vs4, inv_cs2h;     // D2Q5 MRT rates; 1/chat_s^2
+  real gx, gy, rho_ave;             // buoyancy
+  real T_box, T_top, T_bot, hot_dT, hot_x0, inv_2s2;
+  real tan_bot, tan_top;            // tan(pi/2 - theta) of the wetting rule (Eq. 54)
+  real T_ref;                       // g and the history are stored relative to T_ref (see below)
+  int y_walls, thermal_box;
+  unsigned flags;
+  int pad;
+};
+
+// One simulation as seen by the step kernel.  The step kernel serves single runs (a one-entry
+// table) and batches (many entries) with the same code.
+template <typename real>
+struct InstDesc {
+  real* fA;
+  real* gA;
+  real* fB;
+  real* gB;
+  real* Th;
+  unsigned* err;
+  int nx, ny;
+  int ntx, nty;        // tiles along x and y
+  int tile_begin;      // first workgroup index of this instance in the launch
+  int pad;
+  long long t_start;   // clock value at which this instance had taken zero steps
+  long long t_end;     // clock value at which it stops
+  DevParams<real> p;
+};
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// Peng-Robinson pressure and (dp/dT)_rho (Eq. 10).  phi(T) = s^2, s = 1 + kappa (1 - sqrt(T/Tc)),
+// dphi/dT = -kappa s / (Tc sqrt(T/Tc)).
+template <typename real>
+__device__ __forceinline__ void pr_eos(const DevParams<real>& p, real rho, real T, real& press, real& dpdT) {
+  const real sq = sqrt(T / p.Tc);
+  const real s = real(1) + p.kappa * (real(1) - sq);
+  const real br = p.b * rho;
+  const real i1 = real(1) / (real(1) - br);
+  const real i2 = real(1) / (real(1) + real(2) * br - br * br);
+  const real rr = rho * rho;
+  press = rho * p.R * T * i1 - p.a * s * s * rr * i2;
+  dpdT = rho * p.R * i1 + p.a * p.kappa * s / (p.Tc * sq) * rr * i2;
+}
+
+// Pseudopotential psi = sqrt(2 (p_EOS - rho c_s^2) / G) (text after Eq. 9); flags a negative
+// argument.
+template <typename real>
+__device__ __forceinline__ real pseudo(const DevParams<real>& p, real rho, real T, unsigned& err) {
+  real press, dpdT;
+  pr_eos(p, rho, T, press, dpdT);
+  const real arg = real(2) * (press - rho * real(1.0 / 3.0)) / p.G;
+  if (!(arg >= real(0))) {
+    err |= ERR_PSI;
+    return real(0);
+  }
+  return sqrt(arg);
+}
+
+// Wall temperature at column x for a link leaving through the bottom (side 0) or top (side 1).
+template <typename real>
+__device__ __forceinline__ real wall_temperature(const DevParams<real>& p, int side, int x) {
+  if (p.thermal_box) return p.T_box;
+  if (side == 0) {
+    const real d = real(x) - p.hot_x0;
+    return p.T_bot + p.hot_dT * exp(-d * d * p.inv_2s2);
+  }
+  return p.T_top;
+}
+
+}  // namespace lbm

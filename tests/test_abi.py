@@ -1,0 +1,103 @@
+"""The C-ABI library loads on a machine without a GPU, exports every symbol include/lbm.h
+declares, and its host-only entry points behave (no device work is done here)."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2205_00686_amd import _native
+    return _native.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    from paper_2205_00686_amd import _native
+    syms = _declared_symbols()
+    assert len(syms) >= 20
+    assert set(syms) == set(_native.EXPORTS)
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_library_carries_gfx950_code_object():
+    so = os.path.join(ROOT, "paper_2205_00686_amd", "liblbm.so")
+    assert b"amdgcn-amd-amdhsa--gfx950" in open(so, "rb").read()
+
+
+def test_validate_and_footprint(L):
+    from paper_2205_00686_amd import _native
+    p = _native.LbmParams()
+    L.lbm_params_default(ctypes.byref(p), 512, 512)
+    assert L.lbm_validate(ctypes.byref(p)) == 0
+    n = 512 * 512
+    fp = L.lbm_footprint_bytes(ctypes.byref(p))
+    assert 120 * n <= fp <= 120 * n + 64 * 1024  # f, g twice + history, FP32, plus a small control block
+    p.precision = 1
+    assert 240 * n <= L.lbm_footprint_bytes(ctypes.byref(p)) <= 240 * n + 64 * 1024
+    for field, bad in (("nx", 2), ("ny", 1), ("nu", -0.1), ("s_e", 2.0), ("wdot", 1.0), ("cv", 0.0),
+                       ("precision", 7), ("lambda_", 0.0)):
+        q = _native.LbmParams()
+        L.lbm_params_default(ctypes.byref(q), 64, 64)
+        setattr(q, field, bad)
+        assert L.lbm_validate(ctypes.byref(q)) == -1, field
+        assert L.lbm_footprint_bytes(ctypes.byref(q)) == 0
+    q = _native.LbmParams()
+    L.lbm_params_default(ctypes.byref(q), 64, 64)
+    q.y_walls = 1  # walls without wall temperatures
+    assert L.lbm_validate(ctypes.byref(q)) == -1
+
+
+def test_create_rejects_small_or_misaligned_buffers(L):
+    from paper_2205_00686_amd import _native
+    p = _native.LbmParams()
+    L.lbm_params_default(ctypes.byref(p), 64, 64)
+    h = ctypes.c_void_p()
+    need = L.lbm_footprint_bytes(ctypes.byref(p))
+    # host-side argument checks happen before any device call
+    assert L.lbm_create(ctypes.byref(p), ctypes.c_void_p(4096), need - 1, None, ctypes.byref(h)) == -2
+    assert L.lbm_create(ctypes.byref(p), ctypes.c_void_p(4097), need, None, ctypes.byref(h)) == -1
+    assert L.lbm_create(ctypes.byref(p), None, need, None, ctypes.byref(h)) == -1
+
+
+def test_default_parameters_are_the_papers(L):
+    from paper_2205_00686_amd import _native
+    p = _native.LbmParams()
+    L.lbm_params_default(ctypes.byref(p), 10, 20)
+    assert (p.nx, p.ny) == (10, 20)
+    assert p.a == pytest.approx(3 / 49) and p.b == pytest.approx(2 / 21) and p.R == 1 and p.G == -1
+    assert p.acentric == 0.344 and p.nu == 0.1 and p.cv == 5.0 and p.lambda_ == pytest.approx(1 / 3)
+    assert math.isnan(p.rho_ave)
+
+
+def test_critical_temperature_and_coexistence_agree_with_oracle(L, orc, base_params):
+    """Two independent implementations of the Maxwell construction (library: Gauss-Legendre,
+    golden section; oracle: Simpson, scan) agree."""
+    import paper_2205_00686_amd as lbm
+    Tc = lbm.critical_temperature(base_params)
+    assert Tc == pytest.approx(orc.Tc(base_params), rel=1e-15)
+    for tr in (0.8, 0.86, 0.9, 0.946):
+        a = lbm.coexistence(base_params, tr * Tc)
+        b = orc.maxwell(base_params, tr * Tc)
+        assert a[0] == pytest.approx(b[0], rel=1e-9)
+        assert a[1] == pytest.approx(b[1], rel=1e-8)
+        assert a[2] == pytest.approx(b[2], rel=1e-8)
+    with pytest.raises(lbm.LbmError):
+        lbm.coexistence(base_params, 1.05 * Tc)
+
+
+def test_strerror(L):
+    for s in (0, -1, -2, -3, -4, -5):
+        assert len(L.lbm_strerror(s)) > 0

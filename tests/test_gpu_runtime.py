@@ -1,0 +1,202 @@
+"""GPU runtime behaviour through the C ABI: graph replay vs single launches, determinism,
+checkpoint/resume, batched vs alone (bit-identical), failure detection, and parity at the full
+sizes of the benchmark workloads over a short horizon."""
+import numpy as np
+import pytest
+
+from workloads import Params, boiling, droplet, evaporation
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_00686_amd as lbm
+    return lbm
+
+
+@pytest.fixture(scope="module")
+def sat_gpu(lbm):
+    base = Params()
+    Tc = lbm.critical_temperature(base)
+    rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
+    return Tc, rl, rg
+
+
+def _raw(s):
+    f, g, h = s.state(absolute=False)
+    return np.concatenate([f.ravel(), g.ravel(), h.ravel()])
+
+
+def test_graph_replay_equals_single_launches(lbm, sat_gpu):
+    Tc, rl, rg = sat_gpu
+    w = boiling(Tc, rl, rg, nx=96, ny=80, hot_width=6.0, seed=3)
+    print("\n[case] graph vs single launches 96x80 boiling fp32", flush=True)
+    a = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    b = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    a.step(150)  # two 64-step graph replays + 22 single launches
+    for _ in range(150):
+        b.step(1)
+    assert a.steps == b.steps == 150
+    assert np.array_equal(_raw(a), _raw(b))
+
+
+def test_runs_are_bitwise_deterministic(lbm, sat_gpu):
+    Tc, rl, rg = sat_gpu
+    w = evaporation(Tc, rl, rg, nx=200, ny=130, R=30.0, superheat=1.2, hot_vapour=True)
+    print("\n[case] determinism 200x130 evaporation fp32", flush=True)
+    outs = []
+    for _ in range(2):
+        s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+        s.step(300)
+        outs.append(_raw(s))
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_checkpoint_resume_is_exact(lbm, sat_gpu, precision):
+    Tc, rl, rg = sat_gpu
+    w = boiling(Tc, rl, rg, nx=80, ny=64, hot_width=6.0, seed=5)
+    print(f"\n[case] checkpoint 80x64 boiling prec={precision}", flush=True)
+    a = lbm.Solver(w.params, precision=precision).init(w.rho, w.ux, w.uy, w.T)
+    a.step(101)  # odd: the saved state sits in the B buffers
+    blob = a.save_state()
+    a.step(77)
+    b = lbm.Solver(w.params, precision=precision).init(w.rho * 0 + 1.0, w.ux, w.uy, w.T)
+    b.load_state(blob)
+    assert b.steps == 101
+    b.step(77)
+    assert np.array_equal(_raw(a), _raw(b))
+    fa, fb = a.fields(), b.fields()
+    for x, y in zip(fa, fb):
+        assert np.array_equal(x, y)
+
+
+def test_batch_equals_alone_bitwise(lbm, sat_gpu):
+    """Instances of different sizes, parameters and step budgets in one batched launch give the
+    same bits as each run alone."""
+    Tc, rl, rg = sat_gpu
+    ws = [boiling(Tc, rl, rg, nx=128, ny=96, gravity=3e-5, dT_rel=0.25, hot_width=8.0, seed=1),
+          evaporation(Tc, rl, rg, nx=100, ny=70, R=15.0, superheat=1.15),
+          droplet(Tc, rl, rg, nx=64, ny=64, R=16.0),
+          boiling(Tc, rl, rg, nx=70, ny=130, gravity=1e-5, dT_rel=0.1, hot_width=5.0, seed=2)]
+    budgets = [150, 97, 64, 200]
+    print("\n[case] batch of 4 vs alone", flush=True)
+    alone = []
+    for w, n in zip(ws, budgets):
+        s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+        s.step(n)
+        alone.append(_raw(s))
+    solvers = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for w in ws]
+    # one instance takes 10 plain steps first: the batch must continue its parity
+    solvers[3].step(10)
+    b = lbm.Batch(solvers)
+    for i, n in enumerate(budgets):
+        b.set_budget(i, n - (10 if i == 3 else 0))
+    b.step(70)
+    b.step(200)
+    st = b.sync()
+    assert st == [0, 0, 0, 0]
+    for i, s in enumerate(solvers):
+        assert s.steps == budgets[i]
+        assert np.array_equal(_raw(s), alone[i]), i
+    # and plain stepping continues correctly after the batch
+    solvers[2].step(5)
+    ref = lbm.Solver(ws[2].params).init(ws[2].rho, ws[2].ux, ws[2].uy, ws[2].T)
+    ref.step(69)
+    assert np.array_equal(_raw(solvers[2]), _raw(ref))
+
+
+def test_nan_population_is_reported(lbm, sat_gpu):
+    Tc, rl, rg = sat_gpu
+    w = droplet(Tc, rl, rg, nx=64, ny=48, R=10.0)
+    print("\n[case] failure injection", flush=True)
+    s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    s.step(3)
+    blob = bytearray(s.save_state())
+    f = np.frombuffer(blob, dtype=np.float32, count=9 * 64 * 48).copy()
+    f[5 * 64 * 48 + 20 * 64 + 7] = np.nan
+    blob[: f.nbytes] = f.tobytes()
+    s.load_state(bytes(blob))
+    s.step(2)
+    with pytest.raises(lbm.LbmError) as e:
+        s.sync()
+    assert e.value.status == -4
+    with pytest.raises(lbm.LbmError) as e:
+        s.step(1)
+    assert e.value.status == -5
+    # a second, healthy context on the same device is unaffected
+    t = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    t.step(5)
+    t.sync()
+
+
+def test_density_above_eos_limit_is_reported(lbm, sat_gpu):
+    Tc, rl, rg = sat_gpu
+    w = droplet(Tc, rl, rg, nx=32, ny=32, R=8.0)
+    rho = w.rho.copy()
+    rho[16, 16] = 9.5  # p_EOS > rho/3: the pseudopotential is undefined there
+    s = lbm.Solver(w.params).init(rho, w.ux, w.uy, w.T)
+    s.step(1)
+    with pytest.raises(lbm.LbmError) as e:
+        s.sync()
+    assert e.value.status == -4
+
+
+def test_init_rejects_unstable_heat_capacity(lbm, sat_gpu):
+    Tc, rl, rg = sat_gpu
+    w = droplet(Tc, rl, rg, nx=32, ny=32, R=8.0, cv=0.1)  # the literal value printed in Section 4.1
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    assert e.value.status == -1
+
+
+def test_evaporation_full_size_fp32_vs_oracle(lbm, orc, sat_gpu):
+    """Benchmark workload at full size (512 x 512, FP32, launch configuration of bench.py) against
+    the FP64 oracle over 100 steps: rho within 1e-4 relative, T within 1e-6 relative."""
+    Tc, rl, rg = sat_gpu
+    w = evaporation(Tc, rl, rg, nx=512, ny=512, R=64.0, superheat=1.10)
+    print("\n[case] evaporation 512x512 fp32 100 steps vs oracle", flush=True)
+    s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    s.step(100)
+    o = orc.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
+    o.step(100)
+    g, e = s.fields(), o.fields()
+    err = [float(np.abs(a - b).max()) for a, b in zip(g, e)]
+    print(f"   max abs err rho={err[0]:.3e} ux={err[1]:.3e} uy={err[2]:.3e} T={err[3]:.3e}", flush=True)
+    assert err[0] <= 1e-4 * rl
+    assert err[3] <= 1e-6 * float(e[3].max())
+    assert max(err[1], err[2]) <= 1e-6
+
+
+def test_boiling_full_size_fp32_vs_oracle(lbm, orc, sat_gpu):
+    """Nucleate boiling at full size (1024 x 2048, FP32) against the FP64 oracle over 20 steps."""
+    Tc, rl, rg = sat_gpu
+    w = boiling(Tc, rl, rg)
+    print("\n[case] boiling 1024x2048 fp32 20 steps vs oracle", flush=True)
+    s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    s.step(20)
+    o = orc.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
+    o.step(20)
+    g, e = s.fields(), o.fields()
+    err = [float(np.abs(a - b).max()) for a, b in zip(g, e)]
+    print(f"   max abs err rho={err[0]:.3e} ux={err[1]:.3e} uy={err[2]:.3e} T={err[3]:.3e}", flush=True)
+    assert err[0] <= 1e-4 * rl
+    assert err[3] <= 1e-6 * float(e[3].max())
+    assert max(err[1], err[2]) <= 1e-6
+
+
+def test_mass_conservation_fp32_long(lbm, sat_gpu):
+    """2000 steps of the 512 x 512 workload in FP32: total mass (FP64 sum) drifts by less than
+    1e-6 relative (each step conserves it exactly up to FP32 rounding of the populations)."""
+    Tc, rl, rg = sat_gpu
+    w = evaporation(Tc, rl, rg, nx=512, ny=512, R=64.0, superheat=1.10)
+    s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    m0, _ = s.diagnostics()
+    s.step(2000)
+    m1, _ = s.diagnostics()
+    print(f"\n[case] fp32 mass drift over 2000 steps: {(m1 - m0) / m0:.3e}", flush=True)
+    assert abs(m1 - m0) <= 1e-6 * m0
