@@ -62,6 +62,9 @@ def main():
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=400)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibration-copy-mib", type=int, default=0,
+                    help="before the timed region, copy this many MiB device-to-device once (a plain copy "
+                         "kernel of known size, used to scale the HBM byte counters of a profile)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library runs each simulation on a single device "
@@ -79,6 +82,13 @@ def main():
     print(f"[bench] {args.nx}x{args.ny} evaporation FP32, warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
           flush=True)
 
+    if args.calibration_copy_mib > 0:
+        n = args.calibration_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s.step(args.warmup)
     s.sync()
     torch.cuda.synchronize()

@@ -113,6 +113,8 @@ static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref)
   d.R = (real)p->R;
   d.G = (real)p->G;
   d.Tc = (real)Tc;
+  d.inv_Tc = (real)(1.0 / Tc);
+  d.inv_G = (real)(1.0 / p->G);
   d.kappa = (real)pr_kappa(p);
   d.s_e = (real)p->s_e;
   d.s_eps = (real)p->s_eps;
@@ -361,9 +363,11 @@ static lbm_status launch_steps(lbm_ctx* h, int n) {
   const long long* clk = h->d_clock;
   for (int k = 0; k < n; ++k) {
     if (h->prm.precision == LBM_FP64)
-      step_kernel<double><<<h->ntiles, NT, 0, h->stream>>>((const InstDesc<double>*)h->d_desc, 1, clk, k);
+      step_kernel<double, StepShape<double>::WAVES, StepShape<double>::MINW><<<h->ntiles, 64 * StepShape<double>::WAVES, 0, h->stream>>>(
+          (const InstDesc<double>*)h->d_desc, 1, clk, k);
     else
-      step_kernel<float><<<h->ntiles, NT, 0, h->stream>>>((const InstDesc<float>*)h->d_desc, 1, clk, k);
+      step_kernel<float, StepShape<float>::WAVES, StepShape<float>::MINW><<<h->ntiles, 64 * StepShape<float>::WAVES, 0, h->stream>>>(
+          (const InstDesc<float>*)h->d_desc, 1, clk, k);
   }
   clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n);
   HIP_OR_FAIL(h, hipGetLastError());
@@ -753,9 +757,11 @@ static lbm_status batch_launch(lbm_batch* b, int k) {
   const int n = (int)b->ctx.size();
   for (int s = 0; s < k; ++s) {
     if (b->precision == LBM_FP64)
-      step_kernel<double><<<b->total_tiles, NT, 0, b->stream>>>((const InstDesc<double>*)b->d_table, n, b->d_clock, s);
+      step_kernel<double, StepShape<double>::WAVES, StepShape<double>::MINW><<<b->total_tiles, 64 * StepShape<double>::WAVES, 0, b->stream>>>(
+          (const InstDesc<double>*)b->d_table, n, b->d_clock, s);
     else
-      step_kernel<float><<<b->total_tiles, NT, 0, b->stream>>>((const InstDesc<float>*)b->d_table, n, b->d_clock, s);
+      step_kernel<float, StepShape<float>::WAVES, StepShape<float>::MINW><<<b->total_tiles, 64 * StepShape<float>::WAVES, 0, b->stream>>>(
+          (const InstDesc<float>*)b->d_table, n, b->d_clock, s);
   }
   clock_advance_kernel<<<1, 64, 0, b->stream>>>(b->d_clock, (long long)k);
   HIP_OR_FAIL(b->ctx[0], hipGetLastError());

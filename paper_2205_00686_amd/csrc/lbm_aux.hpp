@@ -43,16 +43,16 @@ __device__ __forceinline__ void rho_T(const real* __restrict__ f, const real* __
 template <typename real>
 __device__ real psi_any(const DevParams<real>& p, const real* __restrict__ f, const real* __restrict__ g, int nx,
                         int ny, size_t N, int x, int y, unsigned& err) {
-  x = wrapi(x, nx);
-  if (!p.y_walls) y = wrapi(y, ny);
+  x = wrapi(x, nx, true);
+  if (!p.y_walls) y = wrapi(y, ny, true);
   real rho, T;
   if (y == -1 || y == ny) {
     const int top = y == ny;
     const int y1 = top ? ny - 1 : 0, y2 = top ? ny - 2 : 1;
     real r2, r1p, r1m, tt;
     rho_T(f, g, N, y2 * nx + x, r2, tt);
-    rho_T(f, g, N, y1 * nx + wrapi(x + 1, nx), r1p, tt);
-    rho_T(f, g, N, y1 * nx + wrapi(x - 1, nx), r1m, tt);
+    rho_T(f, g, N, y1 * nx + wrapi(x + 1, nx, true), r1p, tt);
+    rho_T(f, g, N, y1 * nx + wrapi(x - 1, nx, true), r1m, tt);
     rho = r2 + (top ? p.tan_top : p.tan_bot) * fabs(r1p - r1m);
     T = wall_temperature(p, top, x);
   } else {

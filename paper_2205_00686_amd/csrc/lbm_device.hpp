@@ -20,9 +20,8 @@
 namespace lbm {
 
 constexpr int TX = 64;        // tile width  (one wavefront along x)
-constexpr int TY = 16;        // tile height
-constexpr int NT = 256;       // threads per workgroup: 64 x 4, each thread owns 4 rows
-constexpr int RPT = TY / 4;   // rows per thread
+constexpr int TY = 16;        // tile height (the workgroup has TY / rows-per-thread wavefronts)
+constexpr int NXCD = 8;       // accelerator complex dies of an MI355X (each with its own L2)
 constexpr int HXW = 3;        // halo columns per side (wetting ghost needs rho at radius 3)
 constexpr int HYW = 2;        // halo rows per side (psi at radius 2 for div u)
 constexpr int EXW = TX + 2 * HXW;
@@ -43,6 +42,7 @@ constexpr unsigned FL_NO_S = 2u;
 template <typename real>
 struct DevParams {
   real a, b, R, G, Tc, kappa;       // Peng-Robinson EOS (Eq. 10), interaction strength (Eq. 9)
+  real inv_Tc, inv_G;
   real s_e, s_eps, s_q, s_p;        // D2Q9 MRT rates (Eq. 5)
   real corr_e, corr_eps;            // sigma / (1/s - 1/2) of Li's forcing (Eq. 8)
   real cv, wdot, w0h, w1h;          // D2Q5 weights (Eq. 26)
@@ -75,37 +75,82 @@ struct InstDesc {
   DevParams<real> p;
 };
 
-__device__ __forceinline__ int wrapi(int v, int n) {
-  int r = v % n;
-  return r < 0 ? r + n : r;
+// Pointers into device memory.  The step kernel takes its buffers from a descriptor table in
+// memory, so the compiler cannot infer their address space; declaring it makes every access a
+// global (not flat) instruction, which does not share the LDS wait counter.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> to_global(T* p) {
+  return (gptr<T>)p;
 }
 
-// Peng-Robinson pressure and (dp/dT)_rho (Eq. 10).  phi(T) = s^2, s = 1 + kappa (1 - sqrt(T/Tc)),
+// Reciprocal and square root: hardware instructions (1 ulp) in FP32, IEEE-exact in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+
+// Periodic wrap of an index.  On grids at least as large as a tile plus its halo the index is
+// less than one period away from [0, n) and one compare with add/subtract suffices; smaller
+// grids (flag `tiny`, uniform per launch) take the modulo.
+__device__ __forceinline__ int wrapi(int v, int n, bool tiny) {
+  if (__builtin_expect(tiny, 0)) {
+    v %= n;
+    return v < 0 ? v + n : v;
+  }
+  v = v < 0 ? v + n : v;
+  return v >= n ? v - n : v;
+}
+
+// Peng-Robinson pressure (Eq. 10): p = rho R T/(1 - b rho) - a phi(T) rho^2/(1 + 2 b rho - b^2 rho^2),
+// phi(T) = s^2, s = 1 + kappa (1 - sqrt(T/Tc)).  With the pressure also (dp/dT)_rho, where
 // dphi/dT = -kappa s / (Tc sqrt(T/Tc)).
+// Reciprocal square root: hardware instruction in FP32, IEEE-exact in FP64.
+__device__ __forceinline__ float frsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double frsqrt(double x) { return 1.0 / sqrt(x); }
+
+// Peng-Robinson pressure (Eq. 10): p = rho R T/(1 - b rho) - a phi(T) rho^2/(1 + 2 b rho - b^2 rho^2),
+// phi(T) = s^2, s = 1 + kappa (1 - sqrt(T/Tc)); with it (dp/dT)_rho, where
+// dphi/dT = -kappa s / sqrt(T Tc).  One reciprocal square root (sqrt(T/Tc) = T / sqrt(T Tc)) and
+// one reciprocal of the product of the two denominators.
 template <typename real>
 __device__ __forceinline__ void pr_eos(const DevParams<real>& p, real rho, real T, real& press, real& dpdT) {
-  const real sq = sqrt(T / p.Tc);
+  const real rs = frsqrt(T * p.Tc);  // 1/sqrt(T Tc)
+  const real sq = T * rs;            // sqrt(T/Tc)
   const real s = real(1) + p.kappa * (real(1) - sq);
   const real br = p.b * rho;
-  const real i1 = real(1) / (real(1) - br);
-  const real i2 = real(1) / (real(1) + real(2) * br - br * br);
+  const real den1 = real(1) - br;
+  const real den2 = real(1) + br * (real(2) - br);
+  const real i12 = rcp(den1 * den2);
+  const real i1 = den2 * i12, i2 = den1 * i12;
   const real rr = rho * rho;
   press = rho * p.R * T * i1 - p.a * s * s * rr * i2;
-  dpdT = rho * p.R * i1 + p.a * p.kappa * s / (p.Tc * sq) * rr * i2;
+  dpdT = rho * p.R * i1 + p.a * p.kappa * s * rs * rr * i2;
+}
+
+template <typename real>
+__device__ __forceinline__ real pr_pressure(const DevParams<real>& p, real rho, real T) {
+  real press, dpdT;
+  pr_eos(p, rho, T, press, dpdT);
+  return press;
 }
 
 // Pseudopotential psi = sqrt(2 (p_EOS - rho c_s^2) / G) (text after Eq. 9); flags a negative
 // argument.
 template <typename real>
-__device__ __forceinline__ real pseudo(const DevParams<real>& p, real rho, real T, unsigned& err) {
-  real press, dpdT;
-  pr_eos(p, rho, T, press, dpdT);
-  const real arg = real(2) * (press - rho * real(1.0 / 3.0)) / p.G;
+__device__ __forceinline__ real psi_from_pressure(const DevParams<real>& p, real rho, real press, unsigned& err) {
+  const real arg = real(2) * (press - rho * real(1.0 / 3.0)) * p.inv_G;
   if (!(arg >= real(0))) {
     err |= ERR_PSI;
     return real(0);
   }
-  return sqrt(arg);
+  return fsqrt(arg);
+}
+
+template <typename real>
+__device__ __forceinline__ real pseudo(const DevParams<real>& p, real rho, real T, unsigned& err) {
+  return psi_from_pressure(p, rho, pr_pressure(p, rho, T), err);
 }
 
 // Wall temperature at column x for a link leaving through the bottom (side 0) or top (side 1).

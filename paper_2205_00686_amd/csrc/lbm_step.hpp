@@ -3,15 +3,18 @@
 // Phases (each separated by a workgroup barrier; the arithmetic of a node never depends on
 // where its tile lies, so a node's result is the same in a single run and in a batch):
 //   1  load f and g of the tile plus a halo (HXW columns, HYW rows); per node rho, j, T
-//      (Eqs. 11, 25) and psi (Eq. 10 and the text after Eq. 9) into LDS; own nodes keep f, g
-//      in registers.  Wall tiles then fill the ghost rows with the wetting density of Eq. (54)
-//      at the wall temperature.
+//      (Eqs. 11, 25), 1/(rho c_v) and psi (Eq. 10 and the text after Eq. 9) into LDS; own nodes
+//      keep f, g and (dp/dT)_rho in registers.  Wall tiles then fill the ghost rows with the
+//      wetting density of Eq. (54) at the wall temperature.
 //   2  on the tile plus one halo node: interaction force (Eq. 9), buoyancy, velocity (Eq. 11).
 //   3  own nodes: div u (isotropic stencil, mirrored ghost velocity at walls), grad T from the
 //      D2Q5 non-equilibrium moments (Eqs. 49-50), Q (Eq. 20), S (Eq. 24, backward second
 //      difference of T), MRT collision of f with Li's forcing (Eqs. 5, 7, 8), MRT collision of
 //      g (Eq. 39), push-streaming of f (Eq. 6, halfway bounce-back at walls) and of g with the
 //      rho c_v-weighted blend at the destination (Eq. 39; anti-bounce-back at Dirichlet edges).
+//
+// A workgroup has WAVES wavefronts of 64 lanes along x; each thread owns TY / WAVES rows of its
+// column (rows ty, ty + WAVES, ...).
 #pragma once
 #include "lbm_device.hpp"
 
@@ -20,8 +23,9 @@ namespace lbm {
 template <typename real>
 struct StepLds {
   real rho[EYW][EXW];
+  real irc[EYW][EXW];  // 1 / (rho c_v), needed at the streaming destination
   real psi[EYW][EXW];
-  real ux[EYW][EXW];  // holds j_x after phase 1, u_x after phase 2
+  real ux[EYW][EXW];   // holds j_x after phase 1, u_x after phase 2
   real uy[EYW][EXW];
   real g[4][EYW][EXW];  // pre-collision g_1..g_4 (needed at the streaming destination)
 };
@@ -66,27 +70,35 @@ __device__ __forceinline__ int row_kind(int y, int ny, int walls) {
 }
 
 template <typename real>
-__device__ __forceinline__ void load_node(const real* __restrict__ fs, const real* __restrict__ gs, size_t N, int o,
+__device__ __forceinline__ void load_node(gptr<const real> fs, gptr<const real> gs, size_t N, unsigned o,
                                           real (&f)[9], real (&g)[5]) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = fs[i * N + o];
+  for (int i = 0; i < 9; ++i) f[i] = (fs + i * N)[o];
 #pragma unroll
-  for (int i = 0; i < 5; ++i) g[i] = gs[i * N + o];
+  for (int i = 0; i < 5; ++i) g[i] = (gs + i * N)[o];
 }
 
-// rho, j, T of a node and its LDS entries (Eqs. 11 and 25), psi with error checks
+// rho, j, T of a node and its LDS entries (Eqs. 11 and 25), psi with error checks; returns
+// (dp/dT)_rho for the node's own collision
 template <typename real>
-__device__ __forceinline__ void node_macro_to_lds(StepLds<real>& L, int ex, int ey, const DevParams<real>& p,
+__device__ __forceinline__ real node_macro_to_lds(StepLds<real>& L, int ex, int ey, const DevParams<real>& p,
                                                   const real (&f)[9], const real (&g)[5], unsigned& err) {
   const real rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const real jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
   const real jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
   const real T = p.T_ref + (((g[0] + g[1]) + (g[2] + g[3])) + g[4]);
-  real psi = real(0);
-  if (!(rho > real(0)) || !isfinite(rho)) err |= ERR_RHO;
-  else if (!(T > real(0)) || !isfinite(T)) err |= ERR_T;
-  else psi = pseudo(p, rho, T, err);
+  real psi = real(0), dpdT = real(0);
+  if (!(rho > real(0)) || !isfinite(rho)) {
+    err |= ERR_RHO;
+  } else if (!(T > real(0)) || !isfinite(T)) {
+    err |= ERR_T;
+  } else {
+    real press;
+    pr_eos(p, rho, T, press, dpdT);
+    psi = psi_from_pressure(p, rho, press, err);
+  }
   L.rho[ey][ex] = rho;
+  L.irc[ey][ex] = rcp(rho * p.cv);
   L.psi[ey][ex] = psi;
   L.ux[ey][ex] = jx;
   L.uy[ey][ex] = jy;
@@ -94,11 +106,13 @@ __device__ __forceinline__ void node_macro_to_lds(StepLds<real>& L, int ex, int 
   L.g[1][ey][ex] = g[2];
   L.g[2][ey][ex] = g[3];
   L.g[3][ey][ex] = g[4];
+  return dpdT;
 }
 
 template <typename real>
 __device__ __forceinline__ void zero_lds_cell(StepLds<real>& L, int ex, int ey) {
   L.rho[ey][ex] = real(0);
+  L.irc[ey][ex] = real(0);
   L.psi[ey][ex] = real(0);
   L.ux[ey][ex] = real(0);
   L.uy[ey][ex] = real(0);
@@ -106,68 +120,61 @@ __device__ __forceinline__ void zero_lds_cell(StepLds<real>& L, int ex, int ey) 
   for (int k = 0; k < 4; ++k) L.g[k][ey][ex] = real(0);
 }
 
-// Interaction force F_m = -G psi(x) sum_i varpi_i psi(x + c_i) c_i (Eq. 9), varpi = 1/3, 1/12
+// Stencil of the interaction force: F_m = -G psi(x) (sx, sy) with (sx, sy) =
+// sum_i varpi_i psi(x + c_i) c_i (Eq. 9), varpi = 1/3 (axes), 1/12 (diagonals)
 template <typename real>
-__device__ __forceinline__ void interaction_force(const StepLds<real>& L, int ex, int ey, real G, real& fx, real& fy) {
+__device__ __forceinline__ void psi_stencil(const StepLds<real>& L, int ex, int ey, real& sx, real& sy) {
   const real pE = L.psi[ey][ex + 1], pN = L.psi[ey + 1][ex], pW = L.psi[ey][ex - 1], pS = L.psi[ey - 1][ex];
   const real pNE = L.psi[ey + 1][ex + 1], pNW = L.psi[ey + 1][ex - 1], pSW = L.psi[ey - 1][ex - 1],
              pSE = L.psi[ey - 1][ex + 1];
-  const real sx = real(1.0 / 3.0) * (pE - pW) + real(1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));
-  const real sy = real(1.0 / 3.0) * (pN - pS) + real(1.0 / 12.0) * ((pNE + pNW) - (pSE + pSW));
-  const real c = -G * L.psi[ey][ex];
-  fx = c * sx;
-  fy = c * sy;
+  sx = real(1.0 / 3.0) * (pE - pW) + real(1.0 / 12.0) * ((pNE - pNW) + (pSE - pSW));
+  sy = real(1.0 / 3.0) * (pN - pS) + real(1.0 / 12.0) * ((pNE + pNW) - (pSE + pSW));
 }
 
-template <typename real>
-__global__ __launch_bounds__(NT) void step_kernel(const InstDesc<real>* __restrict__ table, int ninst,
-                                                  const long long* __restrict__ clock, int k) {
-  // ---- which simulation and which tile (uniform per workgroup)
-  const int bid = blockIdx.x;
-  int lo = 0, hi = ninst - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (table[mid].tile_begin <= bid) lo = mid;
-    else hi = mid - 1;
-  }
-  const InstDesc<real>& D = table[lo];
-  const long long t = *clock + k;
-  if (t < D.t_start || t >= D.t_end) return;
-  const int tile = bid - D.tile_begin;
-  if (tile < 0 || tile >= D.ntx * D.nty) return;
-  const int by = tile / D.ntx;
-  const int bx = tile - by * D.ntx;
-  const int x0 = bx * TX, y0 = by * TY;
+// One tile.  INTERIOR tiles (load region entirely inside the grid, away from walls and
+// Dirichlet edges) need no index wrapping and no boundary tests; the general variant handles
+// periodic wrap, wall ghost rows, bounce-back and anti-bounce-back.  Both variants perform the
+// same arithmetic on every node.
+template <typename real, int WAVES, bool INTERIOR>
+__device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>& L, long long t, int x0, int y0) {
+  constexpr int NT = 64 * WAVES;
+  constexpr int RPT = TY / WAVES;
+  static_assert(RPT * WAVES == TY, "rows per thread must divide the tile height");
   const int nx = D.nx, ny = D.ny;
   const size_t N = (size_t)nx * (size_t)ny;
   const bool odd = ((t - D.t_start) & 1) != 0;
-  const real* __restrict__ fs = odd ? D.fB : D.fA;
-  const real* __restrict__ gs = odd ? D.gB : D.gA;
-  real* __restrict__ fd = odd ? D.fA : D.fB;
-  real* __restrict__ gd = odd ? D.gA : D.gB;
-  real* __restrict__ Th = D.Th;
+  const gptr<const real> fs = to_global<const real>(odd ? D.fB : D.fA);
+  const gptr<const real> gs = to_global<const real>(odd ? D.gB : D.gA);
+  const gptr<real> fd = to_global<real>(odd ? D.fA : D.fB);
+  const gptr<real> gd = to_global<real>(odd ? D.gA : D.gB);
+  const gptr<real> Th = to_global<real>(D.Th);
   const DevParams<real> p = D.p;
-  const int walls = p.y_walls;
+  const int walls = INTERIOR ? 0 : p.y_walls;
+  const bool tb = INTERIOR ? false : p.thermal_box != 0;
   const bool freeze = (p.flags & FL_FREEZE_FLOW) != 0;
+  const bool tiny = nx < EXW + 1 || ny < EYW + 1;  // periodic images closer than one halo
 
-  __shared__ StepLds<real> L;
   const int tid = threadIdx.x;
   const int tx = tid & (TX - 1);
   const int ty = tid >> 6;
   unsigned err = 0u;
 
+  auto wx = [&](int v) { return INTERIOR ? v : wrapi(v, nx, tiny); };
+  auto wy = [&](int v) { return (INTERIOR || walls) ? v : wrapi(v, ny, tiny); };
+  auto fluid_row = [&](int y) { return INTERIOR || row_kind(y, ny, walls) == 0; };
+
   // ---- phase 1: own nodes (kept in registers) and the halo ring
   const int xg = x0 + tx;
-  const int xw = wrapi(xg, nx);
-  real f[RPT][9], g[RPT][5];
+  const int xw = wx(xg);
+  real f[RPT][9], g[RPT][5], dpdT[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int ey = HYW + ty + 4 * r;
-    const int yg = y0 + ty + 4 * r;
-    if (row_kind(yg, ny, walls) == 0) {
-      const int yw = walls ? yg : wrapi(yg, ny);
-      load_node(fs, gs, N, yw * nx + xw, f[r], g[r]);
-      node_macro_to_lds(L, HXW + tx, ey, p, f[r], g[r], err);
+    const int ey = HYW + ty + WAVES * r;
+    const int yg = y0 + ty + WAVES * r;
+    dpdT[r] = real(0);
+    if (fluid_row(yg)) {
+      load_node(fs, gs, N, (unsigned)(wy(yg) * nx + xw), f[r], g[r]);
+      dpdT[r] = node_macro_to_lds(L, HXW + tx, ey, p, f[r], g[r], err);
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[r][i] = real(0);
@@ -180,12 +187,10 @@ __global__ __launch_bounds__(NT) void step_kernel(const InstDesc<real>* __restri
     int ex, ey;
     ring_cell(r, ex, ey);
     const int yg = y0 - HYW + ey;
-    if (row_kind(yg, ny, walls) == 0) {
-      const int yw = walls ? yg : wrapi(yg, ny);
-      const int xr = wrapi(x0 - HXW + ex, nx);
+    if (fluid_row(yg)) {
       real fr[9], gr[5];
-      load_node(fs, gs, N, yw * nx + xr, fr, gr);
-      node_macro_to_lds(L, ex, ey, p, fr, gr, err);
+      load_node(fs, gs, N, (unsigned)(wy(yg) * nx + wx(x0 - HXW + ex)), fr, gr);
+      (void)node_macro_to_lds(L, ex, ey, p, fr, gr, err);
     } else {
       zero_lds_cell(L, ex, ey);
     }
@@ -193,7 +198,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const InstDesc<real>* __restri
   __syncthreads();
 
   // ---- phase 1b: wetting ghost rows, rho_0 = rho_2 + tan(pi/2 - theta) |rho_{x+1,1} - rho_{x-1,1}|
-  if (walls) {
+  if (!INTERIOR && walls) {
     const int eyb = -1 - (y0 - HYW);  // LDS row of y = -1
     const int eyt = ny - (y0 - HYW);  // LDS row of y = ny
     const bool hasb = eyb >= 0 && eyb < EYW, hast = eyt >= 0 && eyt < EYW;
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(NT) void step_kernel(const InstDesc<real>* __restri
           const int d = top ? -1 : 1;  // towards the fluid
           const real tanv = top ? p.tan_top : p.tan_bot;
           const real rg = L.rho[ey + 2 * d][ex] + tanv * fabs(L.rho[ey + d][ex + 1] - L.rho[ey + d][ex - 1]);
-          const real Tw = wall_temperature(p, top, wrapi(x0 - HXW + ex, nx));
+          const real Tw = wall_temperature(p, top, wx(x0 - HXW + ex));
           L.psi[ey][ex] = pseudo(p, rg, Tw, err);
         }
       }
@@ -215,24 +220,26 @@ __global__ __launch_bounds__(NT) void step_kernel(const InstDesc<real>* __restri
   }
 
   // ---- phase 2: forces and velocity on the tile plus one node
-  real Fx[RPT], Fy[RPT], Fm2[RPT];
+  real Fx[RPT], Fy[RPT], S2[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int ex = HXW + tx, ey = HYW + ty + 4 * r;
-    const int yg = y0 + ty + 4 * r;
-    Fx[r] = Fy[r] = Fm2[r] = real(0);
-    if (row_kind(yg, ny, walls) == 0) {
+    const int ex = HXW + tx, ey = HYW + ty + WAVES * r;
+    const int yg = y0 + ty + WAVES * r;
+    Fx[r] = Fy[r] = S2[r] = real(0);
+    if (fluid_row(yg)) {
       const real rho = L.rho[ey][ex];
-      real fx = real(0), fy = real(0), fmx = real(0), fmy = real(0);
+      real fx = real(0), fy = real(0);
       if (!freeze) {
-        interaction_force(L, ex, ey, p.G, fmx, fmy);
-        fx = fmx + (rho - p.rho_ave) * p.gx;
-        fy = fmy + (rho - p.rho_ave) * p.gy;
+        real sx, sy;
+        psi_stencil(L, ex, ey, sx, sy);
+        const real c = -p.G * L.psi[ey][ex];
+        fx = c * sx + (rho - p.rho_ave) * p.gx;
+        fy = c * sy + (rho - p.rho_ave) * p.gy;
+        S2[r] = p.G * p.G * (sx * sx + sy * sy);  // |F_m|^2 / psi^2 of Li's correction (Eq. 8)
       }
       Fx[r] = fx;
       Fy[r] = fy;
-      Fm2[r] = fmx * fmx + fmy * fmy;
-      const real ir = real(1) / rho;
+      const real ir = L.irc[ey][ex] * p.cv;  // 1/rho
       L.ux[ey][ex] = (L.ux[ey][ex] + real(0.5) * fx) * ir;
       L.uy[ey][ex] = (L.uy[ey][ex] + real(0.5) * fy) * ir;
     }
@@ -241,16 +248,17 @@ __global__ __launch_bounds__(NT) void step_kernel(const InstDesc<real>* __restri
     int ex, ey;
     uring_cell(r, ex, ey);
     const int yg = y0 - HYW + ey;
-    if (row_kind(yg, ny, walls) == 0) {
+    if (fluid_row(yg)) {
       const real rho = L.rho[ey][ex];
       real fx = real(0), fy = real(0);
       if (!freeze) {
-        real fmx, fmy;
-        interaction_force(L, ex, ey, p.G, fmx, fmy);
-        fx = fmx + (rho - p.rho_ave) * p.gx;
-        fy = fmy + (rho - p.rho_ave) * p.gy;
+        real sx, sy;
+        psi_stencil(L, ex, ey, sx, sy);
+        const real c = -p.G * L.psi[ey][ex];
+        fx = c * sx + (rho - p.rho_ave) * p.gx;
+        fy = c * sy + (rho - p.rho_ave) * p.gy;
       }
-      const real ir = real(1) / rho;
+      const real ir = L.irc[ey][ex] * p.cv;
       L.ux[ey][ex] = (L.ux[ey][ex] + real(0.5) * fx) * ir;
       L.uy[ey][ex] = (L.uy[ey][ex] + real(0.5) * fy) * ir;
     }
@@ -258,50 +266,46 @@ __global__ __launch_bounds__(NT) void step_kernel(const InstDesc<real>* __restri
   __syncthreads();
 
   // ---- phase 3: collision and streaming of the own nodes
-  const real cv = p.cv;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int ex = HXW + tx, ey = HYW + ty + 4 * r;
-    const int yg = y0 + ty + 4 * r;
-    if (xg >= nx || yg >= ny) continue;
+    const int ex = HXW + tx, ey = HYW + ty + WAVES * r;
+    const int yg = y0 + ty + WAVES * r;
+    if (!INTERIOR && (xg >= nx || yg >= ny)) continue;
     const real rho = L.rho[ey][ex];
     const real ux = L.ux[ey][ex], uy = L.uy[ey][ex];
     const real Tr = ((g[r][0] + g[r][1]) + (g[r][2] + g[r][3])) + g[r][4];  // T - T_ref
     const real T = p.T_ref + Tr;
-    const int o = yg * nx + xw;
+    const unsigned o = (unsigned)(yg * nx + xw);
 
     // div u = 3 sum_i w_i c_i . u(x + c_i); a ghost row carries -u of the fluid row next to it
-    real uxn[9], uyn[9];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-      const int cx = (i == 1 || i == 5 || i == 8) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
-      const int cy = (i == 2 || i == 5 || i == 6) ? 1 : ((i == 4 || i == 7 || i == 8) ? -1 : 0);
-      const bool ghost = walls && ((yg == 0 && cy < 0) || (yg == ny - 1 && cy > 0));
-      if (ghost) {
-        uxn[i] = -L.ux[ey][ex + cx];
-        uyn[i] = -L.uy[ey][ex + cx];
-      } else {
-        uxn[i] = L.ux[ey + cy][ex + cx];
-        uyn[i] = L.uy[ey + cy][ex + cx];
-      }
+    real divu;
+    {
+      const bool gs_ = walls && yg == 0, gn_ = walls && yg == ny - 1;
+      const real uxE = L.ux[ey][ex + 1], uxW = L.ux[ey][ex - 1];
+      const real uyN = gn_ ? -uy : L.uy[ey + 1][ex];
+      const real uyS = gs_ ? -uy : L.uy[ey - 1][ex];
+      const real uxNE = gn_ ? -uxE : L.ux[ey + 1][ex + 1], uyNE = gn_ ? -L.uy[ey][ex + 1] : L.uy[ey + 1][ex + 1];
+      const real uxNW = gn_ ? -uxW : L.ux[ey + 1][ex - 1], uyNW = gn_ ? -L.uy[ey][ex - 1] : L.uy[ey + 1][ex - 1];
+      const real uxSW = gs_ ? -uxW : L.ux[ey - 1][ex - 1], uySW = gs_ ? -L.uy[ey][ex - 1] : L.uy[ey - 1][ex - 1];
+      const real uxSE = gs_ ? -uxE : L.ux[ey - 1][ex + 1], uySE = gs_ ? -L.uy[ey][ex + 1] : L.uy[ey - 1][ex + 1];
+      divu = real(1.0 / 3.0) * ((uxE - uxW) + (uyN - uyS)) +
+             real(1.0 / 12.0) * (((uxNE - uxSW) + (uxSE - uxNW)) + ((uyNE - uySW) + (uyNW - uySE)));
     }
-    const real divu = real(1.0 / 3.0) * ((uxn[1] - uxn[3]) + (uyn[2] - uyn[4])) +
-                      real(1.0 / 12.0) * (((uxn[5] - uxn[7]) + (uxn[8] - uxn[6])) + ((uyn[5] - uyn[7]) + (uyn[6] - uyn[8])));
 
     // grad T from m_1, m_2 of the D2Q5 populations (Eqs. 49-50)
     const real dTx = -p.vs1 * (g[r][1] - g[r][3]) * p.inv_cs2h;
     const real dTy = -p.vs1 * (g[r][2] - g[r][4]) * p.inv_cs2h;
-    real press, dpdT;
-    pr_eos(p, rho, T, press, dpdT);
-    const real rcv = rho * cv;
-    const real Q = -(rcv * (ux * dTx + uy * dTy) + T * dpdT * divu);
+    const real rcv = rho * p.cv;
+    const real Q = -(rcv * (ux * dTx + uy * dTy) + T * dpdT[r] * divu);
     const real T1 = Th[o];
-    const real T2 = Th[N + o];
+    const real T2 = (Th + N)[o];
     const real Ssum = (p.flags & FL_NO_S) ? real(0) : rcv * real(0.5) * ((Tr - T1) - (T1 - T2));
     Th[o] = Tr;
-    Th[N + o] = T1;
+    (Th + N)[o] = T1;
 
-    // ---- D2Q9 MRT collision with Li's forcing, moments of the orthogonal basis of Eq. (4)
+    // ---- D2Q9 MRT collision with Li's forcing, moments of the orthogonal basis of Eq. (4).
+    // Applied as a correction f* = f + M^-1 dm with dm = -S (m - m_eq) + (1 - S/2) F (Eq. 5):
+    // dm_0 = 0, so mass is conserved to rounding (no product of rho with a rounded 1/9).
     real fs_[9];
     if (freeze) {
 #pragma unroll
@@ -310,48 +314,44 @@ __global__ __launch_bounds__(NT) void step_kernel(const InstDesc<real>* __restri
       const real* fi = f[r];
       const real sa = (fi[1] + fi[2]) + (fi[3] + fi[4]);
       const real sd = (fi[5] + fi[6]) + (fi[7] + fi[8]);
-      real m1 = -real(4) * fi[0] - sa + real(2) * sd;
-      real m2 = real(4) * fi[0] - real(2) * sa + sd;
-      const real jx = (fi[1] - fi[3]) + ((fi[5] - fi[6]) + (fi[8] - fi[7]));
-      const real jy = (fi[2] - fi[4]) + ((fi[5] + fi[6]) - (fi[7] + fi[8]));
-      real m4 = real(-2) * (fi[1] - fi[3]) + ((fi[5] - fi[6]) + (fi[8] - fi[7]));
-      real m6 = real(-2) * (fi[2] - fi[4]) + ((fi[5] + fi[6]) - (fi[7] + fi[8]));
-      real m7 = (fi[1] - fi[2]) + (fi[3] - fi[4]);
-      real m8 = (fi[5] - fi[6]) + (fi[7] - fi[8]);
+      const real m1 = -real(4) * fi[0] - sa + real(2) * sd;
+      const real m2 = real(4) * fi[0] - real(2) * sa + sd;
+      const real m4 = real(-2) * (fi[1] - fi[3]) + ((fi[5] - fi[6]) + (fi[8] - fi[7]));
+      const real m6 = real(-2) * (fi[2] - fi[4]) + ((fi[5] + fi[6]) - (fi[7] + fi[8]));
+      const real m7 = (fi[1] - fi[2]) + (fi[3] - fi[4]);
+      const real m8 = (fi[5] - fi[6]) + (fi[7] - fi[8]);
       const real uu = ux * ux + uy * uy;
       const real fx = Fx[r], fy = Fy[r];
       const real uF = ux * fx + uy * fy;
-      const real corr = Fm2[r] / (L.psi[ey][ex] * L.psi[ey][ex]);
-      const real F1 = real(6) * uF + p.corr_e * corr;
-      const real F2 = -real(6) * uF - p.corr_eps * corr;
+      const real F1 = real(6) * uF + p.corr_e * S2[r];
+      const real F2 = -real(6) * uF - p.corr_eps * S2[r];
       const real F7 = real(2) * (ux * fx - uy * fy);
       const real F8 = ux * fy + uy * fx;
-      // m* = m - S (m - m_eq) + (1 - S/2) F  (Eq. 5), m_eq of Eq. (7)
-      m1 = m1 - p.s_e * (m1 - rho * (real(-2) + real(3) * uu)) + (real(1) - real(0.5) * p.s_e) * F1;
-      m2 = m2 - p.s_eps * (m2 - rho * (real(1) - real(3) * uu)) + (real(1) - real(0.5) * p.s_eps) * F2;
-      const real m3 = jx + fx;  // conserved moment: jx - s_j (jx - rho ux) + (1 - s_j/2) Fx = jx + Fx
-      m4 = m4 - p.s_q * (m4 + rho * ux) + (real(1) - real(0.5) * p.s_q) * (-fx);
-      const real m5 = jy + fy;
-      m6 = m6 - p.s_q * (m6 + rho * uy) + (real(1) - real(0.5) * p.s_q) * (-fy);
-      m7 = m7 - p.s_p * (m7 - rho * (ux * ux - uy * uy)) + (real(1) - real(0.5) * p.s_p) * F7;
-      m8 = m8 - p.s_p * (m8 - rho * ux * uy) + (real(1) - real(0.5) * p.s_p) * F8;
-      // f* = M^-1 m* with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-      const real a0 = rho * real(1.0 / 9.0);
-      const real b1 = m1 * real(1.0 / 36.0), b2 = m2 * real(1.0 / 36.0);
-      const real c3 = m3 * real(1.0 / 6.0), c4 = m4 * real(1.0 / 12.0);
-      const real c5 = m5 * real(1.0 / 6.0), c6 = m6 * real(1.0 / 12.0);
-      const real d7 = m7 * real(0.25), d8 = m8 * real(0.25);
-      const real axis = a0 - b1 - real(2) * b2;
-      const real diag = a0 + real(2) * b1 + b2;
-      fs_[0] = a0 - real(4) * b1 + real(4) * b2;
-      fs_[1] = axis + (c3 - real(2) * c4) + d7;
-      fs_[2] = axis + (c5 - real(2) * c6) - d7;
-      fs_[3] = axis - (c3 - real(2) * c4) + d7;
-      fs_[4] = axis - (c5 - real(2) * c6) - d7;
-      fs_[5] = diag + (c3 + c4) + (c5 + c6) + d8;
-      fs_[6] = diag - (c3 + c4) + (c5 + c6) - d8;
-      fs_[7] = diag - (c3 + c4) - (c5 + c6) + d8;
-      fs_[8] = diag + (c3 + c4) - (c5 + c6) - d8;
+      // m_eq of Eq. (7); the conserved moments j change by exactly F (s_j drops out)
+      const real d1 = -p.s_e * (m1 - rho * (real(-2) + real(3) * uu)) + (real(1) - real(0.5) * p.s_e) * F1;
+      const real d2 = -p.s_eps * (m2 - rho * (real(1) - real(3) * uu)) + (real(1) - real(0.5) * p.s_eps) * F2;
+      const real d4 = -p.s_q * (m4 + rho * ux) - (real(1) - real(0.5) * p.s_q) * fx;
+      const real d6 = -p.s_q * (m6 + rho * uy) - (real(1) - real(0.5) * p.s_q) * fy;
+      const real d7 = -p.s_p * (m7 - rho * (ux * ux - uy * uy)) + (real(1) - real(0.5) * p.s_p) * F7;
+      const real d8 = -p.s_p * (m8 - rho * ux * uy) + (real(1) - real(0.5) * p.s_p) * F8;
+      // M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+      const real b1 = d1 * real(1.0 / 36.0), b2 = d2 * real(1.0 / 36.0);
+      const real c3 = fx * real(1.0 / 6.0), c4 = d4 * real(1.0 / 12.0);
+      const real c5 = fy * real(1.0 / 6.0), c6 = d6 * real(1.0 / 12.0);
+      const real e7 = d7 * real(0.25), e8 = d8 * real(0.25);
+      const real axis = -b1 - real(2) * b2;
+      const real diag = real(2) * b1 + b2;
+      const real cx_ = c3 - real(2) * c4, cy_ = c5 - real(2) * c6;
+      const real dx_ = c3 + c4, dy_ = c5 + c6;
+      fs_[0] = fi[0] + (real(4) * (b2 - b1));
+      fs_[1] = fi[1] + ((axis + cx_) + e7);
+      fs_[2] = fi[2] + ((axis + cy_) - e7);
+      fs_[3] = fi[3] + ((axis - cx_) + e7);
+      fs_[4] = fi[4] + ((axis - cy_) - e7);
+      fs_[5] = fi[5] + ((diag + (dx_ + dy_)) + e8);
+      fs_[6] = fi[6] + ((diag - (dx_ - dy_)) - e8);
+      fs_[7] = fi[7] + ((diag - (dx_ + dy_)) + e8);
+      fs_[8] = fi[8] + ((diag + (dx_ - dy_)) - e8);
     }
 
     // ---- D2Q5 MRT collision (Eq. 39) with the non-orthogonal basis of Eq. (40)
@@ -371,73 +371,140 @@ __global__ __launch_bounds__(NT) void step_kernel(const InstDesc<real>* __restri
       gs_[4] = gi[4] - (q34m - real(0.5) * dm2) + p.w1h * src;
     }
 
-    // ---- streaming of f: push to x + c_i, halfway bounce-back through the walls
-    {
-      const int xe = wrapi(xg + 1, nx), xwst = wrapi(xg - 1, nx);
-      const bool wall_n = walls && yg == ny - 1, wall_s = walls && yg == 0;
-      const int yn = walls ? yg + 1 : wrapi(yg + 1, ny);
-      const int ys = walls ? yg - 1 : wrapi(yg - 1, ny);
-      real* fd0 = fd;
-      if (freeze) {
+    // ---- streaming: offsets of the eight neighbours (wrapped; a wall row is never written)
+    const bool wall_n = walls && yg == ny - 1, wall_s = walls && yg == 0;
+    const unsigned cE = (unsigned)wx(xg + 1), cW = (unsigned)wx(xg - 1);
+    const unsigned rowc = (unsigned)(yg * nx);
+    const unsigned rown = wall_n ? 0u : (unsigned)(wy(yg + 1) * nx);
+    const unsigned rows = wall_s ? 0u : (unsigned)(wy(yg - 1) * nx);
+
+    // f: push to x + c_i, halfway bounce-back through the walls (Eq. 6)
+    if (freeze) {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) fd0[i * N + o] = fs_[i];
+      for (int i = 0; i < 9; ++i) (fd + i * N)[o] = fs_[i];
+    } else {
+      fd[o] = fs_[0];
+      (fd + 1 * N)[rowc + cE] = fs_[1];
+      (fd + 3 * N)[rowc + cW] = fs_[3];
+      if (wall_n) {
+        (fd + 4 * N)[o] = fs_[2];
+        (fd + 7 * N)[o] = fs_[5];
+        (fd + 8 * N)[o] = fs_[6];
       } else {
-        fd0[o] = fs_[0];
-        fd0[1 * N + yg * nx + xe] = fs_[1];
-        fd0[3 * N + yg * nx + xwst] = fs_[3];
-        if (wall_n) {
-          fd0[4 * N + o] = fs_[2];
-          fd0[7 * N + o] = fs_[5];
-          fd0[8 * N + o] = fs_[6];
-        } else {
-          fd0[2 * N + yn * nx + xw] = fs_[2];
-          fd0[5 * N + yn * nx + xe] = fs_[5];
-          fd0[6 * N + yn * nx + xwst] = fs_[6];
-        }
-        if (wall_s) {
-          fd0[2 * N + o] = fs_[4];
-          fd0[5 * N + o] = fs_[7];
-          fd0[6 * N + o] = fs_[8];
-        } else {
-          fd0[4 * N + ys * nx + xw] = fs_[4];
-          fd0[7 * N + ys * nx + xwst] = fs_[7];
-          fd0[8 * N + ys * nx + xe] = fs_[8];
-        }
+        (fd + 2 * N)[rown + xw] = fs_[2];
+        (fd + 5 * N)[rown + cE] = fs_[5];
+        (fd + 6 * N)[rown + cW] = fs_[6];
+      }
+      if (wall_s) {
+        (fd + 2 * N)[o] = fs_[4];
+        (fd + 5 * N)[o] = fs_[7];
+        (fd + 6 * N)[o] = fs_[8];
+      } else {
+        (fd + 4 * N)[rows + xw] = fs_[4];
+        (fd + 7 * N)[rows + cW] = fs_[7];
+        (fd + 8 * N)[rows + cE] = fs_[8];
       }
     }
 
-    // ---- streaming of g with the modified collision of Eq. (39):
-    //      g_i(y, t+1) = g_i(y, t) + [g*_i(y - c_i) - g_i(y, t)] / (rho(y, t) c_v)
+    // g with the modified collision of Eq. (39):
+    //   g_i(y, t+1) = g_i(y, t) + [g*_i(y - c_i) - g_i(y, t)] / (rho(y, t) c_v)
+    // An edge with a Dirichlet temperature replaces the upstream term by anti-bounce-back,
+    // -g*_i(y) + 2 what_i T_w, for the population entering y in the opposite direction.
     {
-      const real ircv = real(1) / rcv;
+      const real ircv = L.irc[ey][ex];
       gd[o] = g[r][0] + (gs_[0] - g[r][0]) * ircv;
-      const int hxs[5] = {0, 1, 0, -1, 0};
-      const int hys[5] = {0, 0, 1, 0, -1};
-#pragma unroll
-      for (int i = 1; i < 5; ++i) {
-        const int xd = xg + hxs[i], yd = yg + hys[i];
-        const bool out_y = (walls || p.thermal_box) && (yd < 0 || yd >= ny);
-        const bool out_x = p.thermal_box && (xd < 0 || xd >= nx);
-        const int io = i <= 2 ? i + 2 : i - 2;  // opposite direction
-        if (out_x || out_y) {
-          // anti-bounce-back: the population entering this node in direction io
-          const real Tw = p.thermal_box ? p.T_box : wall_temperature(p, yd < 0 ? 0 : 1, xw);
-          const real up = -gs_[i] + real(2) * p.w1h * (Tw - p.T_ref);
-          const real gold = g[r][io];
-          gd[io * N + o] = gold + (up - gold) * ircv;
-        } else {
-          const int exd = ex + hxs[i], eyd = ey + hys[i];
-          const real gold = L.g[i - 1][eyd][exd];
-          const real rd = L.rho[eyd][exd] * cv;
-          const int od = (walls ? yd : wrapi(yd, ny)) * nx + wrapi(xd, nx);
-          gd[i * N + od] = gold + (gs_[i] - gold) / rd;
-        }
+      const bool out_e = tb && xg == nx - 1, out_w = tb && xg == 0;
+      const bool out_n = (walls || tb) && yg == ny - 1, out_s = (walls || tb) && yg == 0;
+      const real two_w = real(2) * p.w1h;
+      if (out_e) {
+        const real up = -gs_[1] + two_w * (p.T_box - p.T_ref);
+        (gd + 3 * N)[o] = g[r][3] + (up - g[r][3]) * ircv;
+      } else {
+        const real gold = L.g[0][ey][ex + 1];
+        (gd + 1 * N)[rowc + cE] = gold + (gs_[1] - gold) * L.irc[ey][ex + 1];
+      }
+      if (out_w) {
+        const real up = -gs_[3] + two_w * (p.T_box - p.T_ref);
+        (gd + 1 * N)[o] = g[r][1] + (up - g[r][1]) * ircv;
+      } else {
+        const real gold = L.g[2][ey][ex - 1];
+        (gd + 3 * N)[rowc + cW] = gold + (gs_[3] - gold) * L.irc[ey][ex - 1];
+      }
+      if (out_n) {
+        const real Tn = tb ? p.T_box : p.T_top;
+        const real up = -gs_[2] + two_w * (Tn - p.T_ref);
+        (gd + 4 * N)[o] = g[r][4] + (up - g[r][4]) * ircv;
+      } else {
+        const real gold = L.g[1][ey + 1][ex];
+        (gd + 2 * N)[rown + xw] = gold + (gs_[2] - gold) * L.irc[ey + 1][ex];
+      }
+      if (out_s) {
+        const real Ts = tb ? p.T_box : wall_temperature(p, 0, xw);
+        const real up = -gs_[4] + two_w * (Ts - p.T_ref);
+        (gd + 2 * N)[o] = g[r][2] + (up - g[r][2]) * ircv;
+      } else {
+        const real gold = L.g[3][ey - 1][ex];
+        (gd + 4 * N)[rows + xw] = gold + (gs_[4] - gold) * L.irc[ey - 1][ex];
       }
     }
   }
 
   if (err) atomicOr(D.err, err);
 }
+
+template <typename real, int WAVES, int MINW>
+__global__ __launch_bounds__(64 * WAVES, MINW) void step_kernel(const InstDesc<real>* __restrict__ table, int ninst,
+                                                                const long long* __restrict__ clock, int k) {
+  // ---- which simulation and which tile (uniform per workgroup).  Workgroups are dispatched to
+  // the 8 XCDs round-robin; remap so that each XCD takes a contiguous range of tiles: neighbouring
+  // tiles then share one L2, where their halo reads hit and where the partial cache lines of the
+  // shifted (pushed) stores of two neighbours are merged before they are written back.
+  const int nwg = gridDim.x;
+  const int xcd = blockIdx.x % NXCD;
+  const int per = nwg / NXCD, rem = nwg % NXCD;
+  const int bid = xcd * per + (xcd < rem ? xcd : rem) + blockIdx.x / NXCD;
+  int lo = 0, hi = ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (table[mid].tile_begin <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  const InstDesc<real>& D = table[lo];
+  const long long t = *clock + k;
+  if (t < D.t_start || t >= D.t_end) return;
+  const int tile = bid - D.tile_begin;
+  if (tile < 0 || tile >= D.ntx * D.nty) return;
+  const int by = tile / D.ntx;
+  const int bx = tile - by * D.ntx;
+  const int x0 = bx * TX, y0 = by * TY;
+  __shared__ StepLds<real> L;
+  // interior: the load region [x0-HXW, x0+TX+HXW) x [y0-HYW, y0+TY+HYW) lies inside the grid,
+  // so no wrap, ghost row, wall or Dirichlet edge is involved
+  const bool interior = x0 >= HXW && x0 + TX + HXW <= D.nx && y0 >= HYW && y0 + TY + HYW <= D.ny;
+  if (interior) step_tile<real, WAVES, true>(D, L, t, x0, y0);
+  else step_tile<real, WAVES, false>(D, L, t, x0, y0);
+}
+
+// Workgroup shapes (wavefronts per workgroup, minimum resident wavefronts per SIMD that the
+// register allocation must allow).
+#ifndef LBM_F32_WAVES
+#define LBM_F32_WAVES 16
+#endif
+#ifndef LBM_F32_MINW
+#define LBM_F32_MINW 1
+#endif
+template <typename real>
+struct StepShape;
+template <>
+struct StepShape<float> {
+  static constexpr int WAVES = LBM_F32_WAVES;
+  static constexpr int MINW = LBM_F32_MINW;
+};
+template <>
+struct StepShape<double> {
+  static constexpr int WAVES = 8;
+  static constexpr int MINW = 1;
+};
 
 // Clock advance after a group of step launches (a kernel, so that it can live in a graph).
 __global__ void clock_advance_kernel(long long* clock, long long n) {
