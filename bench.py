@@ -25,7 +25,10 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (D2Q9+D2Q5 node updates/s) & % HBM roofline; batched vs plain; p50/p99"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = {"f32": 128, "f64": 256}  # f 9+9, g 5+5, history 2+2 values per node update
-TRAFFIC = None  # measured HBM bytes per launch from rocprofv3 counters (profiles/), or None
+# HBM bytes per launch of the step kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
+# scaled by the same counters read for a plain copy of known size (profiles/); keyed by grid size,
+# None where no measurement of the current kernel exists
+TRAFFIC = {(512, 512): 35257214}
 
 
 def build_workload(nx=512, ny=512, steps=20000):
@@ -60,7 +63,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--ny", type=int, default=512)
-    ap.add_argument("--cpu-steps", type=int, default=400)
+    ap.add_argument("--cpu-steps", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="before the timed region, copy this many MiB device-to-device once (a plain copy "
@@ -141,7 +144,7 @@ def main():
                    "nx": args.nx, "ny": args.ny, "precision": "fp32", "kernel": "fused D2Q9+D2Q5 step",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((args.nx, args.ny)),
                      "bytes_per_launch": bytes_per_launch, "kernel_ms_timed_region": round(ms_per_step, 6),
                      "kernel_ms_single_launch_p50": round(launch_p50, 6)},
         "wall_s": round(wall, 4),
