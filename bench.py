@@ -10,6 +10,8 @@ Prints one JSON line: MLUPS over the timed steps, the roofline of the step kerne
 the library's stream), and the FP64 CPU oracle timed on a bounded sample of the same workload.
 
   python bench.py [--gpus 1] [--steps 20000] [--warmup 500] [--no-cpu-baseline]
+  python bench.py --mode batch [--instances 64 --steps 2000]     batched gravity sweep vs plain
+  python bench.py --mode serve [--requests 256 --rate 20]        continuous batching vs FIFO
 """
 from __future__ import annotations
 
@@ -56,10 +58,135 @@ def cpu_baseline(w, steps):
                       f"({dt:.1f} s)"}
 
 
+def sweep_workloads(n, steps, lbm):
+    """The batched gravity sweep: boiling instances on grids of three sizes, gravity log-uniform in
+    [5e-6, 5e-5], hot-spot dT uniform in [0.1, 0.3] Tc (workloads.gravity_sweep, seed 2).  The pool
+    is half full unless the vapour head of that pool would exceed p_sat / 2; then it is filled
+    further (workloads.head_limited_fill), which keeps every instance inside the model's stable
+    range for the whole run."""
+    from workloads import Params, boiling, gravity_sweep, head_limited_fill
+
+    base = Params()
+    Tc = lbm.critical_temperature(base)
+    rl, rg, ps = lbm.coexistence(base, 0.86 * Tc)
+    out = []
+    for spec in gravity_sweep(n=n, steps=steps):
+        fill = head_limited_fill(rl, rg, ps, spec["gravity"], spec["ny"])
+        out.append(boiling(Tc, rl, rg, nx=spec["nx"], ny=spec["ny"], gravity=spec["gravity"],
+                           dT_rel=spec["dT_rel"], seed=spec["seed"], steps=steps, fill=fill))
+    return out
+
+
+def run_batch_mode(args):
+    """Batched (one launch per step over all instances, graph-replayed) against sequential plain runs."""
+    import torch
+
+    import paper_2205_00686_amd as lbm
+
+    ws = sweep_workloads(args.instances, args.steps, lbm)
+    nodes = sum(w.nodes for w in ws)
+    print(f"[bench] batch of {len(ws)} boiling instances, {nodes} nodes, {args.steps} steps", file=sys.stderr,
+          flush=True)
+    # plain: one simulation after the other
+    solvers = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for w in ws]
+    stream = solvers[0].stream
+    for s in solvers:
+        s.step(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for s in solvers:
+        s.step(args.steps)
+    e1.record(stream)
+    e1.synchronize()
+    for s in solvers:
+        s.sync()
+    plain_ms = e0.elapsed_time(e1)
+    plain_state = [s.save_state() for s in solvers[:4]]
+    for s in solvers:
+        s.close()
+    # batched
+    solvers = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for w in ws]
+    b = lbm.Batch(solvers)
+    for i in range(len(solvers)):
+        b.set_budget(i, args.warmup)
+    b.step(args.warmup)
+    b.sync()
+    for i in range(len(solvers)):
+        b.set_budget(i, args.steps)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.step(args.steps)
+    e1.record(stream)
+    e1.synchronize()
+    st = b.sync()
+    batch_ms = e0.elapsed_time(e1)
+    same = all(s.save_state() == p for s, p in zip(solvers[:4], plain_state))
+    lu = nodes * args.steps
+    out = {"metric": METRIC, "mode": "batched vs plain", "unit": "MLUPS", "n_gpus": 1, "dtype": "f32",
+           "config": {"workload": f"gravity sweep: {len(ws)} boiling instances on 256x512/384x768/512x1024 grids, "
+                                  f"g log-uniform [5e-6, 5e-5], dT uniform [0.1, 0.3] Tc, pool fill 0.5 or head-limited",
+                      "instances": len(ws), "nodes": nodes, "steps": args.steps, "warmup": args.warmup},
+           "batched_mlups": round(lu / (batch_ms * 1e-3) / 1e6, 1),
+           "plain_sequential_mlups": round(lu / (plain_ms * 1e-3) / 1e6, 1),
+           "speedup": round(plain_ms / batch_ms, 3),
+           "batched_roofline_frac": round(lu * 128 / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "batched_equals_plain_bitwise_first4": same, "failed_instances": sum(1 for x in st if x != 0)}
+    print(json.dumps(out), flush=True)
+
+
+def run_serve_mode(args):
+    """Continuous batching of a Poisson request stream against one-at-a-time FIFO service."""
+    import paper_2205_00686_amd as lbm
+    from paper_2205_00686_amd import serve
+    from workloads import Params, boiling, droplet, evaporation, head_limited_fill, request_stream
+
+    base = Params()
+    Tc = lbm.critical_temperature(base)
+    rl, rg, ps = lbm.coexistence(base, 0.86 * Tc)
+
+    def make(spec):
+        nx, ny, seed = spec["nx"], spec["ny"], spec["seed"]
+        if spec["kind"] == "droplet":
+            return lambda: droplet(Tc, rl, rg, nx=nx, ny=ny, R=min(nx, ny) / 4.0)
+        if spec["kind"] == "evaporation":
+            return lambda: evaporation(Tc, rl, rg, nx=nx, ny=ny, R=min(nx, ny) / 8.0)
+        fill = head_limited_fill(rl, rg, ps, 2e-5, ny)
+        return lambda: boiling(Tc, rl, rg, nx=nx, ny=ny, seed=seed, fill=fill)
+
+    specs = request_stream(n=args.requests, rate=args.rate, steps_range=(args.min_steps, args.max_steps))
+    mk = lambda: [serve.Request(rid=sp["id"], arrival=sp["arrival"], steps=sp["steps"], make=make(sp),  # noqa: E731
+                                meta={"kind": sp["kind"], "nx": sp["nx"], "ny": sp["ny"]}) for sp in specs]
+    print(f"[bench] serve {args.requests} requests at {args.rate}/s, budget {args.hbm_budget_gb} GB, "
+          f"{args.slots} slots", file=sys.stderr, flush=True)
+    server = serve.Server(hbm_budget=int(args.hbm_budget_gb * 2**30), max_slots=args.slots, chunk=args.chunk,
+                          keep_results=False)
+    _, served = server.run(mk())
+    print(f"[bench] served: {json.dumps(served)}", file=sys.stderr, flush=True)
+    _, base_line = serve.fifo(mk(), keep_results=False)
+    out = {"metric": METRIC, "mode": "served (continuous batching) vs FIFO plain", "unit": "MLUPS", "n_gpus": 1,
+           "dtype": "f32",
+           "config": {"workload": f"Poisson stream of {args.requests} mixed droplet/evaporation/boiling requests at "
+                                  f"{args.rate} req/s, grids log-uniform 128x128..1024x2048, steps uniform "
+                                  f"[{args.min_steps}, {args.max_steps}]",
+                      "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "chunk": args.chunk},
+           "served": served, "fifo": base_line}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--mode", choices=["plain", "batch", "serve"], default="plain")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--min-steps", type=int, default=1000)
+    ap.add_argument("--max-steps", type=int, default=20000)
+    ap.add_argument("--hbm-budget-gb", type=float, default=8.0)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--chunk", type=int, default=512)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20000; 10000 with --mode batch)")
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--ny", type=int, default=512)
@@ -73,6 +200,12 @@ def main():
         print(f"bench.py measures one GPU: the library runs each simulation on a single device "
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
+    if args.steps is None:
+        args.steps = 10000 if args.mode == "batch" else 20000
+    if args.mode == "batch":
+        return run_batch_mode(args)
+    if args.mode == "serve":
+        return run_serve_mode(args)
 
     import torch
 

@@ -161,10 +161,11 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
                             lbm_batch** out);
 
 /* Give instance i a budget of `steps` more steps (0 parks it).  Takes effect at the next
-   lbm_batch_step. */
+   lbm_batch_step.  LBM_E_STATE for an instance that has failed. */
 lbm_status lbm_batch_set_budget(lbm_batch* b, int i, int64_t steps);
 
-/* Advance every instance with budget left by up to k steps (each stops at its own budget). */
+/* Advance every instance with budget left by up to k steps (each stops at its own budget).
+   An instance whose failure lbm_batch_sync has reported stays parked; the others go on. */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t k);
 
 /* Steps still budgeted for instance i. */

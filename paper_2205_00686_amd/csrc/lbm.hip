@@ -88,7 +88,7 @@ struct lbm_batch {
   int total_tiles = 0;
   bool table_dirty = true;
   hipGraphExec_t graph = nullptr;
-  int graph_steps = 0;
+  std::vector<lbm_ctx*> graph_layout;  // active instances (in table order) the graph was captured for
 };
 
 // ------------------------------------------------------------------------------ helpers
@@ -745,10 +745,16 @@ static lbm_status batch_upload(lbm_batch* b) {
     HIP_OR_FAIL(h0, hipMemcpyAsync(b->d_clock, &c, sizeof(c), hipMemcpyHostToDevice, b->stream));
     HIP_OR_FAIL(h0, hipStreamSynchronize(b->stream));
   }
-  if (b->graph) {
+  // the captured launches depend only on the table address, the instance count and the grid size
+  // (total tiles of the active instances in table order); keep the graph while these are unchanged
+  std::vector<lbm_ctx*> layout;
+  for (size_t i = 0; i < n; ++i)
+    if (b->remaining[i] > 0) layout.push_back(b->ctx[i]);
+  if (b->graph && layout != b->graph_layout) {
     (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
   }
+  b->graph_layout = layout;
   b->table_dirty = false;
   return LBM_OK;
 }
@@ -772,8 +778,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
   if (!b || k < 0) return LBM_E_INVAL;
   if (k == 0) return LBM_OK;
   lbm_ctx* h0 = b->ctx[0];
-  for (lbm_ctx* h : b->ctx)
-    if (h->failed) return LBM_E_STATE;
+  // a member that failed was parked by lbm_batch_sync (budget 0): the others go on
   if (b->table_dirty) {
     lbm_status s = batch_upload(b);
     if (s != LBM_OK) return s;

@@ -1,0 +1,200 @@
+"""Continuous-batching server for phase-change solves.
+
+Requests (a workload: parameters, initial fields, step count) arrive over time.  The server admits
+a queued request as soon as a slot is free and its device footprint (lbm_footprint_bytes) fits in
+the HBM budget next to the running ones; its state then stays on the device until it finishes.
+All running simulations advance together, `chunk` steps at a time, in one batched kernel launch
+per step (graph-replayed), each stopping at its own step count; between chunks finished requests
+are read back and retired and newly arrived ones join.  A request's result is bit-identical to
+running it alone (the batched launch executes the same kernel on every node).
+
+`fifo()` is the baseline: one request at a time, in arrival order, each with its own plain
+lbm_step launches.
+"""
+from __future__ import annotations
+
+import concurrent.futures as cf
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import LBM_FP32, Batch, Solver, footprint_bytes
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float           # seconds after the start of the run
+    steps: int
+    make: object             # callable returning a workloads.Workload (initial fields built on demand)
+    nodes: int = 0
+    footprint: int = 0
+    t_arrive: float = float("nan")   # when the request counts as arrived (its arrival, or 0 without realtime)
+    t_admit: float = float("nan")
+    t_done: float = float("nan")
+    result: tuple = None
+    error: str = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.t_arrive
+
+
+def _percentile(v, q):
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else float("nan")
+
+
+def summarize(reqs, t0, t1):
+    done = [r for r in reqs if r.error is None and r.t_done == r.t_done]
+    lat = [r.latency for r in done]
+    lu = sum(r.nodes * r.steps for r in done)
+    span = t1 - t0
+    return {"requests": len(reqs), "completed": len(done), "failed": sum(r.error is not None for r in reqs),
+            "latency_p50_s": _percentile(lat, 50), "latency_p99_s": _percentile(lat, 99),
+            "latency_mean_s": float(np.mean(lat)) if lat else float("nan"),
+            "makespan_s": span, "node_updates": lu, "aggregate_mlups": lu / span / 1e6 if span > 0 else 0.0}
+
+
+class Server:
+    def __init__(self, hbm_budget: int, max_slots: int = 64, chunk: int = 512, precision: int = LBM_FP32,
+                 keep_results: bool = True, prepare_workers: int = 4):
+        self.hbm_budget = int(hbm_budget)
+        self.max_slots = int(max_slots)
+        self.chunk = int(chunk)
+        self.precision = precision
+        self.keep_results = keep_results
+        self.pool = cf.ThreadPoolExecutor(max_workers=prepare_workers)
+
+    def run(self, requests, realtime: bool = True, log=None):
+        """Serve `requests` (sorted by arrival).  With realtime=False every request is considered
+        arrived at t=0 (pure throughput run).  Returns (requests, summary)."""
+        import torch
+
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        arriving = deque(reqs)
+        queued = deque()
+        prep = {}
+        active = {}        # rid -> (request, solver)
+        remaining = {}
+        batch, members = None, ()
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0  # noqa: E731
+        used = 0
+        while arriving or queued or active:
+            # arrivals: start building their initial fields
+            while arriving and (not realtime or arriving[0].arrival <= now()):
+                r = arriving.popleft()
+                r.t_arrive = r.arrival if realtime else 0.0
+                prep[r.rid] = self.pool.submit(r.make)
+                queued.append(r)
+            # admission in arrival order while a slot is free and the footprint fits
+            while queued and len(active) < self.max_slots:
+                r = queued[0]
+                fut = prep[r.rid]
+                if not fut.done():
+                    break
+                w = fut.result()
+                need = footprint_bytes(w.params, self.precision)
+                if used + need > self.hbm_budget:
+                    if not active and need > self.hbm_budget:
+                        queued.popleft()
+                        r.error = "footprint exceeds the HBM budget"
+                        r.t_done = now()
+                        continue
+                    break
+                queued.popleft()
+                del prep[r.rid]
+                try:
+                    s = Solver(w.params, precision=self.precision).init(w.rho, w.ux, w.uy, w.T)
+                except Exception as e:  # noqa: BLE001 -- a bad request must not stop the others
+                    r.error = str(e)
+                    r.t_done = now()
+                    continue
+                r.nodes, r.footprint, r.t_admit = w.nodes, need, now()
+                used += need
+                active[r.rid] = (r, s)
+                remaining[r.rid] = r.steps
+            if not active:
+                # idle: wait for the next arrival or a field preparation
+                if queued:
+                    cf.wait([prep[queued[0].rid]], timeout=0.05)
+                elif arriving and realtime:
+                    time.sleep(max(0.0, min(0.05, arriving[0].arrival - now())))
+                continue
+            ids = tuple(sorted(active))
+            if ids != members:
+                if batch is not None:
+                    batch.close()
+                batch = Batch([active[i][1] for i in ids])
+                members = ids
+            for j, i in enumerate(ids):
+                batch.set_budget(j, min(self.chunk, remaining[i]))
+            batch.step(self.chunk)
+            status = batch.sync()
+            for j, i in enumerate(ids):
+                r, s = active[i]
+                remaining[i] -= min(self.chunk, remaining[i])
+                if status[j] != 0:
+                    r.error = "numerical failure"
+                if remaining[i] == 0 or r.error is not None:
+                    if r.error is None:
+                        fields = s.fields()
+                        if self.keep_results:
+                            r.result = fields
+                    r.t_done = now()
+                    used -= r.footprint
+                    s.close()
+                    del active[i], remaining[i]
+                    if log:
+                        log(r)
+        if batch is not None:
+            batch.close()
+        torch.cuda.synchronize()
+        return reqs, summarize(reqs, 0.0, now())
+
+
+def fifo(requests, precision: int = LBM_FP32, realtime: bool = True, keep_results: bool = True, log=None,
+         prepare_workers: int = 4):
+    """Baseline: one request at a time in arrival order, plain lbm_step launches.  Initial fields
+    of requests that have arrived are prepared in the background meanwhile, as in Server.run."""
+    import torch
+
+    reqs = sorted(requests, key=lambda r: r.arrival)
+    pool = cf.ThreadPoolExecutor(max_workers=prepare_workers)
+    t0 = time.perf_counter()
+    now = lambda: time.perf_counter() - t0  # noqa: E731
+    futs = {}
+
+    def submit_arrived():
+        for q in reqs:
+            if q.rid not in futs and (not realtime or q.arrival <= now()):
+                futs[q.rid] = pool.submit(q.make)
+
+    for r in reqs:
+        r.t_arrive = r.arrival if realtime else 0.0
+    for r in reqs:
+        while realtime and r.arrival > now():
+            time.sleep(min(0.05, r.arrival - now()))
+        submit_arrived()
+        w = futs[r.rid].result()
+        r.t_admit = now()
+        try:
+            s = Solver(w.params, precision=precision).init(w.rho, w.ux, w.uy, w.T)
+            r.nodes = w.nodes
+            s.step(r.steps)
+            fields = s.fields()
+            if keep_results:
+                r.result = fields
+            s.close()
+        except Exception as e:  # noqa: BLE001 -- a bad request must not stop the others
+            r.error = str(e)
+        futs[r.rid] = None
+        r.t_done = now()
+        submit_arrived()
+        if log:
+            log(r)
+    torch.cuda.synchronize()
+    return reqs, summarize(reqs, 0.0, now())

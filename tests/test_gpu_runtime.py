@@ -134,6 +134,40 @@ def test_nan_population_is_reported(lbm, sat_gpu):
     t.sync()
 
 
+def test_batch_member_failure_parks_only_that_member(lbm, sat_gpu):
+    Tc, rl, rg = sat_gpu
+    print("\n[case] batch with a poisoned member", flush=True)
+    ws = [droplet(Tc, rl, rg, nx=64, ny=48, R=10.0), evaporation(Tc, rl, rg, nx=70, ny=66, R=12.0),
+          droplet(Tc, rl, rg, nx=96, ny=40, R=9.0)]
+    alone = []
+    for w in ws:
+        s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+        s.step(150)
+        alone.append(s.save_state())
+        s.close()
+    sol = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for w in ws]
+    # poison member 1: rho = 9.5 lies beyond the EOS limit, flagged on its first step
+    rho = ws[1].rho.copy()
+    rho[30, 30] = 9.5
+    sol[1] = lbm.Solver(ws[1].params).init(rho, ws[1].ux, ws[1].uy, ws[1].T)
+    b = lbm.Batch(sol)
+    for i in range(3):
+        b.set_budget(i, 150)
+    b.step(70)
+    st = b.sync()
+    assert st == [0, -4, 0]
+    assert b.remaining(1) == 0
+    with pytest.raises(lbm.LbmError) as e:
+        b.set_budget(1, 10)
+    assert e.value.status == -5
+    b.step(80)
+    assert b.sync() == [0, -4, 0]
+    b.close()
+    for i in (0, 2):
+        assert sol[i].steps == 150
+        assert sol[i].save_state() == alone[i]
+
+
 def test_density_above_eos_limit_is_reported(lbm, sat_gpu):
     Tc, rl, rg = sat_gpu
     w = droplet(Tc, rl, rg, nx=32, ny=32, R=8.0)

@@ -149,6 +149,23 @@ def boiling(Tc, rho_l, rho_g, nx=1024, ny=2048, T_rel=0.86, dT_rel=0.2, gravity=
                     {"T_sat": T_sat, "seed": seed})
 
 
+def head_limited_fill(rho_l, rho_g, p_sat, gravity, ny, fill=0.5, head_frac=0.5) -> float:
+    """Liquid fill fraction of a boiling pool whose vapour head stays within head_frac * p_sat.
+
+    With buoyancy (rho - rho_ave) g in a box closed at the top, the hydrostatic pressure rise
+    across the vapour column is fill (1 - fill) (rho_l - rho_g) g ny (rho_ave = fill rho_l +
+    (1 - fill) rho_g).  When it approaches the gap between p_sat and the vapour spinodal, the top
+    vapour cannot stay vapour and the column collapses (density reaches zero within ~1500 steps).
+    Returns `fill` if its head is within the limit, otherwise the larger fill (a fuller pool with
+    a shallower vapour headspace) whose head equals the limit."""
+    span = (rho_l - rho_g) * abs(gravity) * ny
+    cap = head_frac * p_sat
+    if span <= 0.0 or fill * (1.0 - fill) * span <= cap:
+        return fill
+    q = cap / span  # fill (1 - fill) = q, q < 1/4 here
+    return 0.5 + math.sqrt(max(0.0, 0.25 - q))
+
+
 # ------------------------------------------------------------------------- batched / served mixes
 GRID_CLASSES = ((256, 512), (384, 768), (512, 1024))
 
