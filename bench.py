@@ -30,7 +30,7 @@ BYTES_PER_LU = {"f32": 128, "f64": 256}  # f 9+9, g 5+5, history 2+2 values per 
 # HBM bytes per launch of the step kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # scaled by the same counters read for a plain copy of known size (profiles/); keyed by grid size,
 # None where no measurement of the current kernel exists
-TRAFFIC = {(512, 512): 35257214}
+TRAFFIC = {}
 
 
 def build_workload(nx=512, ny=512, steps=20000):
@@ -56,6 +56,23 @@ def cpu_baseline(w, steps):
     return {"value": w.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{w.params.nx}x{w.params.ny} evaporation, FP64, {steps} steps after 2 warm-up steps "
                       f"({dt:.1f} s)"}
+
+
+def shape_text(lbm, precision, k):
+    tx, ty, w = lbm.shapes(precision)[k]
+    return f"{tx}x{ty} tile, {w} wavefronts (shape {k})"
+
+
+def choose_shape(s, shape):
+    """Tile shape of a solver: 'auto' times every shape (autotune), an integer fixes one.
+    Returns the measured ms per step per shape ({} when fixed)."""
+    from paper_2205_00686_amd import autotune
+
+    if shape == "auto":
+        r = autotune.tune_solver(s, use_cache=False)
+        return {str(k): round(v, 6) for k, v in sorted(r.ms_per_step.items())}
+    s.set_shape(int(shape))
+    return {}
 
 
 def sweep_workloads(n, steps, lbm):
@@ -87,11 +104,17 @@ def run_batch_mode(args):
     nodes = sum(w.nodes for w in ws)
     print(f"[bench] batch of {len(ws)} boiling instances, {nodes} nodes, {args.steps} steps", file=sys.stderr,
           flush=True)
-    # plain: one simulation after the other
+    from paper_2205_00686_amd import autotune
+
+    # plain: one simulation after the other, each with the tile shape tuned for its grid
     solvers = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for w in ws]
     stream = solvers[0].stream
     for s in solvers:
         s.step(args.warmup)
+    plain_shapes = {}
+    for s in solvers:
+        r = autotune.tune_solver(s)
+        plain_shapes[f"{s.nx}x{s.ny}"] = shape_text(lbm, lbm.LBM_FP32, r.shape)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -112,6 +135,8 @@ def run_batch_mode(args):
         b.set_budget(i, args.warmup)
     b.step(args.warmup)
     b.sync()
+    bt = autotune.tune_batch(b, use_cache=False)
+    print(f"[bench] batch tile shape {b.shape}: {bt.ms_per_step}", file=sys.stderr, flush=True)
     for i in range(len(solvers)):
         b.set_budget(i, args.steps)
     torch.cuda.synchronize()
@@ -126,7 +151,9 @@ def run_batch_mode(args):
     out = {"metric": METRIC, "mode": "batched vs plain", "unit": "MLUPS", "n_gpus": 1, "dtype": "f32",
            "config": {"workload": f"gravity sweep: {len(ws)} boiling instances on 256x512/384x768/512x1024 grids, "
                                   f"g log-uniform [5e-6, 5e-5], dT uniform [0.1, 0.3] Tc, pool fill 0.5 or head-limited",
-                      "instances": len(ws), "nodes": nodes, "steps": args.steps, "warmup": args.warmup},
+                      "instances": len(ws), "nodes": nodes, "steps": args.steps, "warmup": args.warmup,
+                      "batch_tile_shape": shape_text(lbm, lbm.LBM_FP32, b.shape),
+                      "plain_tile_shapes": plain_shapes},
            "batched_mlups": round(lu / (batch_ms * 1e-3) / 1e6, 1),
            "plain_sequential_mlups": round(lu / (plain_ms * 1e-3) / 1e6, 1),
            "speedup": round(plain_ms / batch_ms, 3),
@@ -191,6 +218,7 @@ def main():
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--shape", default="auto", help="tile shape index, or 'auto' to autotune (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="before the timed region, copy this many MiB device-to-device once (a plain copy "
@@ -227,6 +255,8 @@ def main():
         del src, dst
     s.step(args.warmup)
     s.sync()
+    tune = choose_shape(s, args.shape)
+    print(f"[bench] tile shape {s.shape}: {tune}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -275,6 +305,7 @@ def main():
         "config": {"workload": f"droplet evaporation in open space, {args.nx}x{args.ny}, FP32 populations, "
                                f"R={64 * args.nx // 512}, edges at 1.1 T_sat",
                    "nx": args.nx, "ny": args.ny, "precision": "fp32", "kernel": "fused D2Q9+D2Q5 step",
+                   "tile_shape": shape_text(lbm, lbm.LBM_FP32, s.shape), "tile_shape_ms_per_step": tune,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((args.nx, args.ny)),

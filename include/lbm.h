@@ -84,9 +84,10 @@ typedef struct {
 /* Fill *p with the paper's parameter values (Sections 2 and 4) for an nx x ny FP32 grid. */
 void lbm_params_default(lbm_params* p, int32_t nx, int32_t ny);
 
-/* Check a parameter set without touching the device.  LBM_E_INVAL if nx or ny < 3, the grid
-   has more than 2^31 nodes, a relaxation rate is outside (0, 2), wdot outside (0, 1),
-   c_v <= 0, nu <= 0 or lambda <= 0. */
+/* Check a parameter set without touching the device.  LBM_E_INVAL if nx or ny < 3, one
+   population plane (nx * ny values) exceeds 2^32 - 1 bytes (about 1.07e9 nodes in FP32,
+   5.4e8 in FP64), a relaxation rate is outside (0, 2), wdot outside (0, 1), c_v <= 0, nu <= 0
+   or lambda <= 0. */
 lbm_status lbm_validate(const lbm_params* p);
 
 /* Exact device bytes a context needs (populations f and g in two copies, the temperature
@@ -112,6 +113,21 @@ lbm_status lbm_step(lbm_ctx* h, int64_t n);
 
 /* Number of steps taken since lbm_init (or the count restored by lbm_load_state). */
 int64_t lbm_steps_done(const lbm_ctx* h);
+
+/* Tile shapes of the step kernel.  A workgroup of `waves` wavefronts updates a tile_x x tile_y
+   block of nodes; the library holds lbm_shape_count(precision) shapes, numbered from 0.  The
+   shape decides only how nodes are grouped into workgroups: every shape gives bit-identical
+   results.  lbm_shape_info: LBM_E_INVAL for an unknown precision or k; NULL outputs are skipped. */
+int lbm_shape_count(int32_t precision);
+lbm_status lbm_shape_info(int32_t precision, int k, int* tile_x, int* tile_y, int* waves);
+
+/* Use shape k for the context's later steps (k = -1: the library's choice from the grid size,
+   the default).  Ordered on the context's stream after the steps already enqueued.
+   LBM_E_INVAL for k outside [-1, lbm_shape_count). */
+lbm_status lbm_set_shape(lbm_ctx* h, int k);
+
+/* The shape in use (never -1); -1 for a NULL context. */
+int lbm_get_shape(const lbm_ctx* h);
 
 /* Wait for the stream and report any device-side numerical failure. */
 lbm_status lbm_sync(lbm_ctx* h);
@@ -170,6 +186,12 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t k);
 
 /* Steps still budgeted for instance i. */
 int64_t lbm_batch_remaining(const lbm_batch* b, int i);
+
+/* Tile shape of the batched launches (k = -1: chosen from the batch's total size, the
+   default); the members' own shapes are not used by the batch.  LBM_E_INVAL for k outside
+   [-1, lbm_shape_count). */
+lbm_status lbm_batch_set_shape(lbm_batch* b, int k);
+int lbm_batch_get_shape(const lbm_batch* b);
 
 /* Wait for the batch's stream; report per-instance numerical failures in status[n] (may be
    NULL).  The contexts' step counters are brought up to date. */

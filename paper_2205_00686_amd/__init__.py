@@ -19,7 +19,8 @@ from . import _native
 from ._native import LBM_FP32, LBM_FP64, LBM_FREEZE_FLOW, LBM_NO_S, NativeLibraryMissing
 
 __all__ = ["Solver", "Batch", "LbmError", "params_struct", "coexistence", "critical_temperature",
-           "footprint_bytes", "LBM_FP32", "LBM_FP64", "LBM_FREEZE_FLOW", "LBM_NO_S", "NativeLibraryMissing"]
+           "footprint_bytes", "shapes", "LBM_FP32", "LBM_FP64", "LBM_FREEZE_FLOW", "LBM_NO_S",
+           "NativeLibraryMissing"]
 
 
 class LbmError(RuntimeError):
@@ -51,6 +52,17 @@ def params_struct(prm, precision: int = LBM_FP32) -> _native.LbmParams:
             setattr(c, name, getattr(prm, name))
     c.precision = int(precision)
     return c
+
+
+def shapes(precision: int = LBM_FP32):
+    """Tile shapes of the step kernel compiled into the library: [(tile_x, tile_y, waves), ...]."""
+    L = _native.lib()
+    out = []
+    for k in range(int(L.lbm_shape_count(int(precision)))):
+        tx, ty, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(L.lbm_shape_info(int(precision), k, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(w)))
+        out.append((tx.value, ty.value, w.value))
+    return out
 
 
 def critical_temperature(prm) -> float:
@@ -142,6 +154,16 @@ class Solver:
     def steps(self) -> int:
         return int(_native.lib().lbm_steps_done(self.handle))
 
+    @property
+    def shape(self) -> int:
+        """Index (into shapes(precision)) of the tile shape used by later steps."""
+        return int(_native.lib().lbm_get_shape(self.handle))
+
+    def set_shape(self, k: int):
+        """Tile shape k for later steps; -1 restores the library's choice.  Results do not change."""
+        _check(_native.lib().lbm_set_shape(self.handle, int(k)), self.handle)
+        return self
+
     def fields(self):
         out = [np.empty((self.ny, self.nx)) for _ in range(4)]
         _check(_native.lib().lbm_read_fields(self.handle, *(_dptr(a) for a in out)), self.handle)
@@ -212,6 +234,15 @@ class Batch:
 
     def remaining(self, i: int) -> int:
         return int(_native.lib().lbm_batch_remaining(self.handle, int(i)))
+
+    @property
+    def shape(self) -> int:
+        return int(_native.lib().lbm_batch_get_shape(self.handle))
+
+    def set_shape(self, k: int):
+        """Tile shape k of the batched launches; -1 restores the library's choice."""
+        _check(_native.lib().lbm_batch_set_shape(self.handle, int(k)))
+        return self
 
     def sync(self):
         n = len(self.solvers)

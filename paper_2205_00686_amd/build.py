@@ -13,6 +13,9 @@ HEADERS = [os.path.join(HERE, "csrc", n) for n in ("lbm_device.hpp", "lbm_step.h
 OUT = os.path.join(HERE, "liblbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+         # fuse a multiply and an add only inside one expression: the arithmetic of a node is then
+         # fixed by the source, whatever the tile shape or code layout of the kernel instance
+         "-ffp-contract=on",
          # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include")]

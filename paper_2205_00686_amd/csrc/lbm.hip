@@ -41,6 +41,30 @@ double pr_kappa(const lbm_params* p) {
   return 0.37464 + 1.54226 * w - 0.26992 * w * w;
 }
 
+// ---- tile shapes compiled into the library (tile height, wavefronts), per precision
+struct ShapeDef {
+  int ty, waves;
+};
+#define LBM_SHAPE_DEF(k, ty, w) {ty, w},
+constexpr ShapeDef F32_SHAPES[] = {LBM_F32_SHAPES(LBM_SHAPE_DEF)};
+constexpr ShapeDef F64_SHAPES[] = {LBM_F64_SHAPES(LBM_SHAPE_DEF)};
+#undef LBM_SHAPE_DEF
+constexpr int N_F32_SHAPES = (int)(sizeof(F32_SHAPES) / sizeof(F32_SHAPES[0]));
+constexpr int N_F64_SHAPES = (int)(sizeof(F64_SHAPES) / sizeof(F64_SHAPES[0]));
+
+int shape_count(int precision) { return precision == LBM_FP64 ? N_F64_SHAPES : N_F32_SHAPES; }
+const ShapeDef& shape_def(int precision, int k) { return precision == LBM_FP64 ? F64_SHAPES[k] : F32_SHAPES[k]; }
+int tiles_of(int nx, int ny, int ty) { return ((nx + TX - 1) / TX) * ((ny + ty - 1) / ty); }
+
+// Shape used when none is requested: the 1-row-per-thread shape while the grid has fewer
+// tiles than about four per compute unit (the launch is a single wave of workgroups and its
+// latency matters), the 2-rows-per-thread shape (two workgroups resident per compute unit)
+// beyond.  The autotuner replaces this guess by a measurement.
+int default_shape(int precision, int nx, int ny) {
+  if (precision == LBM_FP64) return 0;
+  return tiles_of(nx, ny, F32_SHAPES[0].ty) >= 1024 ? 1 : 0;
+}
+
 }  // namespace
 
 struct lbm_ctx {
@@ -69,6 +93,8 @@ struct lbm_ctx {
   int64_t steps = 0;
   double rho_ave = 0.0;
   double T_ref = 0.0;  // storage offset of g and the history (exact in the working precision)
+  int shape_req = -1;  // requested tile shape (-1: chosen from the grid size)
+  int shape = 0;       // tile shape in use
   int ntiles = 0;
   hipGraphExec_t graph = nullptr;
   std::string last_error;
@@ -86,9 +112,11 @@ struct lbm_batch {
   long long* d_clock = nullptr;
   long long clock = 0;           // host mirror of the device clock
   int total_tiles = 0;
+  int shape = -1;                // tile shape of the batched launches (-1: from the first context)
   bool table_dirty = true;
   hipGraphExec_t graph = nullptr;
   std::vector<lbm_ctx*> graph_layout;  // active instances (in table order) the graph was captured for
+  int graph_shape = -1;                // tile shape the graph was captured with
 };
 
 // ------------------------------------------------------------------------------ helpers
@@ -150,7 +178,7 @@ static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref)
 }
 
 template <typename real>
-static InstDesc<real> make_desc(lbm_ctx* h) {
+static InstDesc<real> make_desc(lbm_ctx* h, int ty) {
   InstDesc<real> D{};
   D.fA = (real*)h->fA;
   D.gA = (real*)h->gA;
@@ -161,7 +189,7 @@ static InstDesc<real> make_desc(lbm_ctx* h) {
   D.nx = h->prm.nx;
   D.ny = h->prm.ny;
   D.ntx = (h->prm.nx + TX - 1) / TX;
-  D.nty = (h->prm.ny + TY - 1) / TY;
+  D.nty = (h->prm.ny + ty - 1) / ty;
   D.tile_begin = 0;
   D.t_start = 0;
   D.t_end = std::numeric_limits<long long>::max();
@@ -220,8 +248,10 @@ double lbm_critical_temperature(const lbm_params* p) { return 0.0778 * p->a / (0
 lbm_status lbm_validate(const lbm_params* p) {
   if (!p) return LBM_E_INVAL;
   if (p->nx < 3 || p->ny < 3) return LBM_E_INVAL;
-  if ((double)p->nx * (double)p->ny > 2147483647.0) return LBM_E_INVAL;
   if (p->precision != LBM_FP32 && p->precision != LBM_FP64) return LBM_E_INVAL;
+  // the step kernel addresses a plane with 32-bit byte offsets
+  const double plane_bytes = (double)p->nx * (double)p->ny * (p->precision == LBM_FP64 ? 8.0 : 4.0);
+  if (plane_bytes > 4294967295.0) return LBM_E_INVAL;
   auto rate_ok = [](double s) { return std::isfinite(s) && s > 0.0 && s < 2.0; };
   if (!(p->nu > 0.0) || !(p->lambda > 0.0) || !(p->cv > 0.0)) return LBM_E_INVAL;
   if (!(p->wdot > 0.0 && p->wdot < 1.0)) return LBM_E_INVAL;
@@ -280,7 +310,9 @@ lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hi
   h->fB = q; q += align_up(9 * h->N * h->rsz);
   h->gB = q; q += align_up(5 * h->N * h->rsz);
   h->Th = q;
-  h->ntiles = ((p->nx + TX - 1) / TX) * ((p->ny + TY - 1) / TY);
+  h->shape_req = -1;
+  h->shape = default_shape(p->precision, p->nx, p->ny);
+  h->ntiles = tiles_of(p->nx, p->ny, shape_def(p->precision, h->shape).ty);
   *out = h;
   return LBM_OK;
 }
@@ -294,10 +326,10 @@ lbm_status lbm_destroy(lbm_ctx* h) {
 
 static lbm_status upload_desc(lbm_ctx* h) {
   if (h->prm.precision == LBM_FP64) {
-    h->desc64 = make_desc<double>(h);
+    h->desc64 = make_desc<double>(h, shape_def(LBM_FP64, h->shape).ty);
     HIP_OR_FAIL(h, hipMemcpyAsync(h->d_desc, &h->desc64, sizeof(h->desc64), hipMemcpyHostToDevice, h->stream));
   } else {
-    h->desc32 = make_desc<float>(h);
+    h->desc32 = make_desc<float>(h, shape_def(LBM_FP32, h->shape).ty);
     HIP_OR_FAIL(h, hipMemcpyAsync(h->d_desc, &h->desc32, sizeof(h->desc32), hipMemcpyHostToDevice, h->stream));
   }
   return LBM_OK;
@@ -359,16 +391,29 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
   return LBM_OK;
 }
 
-static lbm_status launch_steps(lbm_ctx* h, int n) {
-  const long long* clk = h->d_clock;
-  for (int k = 0; k < n; ++k) {
-    if (h->prm.precision == LBM_FP64)
-      step_kernel<double, StepShape<double>::WAVES, StepShape<double>::MINW><<<h->ntiles, 64 * StepShape<double>::WAVES, 0, h->stream>>>(
-          (const InstDesc<double>*)h->d_desc, 1, clk, k);
-    else
-      step_kernel<float, StepShape<float>::WAVES, StepShape<float>::MINW><<<h->ntiles, 64 * StepShape<float>::WAVES, 0, h->stream>>>(
-          (const InstDesc<float>*)h->d_desc, 1, clk, k);
+// one launch of the step kernel of tile shape `shape` over `grid` workgroups
+static void launch_step(int precision, int shape, int grid, hipStream_t st, const void* table, int ninst,
+                        const long long* clk, int k) {
+#define LBM_LAUNCH_F32(kk, ty, w)                                                                         \
+  case kk:                                                                                                \
+    step_kernel<float, Shape<ty, w>><<<grid, 64 * w, 0, st>>>((const InstDesc<float>*)table, ninst, clk, k); \
+    break;
+#define LBM_LAUNCH_F64(kk, ty, w)                                                                           \
+  case kk:                                                                                                  \
+    step_kernel<double, Shape<ty, w>><<<grid, 64 * w, 0, st>>>((const InstDesc<double>*)table, ninst, clk, k); \
+    break;
+  if (precision == LBM_FP64) {
+    switch (shape) { LBM_F64_SHAPES(LBM_LAUNCH_F64) default: break; }
+  } else {
+    switch (shape) { LBM_F32_SHAPES(LBM_LAUNCH_F32) default: break; }
   }
+#undef LBM_LAUNCH_F32
+#undef LBM_LAUNCH_F64
+}
+
+static lbm_status launch_steps(lbm_ctx* h, int n) {
+  for (int k = 0; k < n; ++k)
+    launch_step(h->prm.precision, h->shape, h->ntiles, h->stream, h->d_desc, 1, h->d_clock, k);
   clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n);
   HIP_OR_FAIL(h, hipGetLastError());
   return LBM_OK;
@@ -423,6 +468,40 @@ lbm_status lbm_step(lbm_ctx* h, int64_t n) {
 }
 
 int64_t lbm_steps_done(const lbm_ctx* h) { return h ? h->steps : -1; }
+
+int lbm_shape_count(int precision) {
+  if (precision != LBM_FP32 && precision != LBM_FP64) return 0;
+  return shape_count(precision);
+}
+
+lbm_status lbm_shape_info(int precision, int k, int* tile_x, int* tile_y, int* waves) {
+  if ((precision != LBM_FP32 && precision != LBM_FP64) || k < 0 || k >= shape_count(precision)) return LBM_E_INVAL;
+  const ShapeDef& d = shape_def(precision, k);
+  if (tile_x) *tile_x = TX;
+  if (tile_y) *tile_y = d.ty;
+  if (waves) *waves = d.waves;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_shape(lbm_ctx* h, int k) {
+  if (!h || k < -1 || k >= shape_count(h->prm.precision)) return LBM_E_INVAL;
+  h->shape_req = k;
+  const int s = k < 0 ? default_shape(h->prm.precision, h->prm.nx, h->prm.ny) : k;
+  if (s == h->shape) return LBM_OK;
+  h->shape = s;
+  h->ntiles = tiles_of(h->prm.nx, h->prm.ny, shape_def(h->prm.precision, s).ty);
+  if (h->graph) {
+    (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+  }
+  if (h->initialised) {
+    if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+    return upload_desc(h);  // ordered on the stream after the launches already enqueued
+  }
+  return LBM_OK;
+}
+
+int lbm_get_shape(const lbm_ctx* h) { return h ? h->shape : -1; }
 
 lbm_status lbm_sync(lbm_ctx* h) {
   if (!h) return LBM_E_INVAL;
@@ -670,6 +749,11 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   b->pending.assign(n, 0);
   b->stream = (hipStream_t)hip_stream;
   b->precision = prec;
+  {
+    long long tiles = 0;  // default shape from the size of the whole batch
+    for (int i = 0; i < n; ++i) tiles += tiles_of(ctxs[i]->prm.nx, ctxs[i]->prm.ny, shape_def(prec, 0).ty);
+    b->shape = (prec == LBM_FP32 && tiles >= 1024) ? 1 : 0;
+  }
   b->base = (char*)dev_mem;
   b->bytes = bytes;
   b->d_clock = (long long*)b->base;
@@ -691,6 +775,22 @@ int64_t lbm_batch_remaining(const lbm_batch* b, int i) {
   return b->remaining[i];
 }
 
+lbm_status lbm_batch_set_shape(lbm_batch* b, int k) {
+  if (!b || k < -1 || k >= shape_count(b->precision)) return LBM_E_INVAL;
+  if (k < 0) {
+    long long tiles = 0;
+    for (lbm_ctx* h : b->ctx) tiles += tiles_of(h->prm.nx, h->prm.ny, shape_def(b->precision, 0).ty);
+    k = (b->precision == LBM_FP32 && tiles >= 1024) ? 1 : 0;
+  }
+  if (k != b->shape) {
+    b->shape = k;
+    b->table_dirty = true;  // tile counts change; the graph is recaptured at the next upload
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_get_shape(const lbm_batch* b) { return b ? b->shape : -1; }
+
 }  // extern "C"
 
 // Table of the batch: active instances first (in the caller's order), then parked ones, so
@@ -708,7 +808,7 @@ static void fill_table(lbm_batch* b, std::vector<InstDesc<real>>& tab) {
   for (int j = 0; j < n; ++j) {
     const int i = order[j];
     lbm_ctx* h = b->ctx[i];
-    InstDesc<real> D = make_desc<real>(h);
+    InstDesc<real> D = make_desc<real>(h, shape_def(b->precision, b->shape).ty);
     // parity continues from the context's own step count: clock - t_start = steps done
     D.t_start = b->clock - (long long)(h->steps + b->pending[i]);
     if (b->remaining[i] > 0) {
@@ -750,25 +850,19 @@ static lbm_status batch_upload(lbm_batch* b) {
   std::vector<lbm_ctx*> layout;
   for (size_t i = 0; i < n; ++i)
     if (b->remaining[i] > 0) layout.push_back(b->ctx[i]);
-  if (b->graph && layout != b->graph_layout) {
+  if (b->graph && (layout != b->graph_layout || b->shape != b->graph_shape)) {
     (void)hipGraphExecDestroy(b->graph);
     b->graph = nullptr;
   }
   b->graph_layout = layout;
+  b->graph_shape = b->shape;
   b->table_dirty = false;
   return LBM_OK;
 }
 
 static lbm_status batch_launch(lbm_batch* b, int k) {
   const int n = (int)b->ctx.size();
-  for (int s = 0; s < k; ++s) {
-    if (b->precision == LBM_FP64)
-      step_kernel<double, StepShape<double>::WAVES, StepShape<double>::MINW><<<b->total_tiles, 64 * StepShape<double>::WAVES, 0, b->stream>>>(
-          (const InstDesc<double>*)b->d_table, n, b->d_clock, s);
-    else
-      step_kernel<float, StepShape<float>::WAVES, StepShape<float>::MINW><<<b->total_tiles, 64 * StepShape<float>::WAVES, 0, b->stream>>>(
-          (const InstDesc<float>*)b->d_table, n, b->d_clock, s);
-  }
+  for (int s = 0; s < k; ++s) launch_step(b->precision, b->shape, b->total_tiles, b->stream, b->d_table, n, b->d_clock, s);
   clock_advance_kernel<<<1, 64, 0, b->stream>>>(b->d_clock, (long long)k);
   HIP_OR_FAIL(b->ctx[0], hipGetLastError());
   return LBM_OK;

@@ -20,14 +20,24 @@
 namespace lbm {
 
 constexpr int TX = 64;        // tile width  (one wavefront along x)
-constexpr int TY = 16;        // tile height (the workgroup has TY / rows-per-thread wavefronts)
 constexpr int NXCD = 8;       // accelerator complex dies of an MI355X (each with its own L2)
 constexpr int HXW = 3;        // halo columns per side (wetting ghost needs rho at radius 3)
 constexpr int HYW = 2;        // halo rows per side (psi at radius 2 for div u)
 constexpr int EXW = TX + 2 * HXW;
-constexpr int EYW = TY + 2 * HYW;
-constexpr int RING = EXW * EYW - TX * TY;                       // halo cells of the load region
-constexpr int URING = (TX + 2) * (TY + 2) - TX * TY;            // halo cells of the velocity region
+
+// Workgroup shape of the step kernel: a TX x TY_ tile updated by WAVES_ wavefronts of 64 lanes
+// along x; each thread owns RPT rows of its column.
+template <int TY_, int WAVES_>
+struct Shape {
+  static constexpr int TY = TY_;
+  static constexpr int WAVES = WAVES_;
+  static constexpr int NT = 64 * WAVES_;
+  static constexpr int RPT = TY_ / WAVES_;
+  static constexpr int EYW = TY_ + 2 * HYW;
+  static constexpr int RING = EXW * EYW - TX * TY_;             // halo cells of the load region
+  static constexpr int URING = (TX + 2) * (TY_ + 2) - TX * TY_;  // halo cells of the velocity region
+  static_assert(RPT * WAVES_ == TY_, "rows per thread must divide the tile height");
+};
 
 // error bits of the device error word
 constexpr unsigned ERR_RHO = 1u;   // density <= 0 or not finite

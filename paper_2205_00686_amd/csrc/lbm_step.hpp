@@ -13,14 +13,15 @@
 //      g (Eq. 39), push-streaming of f (Eq. 6, halfway bounce-back at walls) and of g with the
 //      rho c_v-weighted blend at the destination (Eq. 39; anti-bounce-back at Dirichlet edges).
 //
-// A workgroup has WAVES wavefronts of 64 lanes along x; each thread owns TY / WAVES rows of its
-// column (rows ty, ty + WAVES, ...).
+// A workgroup has S::WAVES wavefronts of 64 lanes along x; each thread owns S::RPT rows of its
+// column (rows ty, ty + WAVES, ...).  The tile shape changes only which node a thread handles,
+// never the arithmetic of a node.
 #pragma once
 #include "lbm_device.hpp"
 
 namespace lbm {
 
-template <typename real>
+template <typename real, int EYW>
 struct StepLds {
   real rho[EYW][EXW];
   real irc[EYW][EXW];  // 1 / (rho c_v), needed at the streaming destination
@@ -31,13 +32,15 @@ struct StepLds {
 };
 
 // position of halo cell r of the load region (ring around the TX x TY interior)
+template <class S>
 __device__ __forceinline__ void ring_cell(int r, int& ex, int& ey) {
+  static_assert(HYW == 2, "the ring has two rows above and below the tile");
   if (r < 2 * EXW) {
     ey = r / EXW;
     ex = r - ey * EXW;
   } else if (r < 4 * EXW) {
     const int q = r - 2 * EXW;
-    ey = EYW - 2 + q / EXW;
+    ey = S::EYW - 2 + q / EXW;
     ex = q % EXW;
   } else {
     const int q = r - 4 * EXW;
@@ -48,10 +51,11 @@ __device__ __forceinline__ void ring_cell(int r, int& ex, int& ey) {
 }
 
 // position of halo cell r of the velocity region (one node around the interior)
+template <class S>
 __device__ __forceinline__ void uring_cell(int r, int& ex, int& ey) {
   if (r < 2 * (TX + 2)) {
     const int side = r / (TX + 2);
-    ey = side ? EYW - HYW : HYW - 1;
+    ey = side ? S::EYW - HYW : HYW - 1;
     ex = HXW - 1 + (r - side * (TX + 2));
   } else {
     const int q = r - 2 * (TX + 2);
@@ -69,19 +73,32 @@ __device__ __forceinline__ int row_kind(int y, int ny, int walls) {
   return 3;
 }
 
+// Global accesses as (uniform base, 32-bit byte offset per lane): the base lives in scalar
+// registers and one vector register carries the offset, so an access costs no vector
+// arithmetic.  A plane holds fewer than 2^32 bytes (checked by lbm_validate).
+// A base computed by uniform arithmetic is passed through readfirstlane (it already is uniform,
+// so this costs two scalar moves), which keeps the compiler from folding the plane offset into a
+// 64-bit per-lane address.
+template <typename T>
+__device__ __forceinline__ gptr<T> sbase(gptr<T> ptr) {
+  const unsigned long long v = (unsigned long long)ptr;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (gptr<T>)(((unsigned long long)hi << 32) | lo);
+}
 template <typename real>
-__device__ __forceinline__ void load_node(gptr<const real> fs, gptr<const real> gs, size_t N, unsigned o,
-                                          real (&f)[9], real (&g)[5]) {
-#pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = (fs + i * N)[o];
-#pragma unroll
-  for (int i = 0; i < 5; ++i) g[i] = (gs + i * N)[o];
+__device__ __forceinline__ real ldb(gptr<const char> base, unsigned off) {
+  return *(gptr<const real>)(base + off);
+}
+template <typename real>
+__device__ __forceinline__ void stb(gptr<char> base, unsigned off, real v) {
+  *(gptr<real>)(base + off) = v;
 }
 
 // rho, j, T of a node and its LDS entries (Eqs. 11 and 25), psi with error checks; returns
 // (dp/dT)_rho for the node's own collision
-template <typename real>
-__device__ __forceinline__ real node_macro_to_lds(StepLds<real>& L, int ex, int ey, const DevParams<real>& p,
+template <typename real, class LDS>
+__device__ __forceinline__ real node_macro_to_lds(LDS& L, int ex, int ey, const DevParams<real>& p,
                                                   const real (&f)[9], const real (&g)[5], unsigned& err) {
   const real rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const real jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
@@ -109,8 +126,8 @@ __device__ __forceinline__ real node_macro_to_lds(StepLds<real>& L, int ex, int 
   return dpdT;
 }
 
-template <typename real>
-__device__ __forceinline__ void zero_lds_cell(StepLds<real>& L, int ex, int ey) {
+template <typename real, class LDS>
+__device__ __forceinline__ void zero_lds_cell(LDS& L, int ex, int ey) {
   L.rho[ey][ex] = real(0);
   L.irc[ey][ex] = real(0);
   L.psi[ey][ex] = real(0);
@@ -122,8 +139,8 @@ __device__ __forceinline__ void zero_lds_cell(StepLds<real>& L, int ex, int ey) 
 
 // Stencil of the interaction force: F_m = -G psi(x) (sx, sy) with (sx, sy) =
 // sum_i varpi_i psi(x + c_i) c_i (Eq. 9), varpi = 1/3 (axes), 1/12 (diagonals)
-template <typename real>
-__device__ __forceinline__ void psi_stencil(const StepLds<real>& L, int ex, int ey, real& sx, real& sy) {
+template <typename real, class LDS>
+__device__ __forceinline__ void psi_stencil(const LDS& L, int ex, int ey, real& sx, real& sy) {
   const real pE = L.psi[ey][ex + 1], pN = L.psi[ey + 1][ex], pW = L.psi[ey][ex - 1], pS = L.psi[ey - 1][ex];
   const real pNE = L.psi[ey + 1][ex + 1], pNW = L.psi[ey + 1][ex - 1], pSW = L.psi[ey - 1][ex - 1],
              pSE = L.psi[ey - 1][ex + 1];
@@ -135,19 +152,19 @@ __device__ __forceinline__ void psi_stencil(const StepLds<real>& L, int ex, int 
 // Dirichlet edges) need no index wrapping and no boundary tests; the general variant handles
 // periodic wrap, wall ghost rows, bounce-back and anti-bounce-back.  Both variants perform the
 // same arithmetic on every node.
-template <typename real, int WAVES, bool INTERIOR>
-__device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>& L, long long t, int x0, int y0) {
-  constexpr int NT = 64 * WAVES;
-  constexpr int RPT = TY / WAVES;
-  static_assert(RPT * WAVES == TY, "rows per thread must divide the tile height");
+template <typename real, class S, bool INTERIOR>
+__device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real, S::EYW>& L, long long t, int x0,
+                                          int y0) {
+  constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, RING = S::RING, URING = S::URING, EYW = S::EYW;
   const int nx = D.nx, ny = D.ny;
-  const size_t N = (size_t)nx * (size_t)ny;
+  constexpr ptrdiff_t SZ = sizeof(real);
+  const ptrdiff_t PB = (ptrdiff_t)nx * (ptrdiff_t)ny * SZ;  // bytes per plane
   const bool odd = ((t - D.t_start) & 1) != 0;
-  const gptr<const real> fs = to_global<const real>(odd ? D.fB : D.fA);
-  const gptr<const real> gs = to_global<const real>(odd ? D.gB : D.gA);
-  const gptr<real> fd = to_global<real>(odd ? D.fA : D.fB);
-  const gptr<real> gd = to_global<real>(odd ? D.gA : D.gB);
-  const gptr<real> Th = to_global<real>(D.Th);
+  const gptr<const char> fs = (gptr<const char>)to_global<const real>(odd ? D.fB : D.fA);
+  const gptr<const char> gs = (gptr<const char>)to_global<const real>(odd ? D.gB : D.gA);
+  const gptr<char> fd = (gptr<char>)to_global<real>(odd ? D.fA : D.fB);
+  const gptr<char> gd = (gptr<char>)to_global<real>(odd ? D.gA : D.gB);
+  const gptr<char> Th = (gptr<char>)to_global<real>(D.Th);
   const DevParams<real> p = D.p;
   const int walls = INTERIOR ? 0 : p.y_walls;
   const bool tb = INTERIOR ? false : p.thermal_box != 0;
@@ -162,38 +179,69 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>
   auto wx = [&](int v) { return INTERIOR ? v : wrapi(v, nx, tiny); };
   auto wy = [&](int v) { return (INTERIOR || walls) ? v : wrapi(v, ny, tiny); };
   auto fluid_row = [&](int y) { return INTERIOR || row_kind(y, ny, walls) == 0; };
+  auto fsp = [&](int i) { return sbase(fs + i * PB); };
+  auto gsp = [&](int i) { return sbase(gs + i * PB); };
+  auto fdp = [&](int i) { return sbase(fd + i * PB); };
+  auto gdp = [&](int i) { return sbase(gd + i * PB); };
 
-  // ---- phase 1: own nodes (kept in registers) and the halo ring
+  // ---- phase 1: every global load of the tile is issued first (own nodes with their T
+  // history, then the halo ring), so that the workgroup waits for memory once.  Own nodes keep
+  // f, g and the history in registers.
+  constexpr int RPN = (RING + NT - 1) / NT;  // halo ring nodes per thread
   const int xg = x0 + tx;
   const int xw = wx(xg);
-  real f[RPT][9], g[RPT][5], dpdT[RPT];
+  real f[RPT][9], g[RPT][5], T1[RPT], T2[RPT], dpdT[RPT];
+  unsigned ob[RPT];  // byte offset of the own node in a plane
+  bool own[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int ey = HYW + ty + WAVES * r;
     const int yg = y0 + ty + WAVES * r;
-    dpdT[r] = real(0);
-    if (fluid_row(yg)) {
-      load_node(fs, gs, N, (unsigned)(wy(yg) * nx + xw), f[r], g[r]);
-      dpdT[r] = node_macro_to_lds(L, HXW + tx, ey, p, f[r], g[r], err);
+    own[r] = fluid_row(yg);
+    ob[r] = (unsigned)(wy(yg) * nx + xw) * (unsigned)SZ;
+    if (own[r]) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[r][i] = ldb<real>(fsp(i), ob[r]);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[r][i] = ldb<real>(gsp(i), ob[r]);
+      T1[r] = ldb<real>(Th, ob[r]);
+      T2[r] = ldb<real>(sbase(Th + PB), ob[r]);
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[r][i] = real(0);
 #pragma unroll
       for (int i = 0; i < 5; ++i) g[r][i] = real(0);
-      zero_lds_cell(L, HXW + tx, ey);
+      T1[r] = T2[r] = real(0);
     }
   }
-  for (int r = tid; r < RING; r += NT) {
-    int ex, ey;
-    ring_cell(r, ex, ey);
-    const int yg = y0 - HYW + ey;
-    if (fluid_row(yg)) {
-      real fr[9], gr[5];
-      load_node(fs, gs, N, (unsigned)(wy(yg) * nx + wx(x0 - HXW + ex)), fr, gr);
-      (void)node_macro_to_lds(L, ex, ey, p, fr, gr, err);
-    } else {
-      zero_lds_cell(L, ex, ey);
+  real fr[RPN][9], gr[RPN][5];
+  int rex[RPN], rey[RPN];
+  bool rin[RPN], rfl[RPN];
+#pragma unroll
+  for (int q = 0; q < RPN; ++q) {
+    const int r = tid + q * NT;
+    rin[q] = r < RING;
+    ring_cell<S>(rin[q] ? r : 0, rex[q], rey[q]);
+    const int yg = y0 - HYW + rey[q];
+    rfl[q] = rin[q] && fluid_row(yg);
+    if (rfl[q]) {
+      const unsigned o = (unsigned)(wy(yg) * nx + wx(x0 - HXW + rex[q])) * (unsigned)SZ;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) fr[q][i] = ldb<real>(fsp(i), o);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) gr[q][i] = ldb<real>(gsp(i), o);
     }
+  }
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int ey = HYW + ty + WAVES * r;
+    dpdT[r] = real(0);
+    if (own[r]) dpdT[r] = node_macro_to_lds<real>(L, HXW + tx, ey, p, f[r], g[r], err);
+    else zero_lds_cell<real>(L, HXW + tx, ey);
+  }
+#pragma unroll
+  for (int q = 0; q < RPN; ++q) {
+    if (rfl[q]) (void)node_macro_to_lds<real>(L, rex[q], rey[q], p, fr[q], gr[q], err);
+    else if (rin[q]) zero_lds_cell<real>(L, rex[q], rey[q]);
   }
   __syncthreads();
 
@@ -231,7 +279,7 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>
       real fx = real(0), fy = real(0);
       if (!freeze) {
         real sx, sy;
-        psi_stencil(L, ex, ey, sx, sy);
+        psi_stencil<real>(L, ex, ey, sx, sy);
         const real c = -p.G * L.psi[ey][ex];
         fx = c * sx + (rho - p.rho_ave) * p.gx;
         fy = c * sy + (rho - p.rho_ave) * p.gy;
@@ -246,14 +294,14 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>
   }
   for (int r = tid; r < URING; r += NT) {
     int ex, ey;
-    uring_cell(r, ex, ey);
+    uring_cell<S>(r, ex, ey);
     const int yg = y0 - HYW + ey;
     if (fluid_row(yg)) {
       const real rho = L.rho[ey][ex];
       real fx = real(0), fy = real(0);
       if (!freeze) {
         real sx, sy;
-        psi_stencil(L, ex, ey, sx, sy);
+        psi_stencil<real>(L, ex, ey, sx, sy);
         const real c = -p.G * L.psi[ey][ex];
         fx = c * sx + (rho - p.rho_ave) * p.gx;
         fy = c * sy + (rho - p.rho_ave) * p.gy;
@@ -275,7 +323,7 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>
     const real ux = L.ux[ey][ex], uy = L.uy[ey][ex];
     const real Tr = ((g[r][0] + g[r][1]) + (g[r][2] + g[r][3])) + g[r][4];  // T - T_ref
     const real T = p.T_ref + Tr;
-    const unsigned o = (unsigned)(yg * nx + xw);
+    const unsigned o = ob[r];
 
     // div u = 3 sum_i w_i c_i . u(x + c_i); a ghost row carries -u of the fluid row next to it
     real divu;
@@ -297,11 +345,9 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>
     const real dTy = -p.vs1 * (g[r][2] - g[r][4]) * p.inv_cs2h;
     const real rcv = rho * p.cv;
     const real Q = -(rcv * (ux * dTx + uy * dTy) + T * dpdT[r] * divu);
-    const real T1 = Th[o];
-    const real T2 = (Th + N)[o];
-    const real Ssum = (p.flags & FL_NO_S) ? real(0) : rcv * real(0.5) * ((Tr - T1) - (T1 - T2));
-    Th[o] = Tr;
-    (Th + N)[o] = T1;
+    const real Ssum = (p.flags & FL_NO_S) ? real(0) : rcv * real(0.5) * ((Tr - T1[r]) - (T1[r] - T2[r]));
+    stb(Th, o, Tr);
+    stb(sbase(Th + PB), o, T1[r]);
 
     // ---- D2Q9 MRT collision with Li's forcing, moments of the orthogonal basis of Eq. (4).
     // Applied as a correction f* = f + M^-1 dm with dm = -S (m - m_eq) + (1 - S/2) F (Eq. 5):
@@ -371,38 +417,54 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>
       gs_[4] = gi[4] - (q34m - real(0.5) * dm2) + p.w1h * src;
     }
 
-    // ---- streaming: offsets of the eight neighbours (wrapped; a wall row is never written)
+    // ---- streaming.  Interior tiles: a neighbour's byte offset differs from the node's by a
+    // uniform amount, folded into the plane base.  Other tiles: wrapped offsets of the eight
+    // neighbours (a wall row is never written).
+    const ptrdiff_t RB = (ptrdiff_t)nx * SZ;
     const bool wall_n = walls && yg == ny - 1, wall_s = walls && yg == 0;
     const unsigned cE = (unsigned)wx(xg + 1), cW = (unsigned)wx(xg - 1);
     const unsigned rowc = (unsigned)(yg * nx);
     const unsigned rown = wall_n ? 0u : (unsigned)(wy(yg + 1) * nx);
     const unsigned rows = wall_s ? 0u : (unsigned)(wy(yg - 1) * nx);
+    const unsigned xwu = (unsigned)xw;
+    // destination of a population moving by (dx, dy): plane base and byte offset
+    auto dst = [&](gptr<char> plane, int dx, int dy, unsigned& off) -> gptr<char> {
+      if (INTERIOR) {
+        off = o;
+        return sbase(plane + (dy * RB + dx * SZ));
+      }
+      const unsigned row = dy > 0 ? rown : dy < 0 ? rows : rowc;
+      const unsigned col = dx > 0 ? cE : dx < 0 ? cW : xwu;
+      off = (row + col) * (unsigned)SZ;
+      return plane;
+    };
+    unsigned off;
 
     // f: push to x + c_i, halfway bounce-back through the walls (Eq. 6)
     if (freeze) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) (fd + i * N)[o] = fs_[i];
+      for (int i = 0; i < 9; ++i) stb(fdp(i), o, fs_[i]);
     } else {
-      fd[o] = fs_[0];
-      (fd + 1 * N)[rowc + cE] = fs_[1];
-      (fd + 3 * N)[rowc + cW] = fs_[3];
+      stb(fdp(0), o, fs_[0]);
+      { auto b = dst(fdp(1), 1, 0, off); stb(b, off, fs_[1]); }
+      { auto b = dst(fdp(3), -1, 0, off); stb(b, off, fs_[3]); }
       if (wall_n) {
-        (fd + 4 * N)[o] = fs_[2];
-        (fd + 7 * N)[o] = fs_[5];
-        (fd + 8 * N)[o] = fs_[6];
+        stb(fdp(4), o, fs_[2]);
+        stb(fdp(7), o, fs_[5]);
+        stb(fdp(8), o, fs_[6]);
       } else {
-        (fd + 2 * N)[rown + xw] = fs_[2];
-        (fd + 5 * N)[rown + cE] = fs_[5];
-        (fd + 6 * N)[rown + cW] = fs_[6];
+        { auto b = dst(fdp(2), 0, 1, off); stb(b, off, fs_[2]); }
+        { auto b = dst(fdp(5), 1, 1, off); stb(b, off, fs_[5]); }
+        { auto b = dst(fdp(6), -1, 1, off); stb(b, off, fs_[6]); }
       }
       if (wall_s) {
-        (fd + 2 * N)[o] = fs_[4];
-        (fd + 5 * N)[o] = fs_[7];
-        (fd + 6 * N)[o] = fs_[8];
+        stb(fdp(2), o, fs_[4]);
+        stb(fdp(5), o, fs_[7]);
+        stb(fdp(6), o, fs_[8]);
       } else {
-        (fd + 4 * N)[rows + xw] = fs_[4];
-        (fd + 7 * N)[rows + cW] = fs_[7];
-        (fd + 8 * N)[rows + cE] = fs_[8];
+        { auto b = dst(fdp(4), 0, -1, off); stb(b, off, fs_[4]); }
+        { auto b = dst(fdp(7), -1, -1, off); stb(b, off, fs_[7]); }
+        { auto b = dst(fdp(8), 1, -1, off); stb(b, off, fs_[8]); }
       }
     }
 
@@ -412,39 +474,43 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>
     // -g*_i(y) + 2 what_i T_w, for the population entering y in the opposite direction.
     {
       const real ircv = L.irc[ey][ex];
-      gd[o] = g[r][0] + (gs_[0] - g[r][0]) * ircv;
+      stb(gdp(0), o, g[r][0] + (gs_[0] - g[r][0]) * ircv);
       const bool out_e = tb && xg == nx - 1, out_w = tb && xg == 0;
       const bool out_n = (walls || tb) && yg == ny - 1, out_s = (walls || tb) && yg == 0;
       const real two_w = real(2) * p.w1h;
       if (out_e) {
         const real up = -gs_[1] + two_w * (p.T_box - p.T_ref);
-        (gd + 3 * N)[o] = g[r][3] + (up - g[r][3]) * ircv;
+        stb(gdp(3), o, g[r][3] + (up - g[r][3]) * ircv);
       } else {
         const real gold = L.g[0][ey][ex + 1];
-        (gd + 1 * N)[rowc + cE] = gold + (gs_[1] - gold) * L.irc[ey][ex + 1];
+        auto b = dst(gdp(1), 1, 0, off);
+        stb(b, off, gold + (gs_[1] - gold) * L.irc[ey][ex + 1]);
       }
       if (out_w) {
         const real up = -gs_[3] + two_w * (p.T_box - p.T_ref);
-        (gd + 1 * N)[o] = g[r][1] + (up - g[r][1]) * ircv;
+        stb(gdp(1), o, g[r][1] + (up - g[r][1]) * ircv);
       } else {
         const real gold = L.g[2][ey][ex - 1];
-        (gd + 3 * N)[rowc + cW] = gold + (gs_[3] - gold) * L.irc[ey][ex - 1];
+        auto b = dst(gdp(3), -1, 0, off);
+        stb(b, off, gold + (gs_[3] - gold) * L.irc[ey][ex - 1]);
       }
       if (out_n) {
         const real Tn = tb ? p.T_box : p.T_top;
         const real up = -gs_[2] + two_w * (Tn - p.T_ref);
-        (gd + 4 * N)[o] = g[r][4] + (up - g[r][4]) * ircv;
+        stb(gdp(4), o, g[r][4] + (up - g[r][4]) * ircv);
       } else {
         const real gold = L.g[1][ey + 1][ex];
-        (gd + 2 * N)[rown + xw] = gold + (gs_[2] - gold) * L.irc[ey + 1][ex];
+        auto b = dst(gdp(2), 0, 1, off);
+        stb(b, off, gold + (gs_[2] - gold) * L.irc[ey + 1][ex]);
       }
       if (out_s) {
         const real Ts = tb ? p.T_box : wall_temperature(p, 0, xw);
         const real up = -gs_[4] + two_w * (Ts - p.T_ref);
-        (gd + 2 * N)[o] = g[r][2] + (up - g[r][2]) * ircv;
+        stb(gdp(2), o, g[r][2] + (up - g[r][2]) * ircv);
       } else {
         const real gold = L.g[3][ey - 1][ex];
-        (gd + 4 * N)[rows + xw] = gold + (gs_[4] - gold) * L.irc[ey - 1][ex];
+        auto b = dst(gdp(4), 0, -1, off);
+        stb(b, off, gold + (gs_[4] - gold) * L.irc[ey - 1][ex]);
       }
     }
   }
@@ -452,9 +518,9 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real>
   if (err) atomicOr(D.err, err);
 }
 
-template <typename real, int WAVES, int MINW>
-__global__ __launch_bounds__(64 * WAVES, MINW) void step_kernel(const InstDesc<real>* __restrict__ table, int ninst,
-                                                                const long long* __restrict__ clock, int k) {
+template <typename real, class S>
+__global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __restrict__ table, int ninst,
+                                                     const long long* __restrict__ clock, int k) {
   // ---- which simulation and which tile (uniform per workgroup).  Workgroups are dispatched to
   // the 8 XCDs round-robin; remap so that each XCD takes a contiguous range of tiles: neighbouring
   // tiles then share one L2, where their halo reads hit and where the partial cache lines of the
@@ -476,35 +542,20 @@ __global__ __launch_bounds__(64 * WAVES, MINW) void step_kernel(const InstDesc<r
   if (tile < 0 || tile >= D.ntx * D.nty) return;
   const int by = tile / D.ntx;
   const int bx = tile - by * D.ntx;
-  const int x0 = bx * TX, y0 = by * TY;
-  __shared__ StepLds<real> L;
+  const int x0 = bx * TX, y0 = by * S::TY;
+  __shared__ StepLds<real, S::EYW> L;
   // interior: the load region [x0-HXW, x0+TX+HXW) x [y0-HYW, y0+TY+HYW) lies inside the grid,
   // so no wrap, ghost row, wall or Dirichlet edge is involved
-  const bool interior = x0 >= HXW && x0 + TX + HXW <= D.nx && y0 >= HYW && y0 + TY + HYW <= D.ny;
-  if (interior) step_tile<real, WAVES, true>(D, L, t, x0, y0);
-  else step_tile<real, WAVES, false>(D, L, t, x0, y0);
+  const bool interior = x0 >= HXW && x0 + TX + HXW <= D.nx && y0 >= HYW && y0 + S::TY + HYW <= D.ny;
+  if (interior) step_tile<real, S, true>(D, L, t, x0, y0);
+  else step_tile<real, S, false>(D, L, t, x0, y0);
 }
 
-// Workgroup shapes (wavefronts per workgroup, minimum resident wavefronts per SIMD that the
-// register allocation must allow).
-#ifndef LBM_F32_WAVES
-#define LBM_F32_WAVES 16
-#endif
-#ifndef LBM_F32_MINW
-#define LBM_F32_MINW 1
-#endif
-template <typename real>
-struct StepShape;
-template <>
-struct StepShape<float> {
-  static constexpr int WAVES = LBM_F32_WAVES;
-  static constexpr int MINW = LBM_F32_MINW;
-};
-template <>
-struct StepShape<double> {
-  static constexpr int WAVES = 8;
-  static constexpr int MINW = 1;
-};
+// Tile shapes compiled into the library, per precision: (tile height, wavefronts).  Index 0 is
+// the shape for small grids, index 1 the one for grids of many tiles; the others are candidates
+// for the autotuner.  All shapes give bit-identical results.
+#define LBM_F32_SHAPES(X) X(0, 16, 16) X(1, 16, 8) X(2, 8, 8) X(3, 32, 16) X(4, 8, 4) X(5, 4, 4)
+#define LBM_F64_SHAPES(X) X(0, 16, 8) X(1, 8, 8) X(2, 16, 16) X(3, 8, 4) X(4, 4, 4)
 
 // Clock advance after a group of step launches (a kernel, so that it can live in a graph).
 __global__ void clock_advance_kernel(long long* clock, long long n) {

@@ -101,3 +101,41 @@ def test_critical_temperature_and_coexistence_agree_with_oracle(L, orc, base_par
 def test_strerror(L):
     for s in (0, -1, -2, -3, -4, -5):
         assert len(L.lbm_strerror(s)) > 0
+
+
+def test_plane_size_limit(L):
+    """A population plane must stay below 2^32 bytes (the step kernel's 32-bit byte offsets)."""
+    from paper_2205_00686_amd import _native
+    p = _native.LbmParams()
+    L.lbm_params_default(ctypes.byref(p), 32768, 32767)  # 4 * 32768 * 32767 < 2^32
+    assert L.lbm_validate(ctypes.byref(p)) == 0
+    p.ny = 32768  # exactly 2^32 bytes
+    assert L.lbm_validate(ctypes.byref(p)) == -1
+    p.precision = 1
+    p.ny = 16383  # 8 * 32768 * 16383 < 2^32
+    assert L.lbm_validate(ctypes.byref(p)) == 0
+    p.ny = 16384
+    assert L.lbm_validate(ctypes.byref(p)) == -1
+
+
+def test_tile_shapes_api(L):
+    from paper_2205_00686_amd import shapes
+    for prec in (0, 1):
+        n = L.lbm_shape_count(prec)
+        assert n >= 4
+        got = shapes(prec)
+        assert len(got) == n
+        for tx, ty, w in got:
+            assert tx == 64 and ty % w == 0 and 1 <= w <= 16 and ty in (4, 8, 16, 32)
+        assert len(set(got)) == n
+        tx, ty, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        assert L.lbm_shape_info(prec, n, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(w)) == -1
+        assert L.lbm_shape_info(prec, -1, None, None, None) == -1
+        assert L.lbm_shape_info(prec, 0, None, None, None) == 0
+    assert L.lbm_shape_count(7) == 0
+    assert L.lbm_shape_info(7, 0, None, None, None) == -1
+    # contexts and batches: NULL handles are rejected without touching a device
+    assert L.lbm_set_shape(None, 0) == -1
+    assert L.lbm_get_shape(None) == -1
+    assert L.lbm_batch_set_shape(None, 0) == -1
+    assert L.lbm_batch_get_shape(None) == -1
