@@ -28,9 +28,9 @@ METRIC = "MLUPS (D2Q9+D2Q5 node updates/s) & % HBM roofline; batched vs plain; p
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = {"f32": 128, "f64": 256}  # f 9+9, g 5+5, history 2+2 values per node update
 # HBM bytes per launch of the step kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
-# scaled by the same counters read for a plain copy of known size (profiles/); keyed by grid size,
-# None where no measurement of the current kernel exists
-TRAFFIC = {}
+# scaled by the same counters read for a plain copy of known size (profiles/); keyed by grid size
+# and tile shape, None where no measurement of the current kernel exists
+TRAFFIC = {(512, 512, 0): 35090643}
 
 
 def build_workload(nx=512, ny=512, steps=20000):
@@ -308,7 +308,7 @@ def main():
                    "tile_shape": shape_text(lbm, lbm.LBM_FP32, s.shape), "tile_shape_ms_per_step": tune,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((args.nx, args.ny)),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((args.nx, args.ny, s.shape)),
                      "bytes_per_launch": bytes_per_launch, "kernel_ms_timed_region": round(ms_per_step, 6),
                      "kernel_ms_single_launch_p50": round(launch_p50, 6)},
         "wall_s": round(wall, 4),
