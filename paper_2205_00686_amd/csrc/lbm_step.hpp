@@ -515,7 +515,16 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real,
     }
   }
 
-  if (err) atomicOr(D.err, err);
+  // A failing simulation flags every node.  One atomic per thread, or even per wavefront, on one
+  // word would serialise the launch, so a wavefront ORs its flags with ballots and sets only the
+  // bits the word does not hold yet.
+  const unsigned long long e1 = __ballot((err & ERR_RHO) != 0u), e2 = __ballot((err & ERR_T) != 0u),
+                           e4 = __ballot((err & ERR_PSI) != 0u);
+  if ((e1 | e2 | e4) != 0ull && (threadIdx.x & 63u) == 0u) {
+    const unsigned bits = (e1 ? ERR_RHO : 0u) | (e2 ? ERR_T : 0u) | (e4 ? ERR_PSI : 0u);
+    const unsigned held = __hip_atomic_load(D.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((held & bits) != bits) atomicOr(D.err, bits);
+  }
 }
 
 template <typename real, class S>
