@@ -59,8 +59,8 @@ def cpu_baseline(w, steps):
 
 
 def shape_text(lbm, precision, k):
-    tx, ty, w = lbm.shapes(precision)[k]
-    return f"{tx}x{ty} tile, {w} wavefronts (shape {k})"
+    tx, ty, w, d = lbm.shapes(precision)[k]
+    return f"{tx}x{ty} tile, {w} wavefronts, {d} step{'s' if d > 1 else ''} per launch (shape {k})"
 
 
 def choose_shape(s, shape):
@@ -273,7 +273,7 @@ def main():
     nodes = w.nodes
     mlups = nodes * args.steps / (ev_ms * 1e-3) / 1e6
 
-    # per-launch kernel duration from event pairs around single launches (no graph)
+    # latency of a one-step call (one launch, no graph) from event pairs around it
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(200)]
     for a, b in evs:
         a.record(stream)
@@ -284,8 +284,10 @@ def main():
     launch_p50 = per_launch_ms[len(per_launch_ms) // 2]
 
     dtype = "f32"
-    bytes_per_launch = BYTES_PER_LU[dtype] * nodes
-    achieved = bytes_per_launch / (ms_per_step * 1e-3) / 1e9
+    depth = lbm.shapes(lbm.LBM_FP32)[s.shape][3]  # time steps per launch of the step kernel
+    bytes_per_launch = BYTES_PER_LU[dtype] * nodes * depth
+    ms_per_launch = ms_per_step * depth
+    achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
     fields = s.fields()
     finite = all(bool((f == f).all()) for f in fields)
 
@@ -309,8 +311,9 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((args.nx, args.ny, s.shape)),
-                     "bytes_per_launch": bytes_per_launch, "kernel_ms_timed_region": round(ms_per_step, 6),
-                     "kernel_ms_single_launch_p50": round(launch_p50, 6)},
+                     "bytes_per_launch": bytes_per_launch, "steps_per_launch": depth,
+                     "kernel_ms_per_launch_timed_region": round(ms_per_launch, 6),
+                     "kernel_ms_single_step_call_p50": round(launch_p50, 6)},
         "wall_s": round(wall, 4),
         "fields_finite": finite,
     }

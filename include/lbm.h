@@ -115,15 +115,21 @@ lbm_status lbm_step(lbm_ctx* h, int64_t n);
 int64_t lbm_steps_done(const lbm_ctx* h);
 
 /* Tile shapes of the step kernel.  A workgroup of `waves` wavefronts updates a tile_x x tile_y
-   block of nodes; the library holds lbm_shape_count(precision) shapes, numbered from 0.  The
-   shape decides only how nodes are grouped into workgroups: every shape gives bit-identical
-   results.  lbm_shape_info: LBM_E_INVAL for an unknown precision or k; NULL outputs are skipped. */
+   block of nodes, steps_per_launch (1 or 2) time steps per kernel launch; the library holds
+   lbm_shape_count(precision) shapes, numbered from 0.  The shape decides only how the work is
+   grouped into workgroups and launches: every shape gives bit-identical results.
+   lbm_shape_info: LBM_E_INVAL for an unknown precision or k; NULL outputs are skipped.
+   A two-step shape keeps the first step's result for the tile and its halo in LDS, which needs
+   a grid larger than that halo region: lbm_shape_fits tells whether shape k can run the grid
+   of *p (1) or not (0, also for invalid parameters). */
 int lbm_shape_count(int32_t precision);
-lbm_status lbm_shape_info(int32_t precision, int k, int* tile_x, int* tile_y, int* waves);
+lbm_status lbm_shape_info(int32_t precision, int k, int* tile_x, int* tile_y, int* waves, int* steps_per_launch);
+int lbm_shape_fits(const lbm_params* p, int k);
 
 /* Use shape k for the context's later steps (k = -1: the library's choice from the grid size,
-   the default).  Ordered on the context's stream after the steps already enqueued.
-   LBM_E_INVAL for k outside [-1, lbm_shape_count). */
+   the default).  Ordered on the context's stream after the steps already enqueued; waits for
+   that stream.  LBM_E_INVAL for k outside [-1, lbm_shape_count) or a shape that does not fit
+   the grid (lbm_shape_fits). */
 lbm_status lbm_set_shape(lbm_ctx* h, int k);
 
 /* The shape in use (never -1); -1 for a NULL context. */
@@ -189,7 +195,7 @@ int64_t lbm_batch_remaining(const lbm_batch* b, int i);
 
 /* Tile shape of the batched launches (k = -1: chosen from the batch's total size, the
    default); the members' own shapes are not used by the batch.  LBM_E_INVAL for k outside
-   [-1, lbm_shape_count). */
+   [-1, lbm_shape_count) or a shape that does not fit every member's grid. */
 lbm_status lbm_batch_set_shape(lbm_batch* b, int k);
 int lbm_batch_get_shape(const lbm_batch* b);
 

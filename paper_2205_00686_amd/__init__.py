@@ -19,7 +19,7 @@ from . import _native
 from ._native import LBM_FP32, LBM_FP64, LBM_FREEZE_FLOW, LBM_NO_S, NativeLibraryMissing
 
 __all__ = ["Solver", "Batch", "LbmError", "params_struct", "coexistence", "critical_temperature",
-           "footprint_bytes", "shapes", "LBM_FP32", "LBM_FP64", "LBM_FREEZE_FLOW", "LBM_NO_S",
+           "footprint_bytes", "shapes", "shape_fits", "LBM_FP32", "LBM_FP64", "LBM_FREEZE_FLOW", "LBM_NO_S",
            "NativeLibraryMissing"]
 
 
@@ -55,14 +55,23 @@ def params_struct(prm, precision: int = LBM_FP32) -> _native.LbmParams:
 
 
 def shapes(precision: int = LBM_FP32):
-    """Tile shapes of the step kernel compiled into the library: [(tile_x, tile_y, waves), ...]."""
+    """Tile shapes of the step kernel compiled into the library:
+    [(tile_x, tile_y, waves, steps_per_launch), ...]."""
     L = _native.lib()
     out = []
     for k in range(int(L.lbm_shape_count(int(precision)))):
-        tx, ty, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(L.lbm_shape_info(int(precision), k, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(w)))
-        out.append((tx.value, ty.value, w.value))
+        tx, ty, w, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(L.lbm_shape_info(int(precision), k, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(w),
+                                ctypes.byref(d)))
+        out.append((tx.value, ty.value, w.value, d.value))
     return out
+
+
+def shape_fits(prm, k: int, precision: int = LBM_FP32) -> bool:
+    """Whether tile shape k can run the grid of prm (two-step shapes need a grid larger than
+    their halo region)."""
+    c = params_struct(prm, precision)
+    return bool(_native.lib().lbm_shape_fits(ctypes.byref(c), int(k)))
 
 
 def critical_temperature(prm) -> float:

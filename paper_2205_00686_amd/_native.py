@@ -18,7 +18,7 @@ LBM_FREEZE_FLOW, LBM_NO_S = 1, 2
 # every symbol include/lbm.h declares
 EXPORTS = (
     "lbm_params_default", "lbm_validate", "lbm_footprint_bytes", "lbm_create", "lbm_init", "lbm_step",
-    "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_set_shape", "lbm_get_shape", "lbm_sync", "lbm_read_fields", "lbm_diagnostics", "lbm_state_bytes", "lbm_save_state",
+    "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_shape_fits", "lbm_set_shape", "lbm_get_shape", "lbm_sync", "lbm_read_fields", "lbm_diagnostics", "lbm_state_bytes", "lbm_save_state",
     "lbm_load_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
     "lbm_last_error", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
     "lbm_batch_remaining", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_sync", "lbm_batch_destroy",
@@ -76,7 +76,8 @@ def lib():
         "lbm_step": ([vp, i64], st),
         "lbm_steps_done": ([vp], i64),
         "lbm_shape_count": ([i32], ctypes.c_int),
-        "lbm_shape_info": ([i32, ctypes.c_int, ip, ip, ip], st),
+        "lbm_shape_info": ([i32, ctypes.c_int, ip, ip, ip, ip], st),
+        "lbm_shape_fits": ([P, ctypes.c_int], ctypes.c_int),
         "lbm_set_shape": ([vp, ctypes.c_int], st),
         "lbm_get_shape": ([vp], ctypes.c_int),
         "lbm_sync": ([vp], st),

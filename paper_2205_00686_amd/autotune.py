@@ -19,7 +19,7 @@ import tempfile
 import threading
 from dataclasses import dataclass, field
 
-from . import Batch, Solver, shapes
+from . import Batch, Solver, shape_fits, shapes
 
 _lock = threading.Lock()
 
@@ -32,8 +32,8 @@ class TuneResult:
     cached: bool = False                # True: taken from the cache, nothing was timed
 
     def describe(self, precision) -> str:
-        tx, ty, w = shapes(precision)[self.shape]
-        return f"{tx}x{ty} tile, {w} wavefronts"
+        tx, ty, w, d = shapes(precision)[self.shape]
+        return f"{tx}x{ty} tile, {w} wavefronts, {d} step(s) per launch"
 
 
 def cache_path() -> str:
@@ -118,9 +118,11 @@ def _valid(entry, n):
 def tune_solver(s: Solver, candidates=None, steps: int = 64, repeats: int = 3, use_cache: bool = True,
                 force: bool = False) -> TuneResult:
     """Pick the fastest tile shape for Solver s and set it.  The simulation's state (populations,
-    history, step count) is saved before timing and restored afterwards, bit for bit."""
+    history, step count) is saved before timing and restored afterwards, bit for bit.  Shapes
+    that do not fit the grid are not candidates."""
     n = len(shapes(s.precision))
     cands = list(range(n)) if candidates is None else [int(k) for k in candidates]
+    cands = [k for k in cands if shape_fits(s.prm, k, s.precision)]
     key = solver_key(s)
     path = cache_path()
     if use_cache and not force:
@@ -153,6 +155,7 @@ def tune_batch(b: Batch, candidates=None, steps: int = 64, repeats: int = 3, use
     prec = b.solvers[0].precision
     n = len(shapes(prec))
     cands = list(range(n)) if candidates is None else [int(k) for k in candidates]
+    cands = [k for k in cands if all(shape_fits(x.prm, k, prec) for x in b.solvers)]
     key = batch_key(b)
     path = cache_path()
     if use_cache and not force:

@@ -41,11 +41,12 @@ double pr_kappa(const lbm_params* p) {
   return 0.37464 + 1.54226 * w - 0.26992 * w * w;
 }
 
-// ---- tile shapes compiled into the library (tile height, wavefronts), per precision
+// ---- tile shapes compiled into the library (tile height, wavefronts, steps per launch), per
+// precision
 struct ShapeDef {
-  int ty, waves;
+  int ty, waves, depth;
 };
-#define LBM_SHAPE_DEF(k, ty, w) {ty, w},
+#define LBM_SHAPE_DEF(k, ty, w, d) {ty, w, d},
 constexpr ShapeDef F32_SHAPES[] = {LBM_F32_SHAPES(LBM_SHAPE_DEF)};
 constexpr ShapeDef F64_SHAPES[] = {LBM_F64_SHAPES(LBM_SHAPE_DEF)};
 #undef LBM_SHAPE_DEF
@@ -55,6 +56,14 @@ constexpr int N_F64_SHAPES = (int)(sizeof(F64_SHAPES) / sizeof(F64_SHAPES[0]));
 int shape_count(int precision) { return precision == LBM_FP64 ? N_F64_SHAPES : N_F32_SHAPES; }
 const ShapeDef& shape_def(int precision, int k) { return precision == LBM_FP64 ? F64_SHAPES[k] : F32_SHAPES[k]; }
 int tiles_of(int nx, int ny, int ty) { return ((nx + TX - 1) / TX) * ((ny + ty - 1) / ty); }
+
+// A two-step shape keeps a consistent image of its wide halo region in LDS only if no grid node
+// appears in it twice: the grid must be larger than the region in both directions.
+bool shape_fits(int precision, int k, int nx, int ny) {
+  const ShapeDef& d = shape_def(precision, k);
+  if (d.depth == 1) return true;
+  return nx >= TX + 2 * (HXW + 4) + 1 && ny >= d.ty + 2 * (HYW + 3) + 1;
+}
 
 // Shape used when none is requested: the 1-row-per-thread shape while the grid has fewer
 // tiles than about four per compute unit (the launch is a single wave of workgroups and its
@@ -89,8 +98,9 @@ struct lbm_ctx {
   InstDesc<double> desc64{};
   bool initialised = false;
   bool failed = false;
-  bool clock_dirty = false;
   int64_t steps = 0;
+  int gen = 0;           // 1 if the current state is in the B buffers
+  long long clock = 0;   // host mirror of the context's device clock (advanced by its own launches)
   double rho_ave = 0.0;
   double T_ref = 0.0;  // storage offset of g and the history (exact in the working precision)
   int shape_req = -1;  // requested tile shape (-1: chosen from the grid size)
@@ -104,6 +114,7 @@ struct lbm_batch {
   std::vector<lbm_ctx*> ctx;
   std::vector<int64_t> remaining;
   std::vector<int64_t> pending;  // steps enqueued since the last sync, per instance
+  std::vector<int64_t> pending_launches;  // launches that advanced each instance since the last sync
   hipStream_t stream = nullptr;
   int precision = 0;
   char* base = nullptr;
@@ -113,7 +124,6 @@ struct lbm_batch {
   long long clock = 0;           // host mirror of the device clock
   int total_tiles = 0;
   int shape = -1;                // tile shape of the batched launches (-1: from the first context)
-  bool table_dirty = true;
   hipGraphExec_t graph = nullptr;
   std::vector<lbm_ctx*> graph_layout;  // active instances (in table order) the graph was captured for
   int graph_shape = -1;                // tile shape the graph was captured with
@@ -191,7 +201,8 @@ static InstDesc<real> make_desc(lbm_ctx* h, int ty) {
   D.ntx = (h->prm.nx + TX - 1) / TX;
   D.nty = (h->prm.ny + ty - 1) / ty;
   D.tile_begin = 0;
-  D.t_start = 0;
+  D.b_base = 0;
+  D.t_base = 0;
   D.t_end = std::numeric_limits<long long>::max();
   D.p = derive<real>(&h->prm, h->rho_ave, h->T_ref);
   return D;
@@ -336,10 +347,9 @@ static lbm_status upload_desc(lbm_ctx* h) {
 }
 
 static lbm_status write_clock(lbm_ctx* h) {
-  long long c = (long long)h->steps;
+  long long c = h->clock;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_clock, &c, sizeof(c), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-  h->clock_dirty = false;
   return LBM_OK;
 }
 
@@ -378,6 +388,8 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
   unsigned zero = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
   h->steps = 0;
+  h->gen = 0;
+  h->clock = 0;
   lbm_status s = upload_desc(h);
   if (s != LBM_OK) return s;
   s = write_clock(h);
@@ -394,13 +406,13 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
 // one launch of the step kernel of tile shape `shape` over `grid` workgroups
 static void launch_step(int precision, int shape, int grid, hipStream_t st, const void* table, int ninst,
                         const long long* clk, int k) {
-#define LBM_LAUNCH_F32(kk, ty, w)                                                                         \
-  case kk:                                                                                                \
-    step_kernel<float, Shape<ty, w>><<<grid, 64 * w, 0, st>>>((const InstDesc<float>*)table, ninst, clk, k); \
+#define LBM_LAUNCH_F32(kk, ty, w, d)                                                                         \
+  case kk:                                                                                                   \
+    step_kernel<float, Shape<ty, w, d>><<<grid, 64 * w, 0, st>>>((const InstDesc<float>*)table, ninst, clk, k); \
     break;
-#define LBM_LAUNCH_F64(kk, ty, w)                                                                           \
-  case kk:                                                                                                  \
-    step_kernel<double, Shape<ty, w>><<<grid, 64 * w, 0, st>>>((const InstDesc<double>*)table, ninst, clk, k); \
+#define LBM_LAUNCH_F64(kk, ty, w, d)                                                                           \
+  case kk:                                                                                                     \
+    step_kernel<double, Shape<ty, w, d>><<<grid, 64 * w, 0, st>>>((const InstDesc<double>*)table, ninst, clk, k); \
     break;
   if (precision == LBM_FP64) {
     switch (shape) { LBM_F64_SHAPES(LBM_LAUNCH_F64) default: break; }
@@ -411,10 +423,12 @@ static void launch_step(int precision, int shape, int grid, hipStream_t st, cons
 #undef LBM_LAUNCH_F64
 }
 
+// n launches of the step kernel, then the clock advance by the steps they span
 static lbm_status launch_steps(lbm_ctx* h, int n) {
+  const int d = shape_def(h->prm.precision, h->shape).depth;
   for (int k = 0; k < n; ++k)
     launch_step(h->prm.precision, h->shape, h->ntiles, h->stream, h->d_desc, 1, h->d_clock, k);
-  clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n);
+  clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n * d);
   HIP_OR_FAIL(h, hipGetLastError());
   return LBM_OK;
 }
@@ -422,7 +436,7 @@ static lbm_status launch_steps(lbm_ctx* h, int n) {
 static lbm_status build_graph(lbm_ctx* h) {
   hipGraph_t g = nullptr;
   HIP_OR_FAIL(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  lbm_status s = launch_steps(h, GRAPH_STEPS);
+  lbm_status s = launch_steps(h, GRAPH_STEPS / shape_def(h->prm.precision, h->shape).depth);
   hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (s != LBM_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -444,26 +458,34 @@ lbm_status lbm_step(lbm_ctx* h, int64_t n) {
   if (h->failed) return fail(h, LBM_E_STATE, "context has failed: " + h->last_error);
   if (n == 0) return LBM_OK;
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
-  if (h->clock_dirty) {
-    lbm_status s = write_clock(h);
-    if (s != LBM_OK) return s;
-  }
-  int64_t left = n;
-  if (left >= GRAPH_STEPS && h->stream != nullptr) {  // the legacy null stream cannot be captured
+  // this call's window: steps [clock, clock + n) from the current buffers; a launch of a
+  // two-step shape does one step where only one is left
+  const int d = shape_def(h->prm.precision, h->shape).depth;
+  if (h->prm.precision == LBM_FP64)
+    set_window_kernel<double><<<1, 64, 0, h->stream>>>((InstDesc<double>*)h->d_desc, h->clock, h->gen, h->clock + n);
+  else
+    set_window_kernel<float><<<1, 64, 0, h->stream>>>((InstDesc<float>*)h->d_desc, h->clock, h->gen, h->clock + n);
+  HIP_OR_FAIL(h, hipGetLastError());
+  const int64_t launches = (n + d - 1) / d;
+  const int64_t per_graph = GRAPH_STEPS / d;
+  int64_t left = launches;
+  if (left >= per_graph && h->stream != nullptr) {  // the legacy null stream cannot be captured
     if (!h->graph) {
       lbm_status s = build_graph(h);
       if (s != LBM_OK) return s;
     }
-    while (left >= GRAPH_STEPS) {
+    while (left >= per_graph) {
       HIP_OR_FAIL(h, hipGraphLaunch(h->graph, h->stream));
-      left -= GRAPH_STEPS;
+      left -= per_graph;
     }
   }
   if (left > 0) {
     lbm_status s = launch_steps(h, (int)left);
     if (s != LBM_OK) return s;
   }
+  h->clock += (long long)launches * d;
   h->steps += n;
+  h->gen ^= (int)(launches & 1);
   return LBM_OK;
 }
 
@@ -474,17 +496,25 @@ int lbm_shape_count(int precision) {
   return shape_count(precision);
 }
 
-lbm_status lbm_shape_info(int precision, int k, int* tile_x, int* tile_y, int* waves) {
+lbm_status lbm_shape_info(int precision, int k, int* tile_x, int* tile_y, int* waves, int* steps_per_launch) {
   if ((precision != LBM_FP32 && precision != LBM_FP64) || k < 0 || k >= shape_count(precision)) return LBM_E_INVAL;
   const ShapeDef& d = shape_def(precision, k);
   if (tile_x) *tile_x = TX;
   if (tile_y) *tile_y = d.ty;
   if (waves) *waves = d.waves;
+  if (steps_per_launch) *steps_per_launch = d.depth;
   return LBM_OK;
+}
+
+int lbm_shape_fits(const lbm_params* p, int k) {
+  if (!p || lbm_validate(p) != LBM_OK || k < 0 || k >= shape_count(p->precision)) return 0;
+  return shape_fits(p->precision, k, p->nx, p->ny) ? 1 : 0;
 }
 
 lbm_status lbm_set_shape(lbm_ctx* h, int k) {
   if (!h || k < -1 || k >= shape_count(h->prm.precision)) return LBM_E_INVAL;
+  if (k >= 0 && !shape_fits(h->prm.precision, k, h->prm.nx, h->prm.ny))
+    return fail(h, LBM_E_INVAL, "two-step tile shape on a grid smaller than its halo region");
   h->shape_req = k;
   const int s = k < 0 ? default_shape(h->prm.precision, h->prm.nx, h->prm.ny) : k;
   if (s == h->shape) return LBM_OK;
@@ -496,7 +526,9 @@ lbm_status lbm_set_shape(lbm_ctx* h, int k) {
   }
   if (h->initialised) {
     if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
-    return upload_desc(h);  // ordered on the stream after the launches already enqueued
+    lbm_status st = upload_desc(h);  // ordered on the stream after the launches already enqueued
+    if (st != LBM_OK) return st;
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   }
   return LBM_OK;
 }
@@ -510,9 +542,9 @@ lbm_status lbm_sync(lbm_ctx* h) {
   return check_device_error(h);
 }
 
-// current source buffers (A after an even number of steps)
+// current source buffers (B after an odd number of launches)
 static void current_buffers(lbm_ctx* h, void*& f, void*& g, void*& fo) {
-  const bool odd = (h->steps & 1) != 0;
+  const bool odd = (h->gen & 1) != 0;
   f = odd ? h->fB : h->fA;
   g = odd ? h->gB : h->gA;
   fo = odd ? h->fA : h->fB;
@@ -602,6 +634,7 @@ lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
   std::memcpy(meta, q + 16 * N * r, sizeof(meta));
   if (meta[0] < 0) return fail(h, LBM_E_INVAL, "corrupt state: negative step count");
   h->steps = meta[0];
+  h->gen = 0;  // the state goes to the A buffers
   std::memcpy(&h->rho_ave, &meta[1], sizeof(double));
   std::memcpy(&h->T_ref, &meta[2], sizeof(double));
   void *f, *g, *fo;
@@ -747,6 +780,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   b->ctx.assign(ctxs, ctxs + n);
   b->remaining.assign(n, 0);
   b->pending.assign(n, 0);
+  b->pending_launches.assign(n, 0);
   b->stream = (hipStream_t)hip_stream;
   b->precision = prec;
   {
@@ -766,7 +800,6 @@ lbm_status lbm_batch_set_budget(lbm_batch* b, int i, int64_t steps) {
   if (!b || i < 0 || i >= (int)b->ctx.size() || steps < 0) return LBM_E_INVAL;
   if (b->ctx[i]->failed) return LBM_E_STATE;
   b->remaining[i] = steps;
-  b->table_dirty = true;
   return LBM_OK;
 }
 
@@ -777,15 +810,15 @@ int64_t lbm_batch_remaining(const lbm_batch* b, int i) {
 
 lbm_status lbm_batch_set_shape(lbm_batch* b, int k) {
   if (!b || k < -1 || k >= shape_count(b->precision)) return LBM_E_INVAL;
+  if (k >= 0)
+    for (lbm_ctx* h : b->ctx)
+      if (!shape_fits(b->precision, k, h->prm.nx, h->prm.ny)) return LBM_E_INVAL;
   if (k < 0) {
     long long tiles = 0;
     for (lbm_ctx* h : b->ctx) tiles += tiles_of(h->prm.nx, h->prm.ny, shape_def(b->precision, 0).ty);
     k = (b->precision == LBM_FP32 && tiles >= 1024) ? 1 : 0;
   }
-  if (k != b->shape) {
-    b->shape = k;
-    b->table_dirty = true;  // tile counts change; the graph is recaptured at the next upload
-  }
+  b->shape = k;  // tile counts change; the graph is recaptured at the next upload
   return LBM_OK;
 }
 
@@ -794,9 +827,10 @@ int lbm_batch_get_shape(const lbm_batch* b) { return b ? b->shape : -1; }
 }  // extern "C"
 
 // Table of the batch: active instances first (in the caller's order), then parked ones, so
-// that tile_begin is non-decreasing along the table as the kernel's binary search needs.
+// that tile_begin is non-decreasing along the table as the kernel's binary search needs.  Each
+// active instance runs min(todo, its budget) steps from the current clock.
 template <typename real>
-static void fill_table(lbm_batch* b, std::vector<InstDesc<real>>& tab) {
+static void fill_table(lbm_batch* b, std::vector<InstDesc<real>>& tab, int64_t todo) {
   const int n = (int)b->ctx.size();
   std::vector<int> order;
   for (int i = 0; i < n; ++i)
@@ -809,15 +843,16 @@ static void fill_table(lbm_batch* b, std::vector<InstDesc<real>>& tab) {
     const int i = order[j];
     lbm_ctx* h = b->ctx[i];
     InstDesc<real> D = make_desc<real>(h, shape_def(b->precision, b->shape).ty);
-    // parity continues from the context's own step count: clock - t_start = steps done
-    D.t_start = b->clock - (long long)(h->steps + b->pending[i]);
+    // buffers as left by the context's own steps and the batched launches not yet synced
+    D.t_base = b->clock;
+    D.b_base = (h->gen ^ (int)(b->pending_launches[i] & 1)) & 1;
     if (b->remaining[i] > 0) {
       D.tile_begin = tiles;
-      D.t_end = b->clock + (long long)b->remaining[i];
+      D.t_end = b->clock + std::min<int64_t>(todo, b->remaining[i]);
       tiles += D.ntx * D.nty;
     } else {
       D.tile_begin = -1;  // fixed up below: parked instances own no workgroups
-      D.t_end = D.t_start;
+      D.t_end = D.t_base;
     }
     tab[j] = D;
   }
@@ -828,25 +863,26 @@ static void fill_table(lbm_batch* b, std::vector<InstDesc<real>>& tab) {
 
 extern "C" {
 
-static lbm_status batch_upload(lbm_batch* b) {
+static lbm_status batch_upload(lbm_batch* b, int64_t todo) {
   lbm_ctx* h0 = b->ctx[0];
   const size_t n = b->ctx.size();
   long long c = b->clock;
   if (b->precision == LBM_FP64) {
     std::vector<InstDesc<double>> tab;
-    fill_table(b, tab);
+    fill_table(b, tab, todo);
     HIP_OR_FAIL(h0, hipMemcpyAsync(b->d_table, tab.data(), n * sizeof(tab[0]), hipMemcpyHostToDevice, b->stream));
     HIP_OR_FAIL(h0, hipMemcpyAsync(b->d_clock, &c, sizeof(c), hipMemcpyHostToDevice, b->stream));
     HIP_OR_FAIL(h0, hipStreamSynchronize(b->stream));
   } else {
     std::vector<InstDesc<float>> tab;
-    fill_table(b, tab);
+    fill_table(b, tab, todo);
     HIP_OR_FAIL(h0, hipMemcpyAsync(b->d_table, tab.data(), n * sizeof(tab[0]), hipMemcpyHostToDevice, b->stream));
     HIP_OR_FAIL(h0, hipMemcpyAsync(b->d_clock, &c, sizeof(c), hipMemcpyHostToDevice, b->stream));
     HIP_OR_FAIL(h0, hipStreamSynchronize(b->stream));
   }
-  // the captured launches depend only on the table address, the instance count and the grid size
-  // (total tiles of the active instances in table order); keep the graph while these are unchanged
+  // the captured launches depend only on the table address, the instance count, the grid size
+  // (total tiles of the active instances in table order) and the shape; keep the graph while
+  // these are unchanged
   std::vector<lbm_ctx*> layout;
   for (size_t i = 0; i < n; ++i)
     if (b->remaining[i] > 0) layout.push_back(b->ctx[i]);
@@ -856,14 +892,15 @@ static lbm_status batch_upload(lbm_batch* b) {
   }
   b->graph_layout = layout;
   b->graph_shape = b->shape;
-  b->table_dirty = false;
   return LBM_OK;
 }
 
-static lbm_status batch_launch(lbm_batch* b, int k) {
+// nl launches of the batch's step kernel, then the clock advance by the steps they span
+static lbm_status batch_launch(lbm_batch* b, int nl) {
   const int n = (int)b->ctx.size();
-  for (int s = 0; s < k; ++s) launch_step(b->precision, b->shape, b->total_tiles, b->stream, b->d_table, n, b->d_clock, s);
-  clock_advance_kernel<<<1, 64, 0, b->stream>>>(b->d_clock, (long long)k);
+  const int d = shape_def(b->precision, b->shape).depth;
+  for (int s = 0; s < nl; ++s) launch_step(b->precision, b->shape, b->total_tiles, b->stream, b->d_table, n, b->d_clock, s);
+  clock_advance_kernel<<<1, 64, 0, b->stream>>>(b->d_clock, (long long)nl * d);
   HIP_OR_FAIL(b->ctx[0], hipGetLastError());
   return LBM_OK;
 }
@@ -873,20 +910,22 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
   if (k == 0) return LBM_OK;
   lbm_ctx* h0 = b->ctx[0];
   // a member that failed was parked by lbm_batch_sync (budget 0): the others go on
-  if (b->table_dirty) {
-    lbm_status s = batch_upload(b);
-    if (s != LBM_OK) return s;
-  }
   int64_t maxrem = 0;
   for (int64_t r : b->remaining) maxrem = std::max(maxrem, r);
-  int64_t todo = std::min(k, maxrem);
-  if (todo == 0 || b->total_tiles == 0) return LBM_OK;
-  int64_t left = todo;
-  while (left >= GRAPH_STEPS && b->stream != nullptr) {
+  const int64_t todo = std::min(k, maxrem);
+  if (todo == 0) return LBM_OK;
+  lbm_status st = batch_upload(b, todo);  // every call: the step window of each instance
+  if (st != LBM_OK) return st;
+  if (b->total_tiles == 0) return LBM_OK;
+  const int d = shape_def(b->precision, b->shape).depth;
+  const int64_t launches = (todo + d - 1) / d;
+  const int64_t per_graph = GRAPH_STEPS / d;
+  int64_t left = launches;
+  while (left >= per_graph && b->stream != nullptr) {
     if (!b->graph) {
       hipGraph_t g = nullptr;
       HIP_OR_FAIL(h0, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-      lbm_status s = batch_launch(b, GRAPH_STEPS);
+      lbm_status s = batch_launch(b, (int)per_graph);
       hipError_t e = hipStreamEndCapture(b->stream, &g);
       if (s != LBM_OK) return s;
       if (e != hipSuccess) return fail(h0, LBM_E_DEVICE, "hipStreamEndCapture failed");
@@ -898,24 +937,19 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
       }
     }
     HIP_OR_FAIL(h0, hipGraphLaunch(b->graph, b->stream));
-    left -= GRAPH_STEPS;
+    left -= per_graph;
   }
   if (left > 0) {
     lbm_status s = batch_launch(b, (int)left);
     if (s != LBM_OK) return s;
   }
-  b->clock += todo;
+  b->clock += launches * d;
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     const int64_t ran = std::min<int64_t>(todo, b->remaining[i]);
     b->pending[i] += ran;
+    b->pending_launches[i] += (ran + d - 1) / d;
     b->remaining[i] -= ran;
   }
-  // instances whose budget ran out inside this call leave the launch at the next call
-  for (int64_t r : b->remaining)
-    if (r == 0) {
-      b->table_dirty = true;
-      break;
-    }
   return LBM_OK;
 }
 
@@ -927,15 +961,15 @@ lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status) {
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     lbm_ctx* h = b->ctx[i];
     h->steps += b->pending[i];
+    h->gen ^= (int)(b->pending_launches[i] & 1);
     b->pending[i] = 0;
-    h->clock_dirty = true;
+    b->pending_launches[i] = 0;
     unsigned e = 0;
     HIP_OR_FAIL(h, hipMemcpy(&e, h->d_err, sizeof(unsigned), hipMemcpyDeviceToHost));
     if (e) {
       h->failed = true;
       h->last_error = "numerical failure on the device (batched run)";
       b->remaining[i] = 0;
-      b->table_dirty = true;
       worst = LBM_E_NUMERIC;
     }
   }

@@ -26,17 +26,22 @@ constexpr int HYW = 2;        // halo rows per side (psi at radius 2 for div u)
 constexpr int EXW = TX + 2 * HXW;
 
 // Workgroup shape of the step kernel: a TX x TY_ tile updated by WAVES_ wavefronts of 64 lanes
-// along x; each thread owns RPT rows of its column.
-template <int TY_, int WAVES_>
+// along x, DEPTH_ time steps per launch; each thread owns RPT rows of its column.  A two-step
+// launch loads the wide region of MXH columns and MYH rows around the tile (MX x MY cells).
+template <int TY_, int WAVES_, int DEPTH_ = 1>
 struct Shape {
   static constexpr int TY = TY_;
   static constexpr int WAVES = WAVES_;
+  static constexpr int DEPTH = DEPTH_;
   static constexpr int NT = 64 * WAVES_;
   static constexpr int RPT = TY_ / WAVES_;
   static constexpr int EYW = TY_ + 2 * HYW;
   static constexpr int RING = EXW * EYW - TX * TY_;             // halo cells of the load region
   static constexpr int URING = (TX + 2) * (TY_ + 2) - TX * TY_;  // halo cells of the velocity region
+  static constexpr int MXH = HXW + 4, MYH = HYW + 3;
+  static constexpr int MX = TX + 2 * MXH, MY = TY_ + 2 * MYH;
   static_assert(RPT * WAVES_ == TY_, "rows per thread must divide the tile height");
+  static_assert(DEPTH_ == 1 || DEPTH_ == 2, "one or two steps per launch");
 };
 
 // error bits of the device error word
@@ -79,8 +84,8 @@ struct InstDesc {
   int nx, ny;
   int ntx, nty;        // tiles along x and y
   int tile_begin;      // first workgroup index of this instance in the launch
-  int pad;
-  long long t_start;   // clock value at which this instance had taken zero steps
+  int b_base;          // 1 if the current state is in the B buffers at clock t_base
+  long long t_base;    // clock value from which launches advance this instance
   long long t_end;     // clock value at which it stops
   DevParams<real> p;
 };
@@ -113,9 +118,6 @@ __device__ __forceinline__ int wrapi(int v, int n, bool tiny) {
   return v >= n ? v - n : v;
 }
 
-// Peng-Robinson pressure (Eq. 10): p = rho R T/(1 - b rho) - a phi(T) rho^2/(1 + 2 b rho - b^2 rho^2),
-// phi(T) = s^2, s = 1 + kappa (1 - sqrt(T/Tc)).  With the pressure also (dp/dT)_rho, where
-// dphi/dT = -kappa s / (Tc sqrt(T/Tc)).
 // Reciprocal square root: hardware instruction in FP32, IEEE-exact in FP64.
 __device__ __forceinline__ float frsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double frsqrt(double x) { return 1.0 / sqrt(x); }

@@ -1,7 +1,8 @@
 // The fused time step: one workgroup per TX x TY tile of one simulation.
 //
-// Phases (each separated by a workgroup barrier; the arithmetic of a node never depends on
-// where its tile lies, so a node's result is the same in a single run and in a batch):
+// One step (phases separated by workgroup barriers; the arithmetic of a node never depends on
+// where its tile lies or on the tile shape, so a node's result is the same in a single run, in a
+// batch and with any shape):
 //   1  load f and g of the tile plus a halo (HXW columns, HYW rows); per node rho, j, T
 //      (Eqs. 11, 25), 1/(rho c_v) and psi (Eq. 10 and the text after Eq. 9) into LDS; own nodes
 //      keep f, g and (dp/dT)_rho in registers.  Wall tiles then fill the ghost rows with the
@@ -13,40 +14,64 @@
 //      g (Eq. 39), push-streaming of f (Eq. 6, halfway bounce-back at walls) and of g with the
 //      rho c_v-weighted blend at the destination (Eq. 39; anti-bounce-back at Dirichlet edges).
 //
+// Two steps per launch (shapes with DEPTH 2, FP32): the workgroup loads a wider halo (MXH
+// columns, MYH rows), runs the first step on the tile plus the ring the second step reads, and
+// streams its result into LDS instead of HBM; the second step is the one-step body reading that
+// LDS state.  HBM traffic and the fixed cost of a launch are paid once per two steps.
+//
 // A workgroup has S::WAVES wavefronts of 64 lanes along x; each thread owns S::RPT rows of its
-// column (rows ty, ty + WAVES, ...).  The tile shape changes only which node a thread handles,
-// never the arithmetic of a node.
+// column (rows ty, ty + WAVES, ...).
 #pragma once
+#include <type_traits>
+
 #include "lbm_device.hpp"
 
 namespace lbm {
 
-template <typename real, int EYW>
-struct StepLds {
-  real rho[EYW][EXW];
-  real irc[EYW][EXW];  // 1 / (rho c_v), needed at the streaming destination
-  real psi[EYW][EXW];
-  real ux[EYW][EXW];   // holds j_x after phase 1, u_x after phase 2
-  real uy[EYW][EXW];
-  real g[4][EYW][EXW];  // pre-collision g_1..g_4 (needed at the streaming destination)
+// Per-node fields a step keeps in LDS, over a MY x MX region.
+template <typename real, int MY, int MX>
+struct MacroLds {
+  real rho[MY][MX];
+  real irc[MY][MX];  // 1 / (rho c_v), needed at the streaming destination
+  real psi[MY][MX];
+  real ux[MY][MX];   // holds j_x after phase 1, u_x after phase 2
+  real uy[MY][MX];
+  real g[4][MY][MX];  // pre-collision g_1..g_4 (needed at the streaming destination)
 };
 
-// position of halo cell r of the load region (ring around the TX x TY interior)
-template <class S>
+template <typename real, int EYW>
+using StepLds = MacroLds<real, EYW, EXW>;
+
+// LDS of a two-step launch: the first step's fields over the wide region, aliased by the second
+// step's fields once the first step has streamed; the state between the two steps (f and g
+// after the first step) over the second step's load region.
+template <typename real, class S>
+struct Step2Lds {
+  union {
+    MacroLds<real, S::MY, S::MX> m1;
+    StepLds<real, S::EYW> m2;
+  };
+  real sf[9][S::EYW][EXW];
+  real sg[5][S::EYW][EXW];
+};
+
+// Position of ring cell r of the region "tile plus hx columns and hy rows on each side":
+// hy full rows above, hy below, then the side columns of the tile rows.
+template <int TY_, int hx, int hy>
 __device__ __forceinline__ void ring_cell(int r, int& ex, int& ey) {
-  static_assert(HYW == 2, "the ring has two rows above and below the tile");
-  if (r < 2 * EXW) {
-    ey = r / EXW;
-    ex = r - ey * EXW;
-  } else if (r < 4 * EXW) {
-    const int q = r - 2 * EXW;
-    ey = S::EYW - 2 + q / EXW;
-    ex = q % EXW;
+  constexpr int W = TX + 2 * hx, H = TY_ + 2 * hy;
+  if (r < hy * W) {
+    ey = r / W;
+    ex = r - ey * W;
+  } else if (r < 2 * hy * W) {
+    const int q = r - hy * W;
+    ey = H - hy + q / W;
+    ex = q % W;
   } else {
-    const int q = r - 4 * EXW;
-    ey = HYW + q / (2 * HXW);
-    const int c = q % (2 * HXW);
-    ex = c < HXW ? c : TX + HXW + (c - HXW);
+    const int q = r - 2 * hy * W;
+    ey = hy + q / (2 * hx);
+    const int c = q % (2 * hx);
+    ex = c < hx ? c : TX + hx + (c - hx);
   }
 }
 
@@ -94,6 +119,8 @@ template <typename real>
 __device__ __forceinline__ void stb(gptr<char> base, unsigned off, real v) {
   *(gptr<real>)(base + off) = v;
 }
+
+// ------------------------------------------------------------------------- per-node arithmetic
 
 // rho, j, T of a node and its LDS entries (Eqs. 11 and 25), psi with error checks; returns
 // (dp/dT)_rho for the node's own collision
@@ -148,18 +175,177 @@ __device__ __forceinline__ void psi_stencil(const LDS& L, int ex, int ey, real& 
   sy = real(1.0 / 3.0) * (pN - pS) + real(1.0 / 12.0) * ((pNE + pNW) - (pSE + pSW));
 }
 
-// One tile.  INTERIOR tiles (load region entirely inside the grid, away from walls and
-// Dirichlet edges) need no index wrapping and no boundary tests; the general variant handles
-// periodic wrap, wall ghost rows, bounce-back and anti-bounce-back.  Both variants perform the
-// same arithmetic on every node.
-template <typename real, class S, bool INTERIOR>
-__device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real, S::EYW>& L, long long t, int x0,
-                                          int y0) {
+// Interaction force (Eq. 9), buoyancy, and velocity u = (j + F/2) / rho (Eq. 11) of the node at
+// (ex, ey); u replaces j in LDS.  S2 = |F_m|^2 / psi^2 of Li's correction (Eq. 8).
+template <typename real, class LDS>
+__device__ __forceinline__ void node_force_velocity(LDS& L, int ex, int ey, const DevParams<real>& p, bool freeze,
+                                                    real& Fx, real& Fy, real& S2) {
+  const real rho = L.rho[ey][ex];
+  real fx = real(0), fy = real(0), s2 = real(0);
+  if (!freeze) {
+    real sx, sy;
+    psi_stencil<real>(L, ex, ey, sx, sy);
+    const real c = -p.G * L.psi[ey][ex];
+    fx = c * sx + (rho - p.rho_ave) * p.gx;
+    fy = c * sy + (rho - p.rho_ave) * p.gy;
+    s2 = p.G * p.G * (sx * sx + sy * sy);
+  }
+  Fx = fx;
+  Fy = fy;
+  S2 = s2;
+  const real ir = L.irc[ey][ex] * p.cv;  // 1/rho
+  L.ux[ey][ex] = (L.ux[ey][ex] + real(0.5) * fx) * ir;
+  L.uy[ey][ex] = (L.uy[ey][ex] + real(0.5) * fy) * ir;
+}
+
+// div u = 3 sum_i w_i c_i . u(x + c_i); a ghost row carries -u of the fluid row next to it
+// (gs_: the node is on the bottom fluid row of a walled domain, gn_: on the top one)
+template <typename real, class LDS>
+__device__ __forceinline__ real node_divu(const LDS& L, int ex, int ey, bool gs_, bool gn_) {
+  const real uy = L.uy[ey][ex];
+  const real uxE = L.ux[ey][ex + 1], uxW = L.ux[ey][ex - 1];
+  const real uyN = gn_ ? -uy : L.uy[ey + 1][ex];
+  const real uyS = gs_ ? -uy : L.uy[ey - 1][ex];
+  const real uxNE = gn_ ? -uxE : L.ux[ey + 1][ex + 1], uyNE = gn_ ? -L.uy[ey][ex + 1] : L.uy[ey + 1][ex + 1];
+  const real uxNW = gn_ ? -uxW : L.ux[ey + 1][ex - 1], uyNW = gn_ ? -L.uy[ey][ex - 1] : L.uy[ey + 1][ex - 1];
+  const real uxSW = gs_ ? -uxW : L.ux[ey - 1][ex - 1], uySW = gs_ ? -L.uy[ey][ex - 1] : L.uy[ey - 1][ex - 1];
+  const real uxSE = gs_ ? -uxE : L.ux[ey - 1][ex + 1], uySE = gs_ ? -L.uy[ey][ex + 1] : L.uy[ey - 1][ex + 1];
+  return real(1.0 / 3.0) * ((uxE - uxW) + (uyN - uyS)) +
+         real(1.0 / 12.0) * (((uxNE - uxSW) + (uxSE - uxNW)) + ((uyNE - uySW) + (uyNW - uySE)));
+}
+
+// Collision of one node: grad T from m_1, m_2 of the D2Q5 populations (Eqs. 49-50), Q (Eq. 20),
+// S (Eq. 24), the D2Q9 MRT collision with Li's forcing and the D2Q5 MRT collision (Eq. 39).
+// Tr = T - T_ref of the node; T1, T2 are T(t-1) - T_ref and T(t-2) - T_ref.
+template <typename real>
+__device__ __forceinline__ void node_collide(const DevParams<real>& p, bool freeze, const real (&f)[9],
+                                             const real (&g)[5], real rho, real ux, real uy, real fx, real fy,
+                                             real S2, real dpdT, real divu, real T1, real T2, real (&fs_)[9],
+                                             real (&gs_)[5], real& Tr) {
+  Tr = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];  // T - T_ref
+  const real T = p.T_ref + Tr;
+  const real dTx = -p.vs1 * (g[1] - g[3]) * p.inv_cs2h;
+  const real dTy = -p.vs1 * (g[2] - g[4]) * p.inv_cs2h;
+  const real rcv = rho * p.cv;
+  const real Q = -(rcv * (ux * dTx + uy * dTy) + T * dpdT * divu);
+  const real Ssum = (p.flags & FL_NO_S) ? real(0) : rcv * real(0.5) * ((Tr - T1) - (T1 - T2));
+
+  // ---- D2Q9 MRT collision with Li's forcing, moments of the orthogonal basis of Eq. (4).
+  // Applied as a correction f* = f + M^-1 dm with dm = -S (m - m_eq) + (1 - S/2) F (Eq. 5):
+  // dm_0 = 0, so mass is conserved to rounding (no product of rho with a rounded 1/9).
+  if (freeze) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fs_[i] = f[i];
+  } else {
+    const real* fi = f;
+    const real sa = (fi[1] + fi[2]) + (fi[3] + fi[4]);
+    const real sd = (fi[5] + fi[6]) + (fi[7] + fi[8]);
+    const real m1 = -real(4) * fi[0] - sa + real(2) * sd;
+    const real m2 = real(4) * fi[0] - real(2) * sa + sd;
+    const real m4 = real(-2) * (fi[1] - fi[3]) + ((fi[5] - fi[6]) + (fi[8] - fi[7]));
+    const real m6 = real(-2) * (fi[2] - fi[4]) + ((fi[5] + fi[6]) - (fi[7] + fi[8]));
+    const real m7 = (fi[1] - fi[2]) + (fi[3] - fi[4]);
+    const real m8 = (fi[5] - fi[6]) + (fi[7] - fi[8]);
+    const real uu = ux * ux + uy * uy;
+    const real uF = ux * fx + uy * fy;
+    const real F1 = real(6) * uF + p.corr_e * S2;
+    const real F2 = -real(6) * uF - p.corr_eps * S2;
+    const real F7 = real(2) * (ux * fx - uy * fy);
+    const real F8 = ux * fy + uy * fx;
+    // m_eq of Eq. (7); the conserved moments j change by exactly F (s_j drops out)
+    const real d1 = -p.s_e * (m1 - rho * (real(-2) + real(3) * uu)) + (real(1) - real(0.5) * p.s_e) * F1;
+    const real d2 = -p.s_eps * (m2 - rho * (real(1) - real(3) * uu)) + (real(1) - real(0.5) * p.s_eps) * F2;
+    const real d4 = -p.s_q * (m4 + rho * ux) - (real(1) - real(0.5) * p.s_q) * fx;
+    const real d6 = -p.s_q * (m6 + rho * uy) - (real(1) - real(0.5) * p.s_q) * fy;
+    const real d7 = -p.s_p * (m7 - rho * (ux * ux - uy * uy)) + (real(1) - real(0.5) * p.s_p) * F7;
+    const real d8 = -p.s_p * (m8 - rho * ux * uy) + (real(1) - real(0.5) * p.s_p) * F8;
+    // M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+    const real b1 = d1 * real(1.0 / 36.0), b2 = d2 * real(1.0 / 36.0);
+    const real c3 = fx * real(1.0 / 6.0), c4 = d4 * real(1.0 / 12.0);
+    const real c5 = fy * real(1.0 / 6.0), c6 = d6 * real(1.0 / 12.0);
+    const real e7 = d7 * real(0.25), e8 = d8 * real(0.25);
+    const real axis = -b1 - real(2) * b2;
+    const real diag = real(2) * b1 + b2;
+    const real cx_ = c3 - real(2) * c4, cy_ = c5 - real(2) * c6;
+    const real dx_ = c3 + c4, dy_ = c5 + c6;
+    fs_[0] = fi[0] + (real(4) * (b2 - b1));
+    fs_[1] = fi[1] + ((axis + cx_) + e7);
+    fs_[2] = fi[2] + ((axis + cy_) - e7);
+    fs_[3] = fi[3] + ((axis - cx_) + e7);
+    fs_[4] = fi[4] + ((axis - cy_) - e7);
+    fs_[5] = fi[5] + ((diag + (dx_ + dy_)) + e8);
+    fs_[6] = fi[6] + ((diag - (dx_ - dy_)) - e8);
+    fs_[7] = fi[7] + ((diag - (dx_ + dy_)) + e8);
+    fs_[8] = fi[8] + ((diag + (dx_ - dy_)) - e8);
+  }
+
+  // ---- D2Q5 MRT collision (Eq. 39) with the non-orthogonal basis of Eq. (40)
+  {
+    const real* gi = g;
+    const real dm1 = p.vs1 * (gi[1] - gi[3]);
+    const real dm2 = p.vs1 * (gi[2] - gi[4]);
+    const real dm3 = p.vs3 * (((gi[1] + gi[2]) + (gi[3] + gi[4])) - p.wdot * Tr);
+    const real dm4 = p.vs4 * ((gi[1] - gi[2]) + (gi[3] - gi[4]));
+    const real src = Q + Ssum;
+    const real q34p = real(0.25) * (dm3 + dm4), q34m = real(0.25) * (dm3 - dm4);
+    gs_[0] = gi[0] + dm3 + p.w0h * src;
+    gs_[1] = gi[1] - (q34p + real(0.5) * dm1) + p.w1h * src;
+    gs_[3] = gi[3] - (q34p - real(0.5) * dm1) + p.w1h * src;
+    gs_[2] = gi[2] - (q34m + real(0.5) * dm2) + p.w1h * src;
+    gs_[4] = gi[4] - (q34m - real(0.5) * dm2) + p.w1h * src;
+  }
+}
+
+// Wetting ghost rows of an LDS region whose cell (0, 0) is the grid node (ox, oy):
+// psi at the ghost node from rho_0 = rho_2 + tan(pi/2 - theta) |rho_{x+1,1} - rho_{x-1,1}|
+// (Eq. 54) at the wall temperature.  Returns true if the region holds a ghost row (the caller
+// then needs a barrier).
+template <typename real, int W, int H, class LDS, class WX>
+__device__ __forceinline__ bool ghost_rows(LDS& L, const DevParams<real>& p, int ox, int oy, int ny, int tid, int nt,
+                                           WX wx, unsigned& err) {
+  const int eyb = -1 - oy;  // LDS row of y = -1
+  const int eyt = ny - oy;  // LDS row of y = ny
+  const bool hasb = eyb >= 0 && eyb < H, hast = eyt >= 0 && eyt < H;
+  if (!(hasb || hast)) return false;
+  for (int c = tid; c < 2 * W; c += nt) {
+    const int top = c >= W;
+    const int ex = c - top * W;
+    const int ey = top ? eyt : eyb;
+    if ((top ? hast : hasb) && ex >= 1 && ex <= W - 2) {
+      const int d = top ? -1 : 1;  // towards the fluid
+      const real tanv = top ? p.tan_top : p.tan_bot;
+      const real rg = L.rho[ey + 2 * d][ex] + tanv * fabs(L.rho[ey + d][ex + 1] - L.rho[ey + d][ex - 1]);
+      const real Tw = wall_temperature(p, top, wx(ox + ex));
+      L.psi[ey][ex] = pseudo(p, rg, Tw, err);
+    }
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------------- one step
+
+// Where the one-step body takes f and g from: the global A/B buffers, or the LDS state left by
+// the first step of a two-step launch (with the temperature history handed over in registers).
+template <typename real, class S>
+struct LdsState {
+  const real (*sf)[S::EYW][EXW];
+  const real (*sg)[S::EYW][EXW];
+  const real* T1;  // per own row: T(t-1) - T_ref, T(t-2) - T_ref after the first step
+  const real* T2;
+};
+
+// One step of one tile.  INTERIOR tiles (load region entirely inside the grid, away from walls
+// and Dirichlet edges) need no index wrapping and no boundary tests; the general variant
+// handles periodic wrap, wall ghost rows, bounce-back and anti-bounce-back.  Both variants
+// perform the same arithmetic on every node.  FROM_LDS: f and g come from `st` (second step of
+// a two-step launch) instead of the global source buffers.
+template <typename real, class S, bool INTERIOR, bool FROM_LDS>
+__device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real, S::EYW>& L, bool odd, int x0, int y0,
+                                          const LdsState<real, S>& st, unsigned& err) {
   constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, RING = S::RING, URING = S::URING, EYW = S::EYW;
   const int nx = D.nx, ny = D.ny;
   constexpr ptrdiff_t SZ = sizeof(real);
   const ptrdiff_t PB = (ptrdiff_t)nx * (ptrdiff_t)ny * SZ;  // bytes per plane
-  const bool odd = ((t - D.t_start) & 1) != 0;
   const gptr<const char> fs = (gptr<const char>)to_global<const real>(odd ? D.fB : D.fA);
   const gptr<const char> gs = (gptr<const char>)to_global<const real>(odd ? D.gB : D.gA);
   const gptr<char> fd = (gptr<char>)to_global<real>(odd ? D.fA : D.fB);
@@ -174,7 +360,6 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real,
   const int tid = threadIdx.x;
   const int tx = tid & (TX - 1);
   const int ty = tid >> 6;
-  unsigned err = 0u;
 
   auto wx = [&](int v) { return INTERIOR ? v : wrapi(v, nx, tiny); };
   auto wy = [&](int v) { return (INTERIOR || walls) ? v : wrapi(v, ny, tiny); };
@@ -196,15 +381,25 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real,
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int yg = y0 + ty + WAVES * r;
+    const int ey = HYW + ty + WAVES * r;
     own[r] = fluid_row(yg);
     ob[r] = (unsigned)(wy(yg) * nx + xw) * (unsigned)SZ;
     if (own[r]) {
+      if (FROM_LDS) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) f[r][i] = ldb<real>(fsp(i), ob[r]);
+        for (int i = 0; i < 9; ++i) f[r][i] = st.sf[i][ey][HXW + tx];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) g[r][i] = ldb<real>(gsp(i), ob[r]);
-      T1[r] = ldb<real>(Th, ob[r]);
-      T2[r] = ldb<real>(sbase(Th + PB), ob[r]);
+        for (int i = 0; i < 5; ++i) g[r][i] = st.sg[i][ey][HXW + tx];
+        T1[r] = st.T1[r];
+        T2[r] = st.T2[r];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[r][i] = ldb<real>(fsp(i), ob[r]);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) g[r][i] = ldb<real>(gsp(i), ob[r]);
+        T1[r] = ldb<real>(Th, ob[r]);
+        T2[r] = ldb<real>(sbase(Th + PB), ob[r]);
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[r][i] = real(0);
@@ -220,15 +415,22 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real,
   for (int q = 0; q < RPN; ++q) {
     const int r = tid + q * NT;
     rin[q] = r < RING;
-    ring_cell<S>(rin[q] ? r : 0, rex[q], rey[q]);
+    ring_cell<S::TY, HXW, HYW>(rin[q] ? r : 0, rex[q], rey[q]);
     const int yg = y0 - HYW + rey[q];
     rfl[q] = rin[q] && fluid_row(yg);
     if (rfl[q]) {
-      const unsigned o = (unsigned)(wy(yg) * nx + wx(x0 - HXW + rex[q])) * (unsigned)SZ;
+      if (FROM_LDS) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) fr[q][i] = ldb<real>(fsp(i), o);
+        for (int i = 0; i < 9; ++i) fr[q][i] = st.sf[i][rey[q]][rex[q]];
 #pragma unroll
-      for (int i = 0; i < 5; ++i) gr[q][i] = ldb<real>(gsp(i), o);
+        for (int i = 0; i < 5; ++i) gr[q][i] = st.sg[i][rey[q]][rex[q]];
+      } else {
+        const unsigned o = (unsigned)(wy(yg) * nx + wx(x0 - HXW + rex[q])) * (unsigned)SZ;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) fr[q][i] = ldb<real>(fsp(i), o);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) gr[q][i] = ldb<real>(gsp(i), o);
+      }
     }
   }
 #pragma unroll
@@ -245,26 +447,9 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real,
   }
   __syncthreads();
 
-  // ---- phase 1b: wetting ghost rows, rho_0 = rho_2 + tan(pi/2 - theta) |rho_{x+1,1} - rho_{x-1,1}|
+  // ---- phase 1b: wetting ghost rows
   if (!INTERIOR && walls) {
-    const int eyb = -1 - (y0 - HYW);  // LDS row of y = -1
-    const int eyt = ny - (y0 - HYW);  // LDS row of y = ny
-    const bool hasb = eyb >= 0 && eyb < EYW, hast = eyt >= 0 && eyt < EYW;
-    if (hasb || hast) {
-      for (int c = tid; c < 2 * EXW; c += NT) {
-        const int top = c >= EXW;
-        const int ex = c - top * EXW;
-        const int ey = top ? eyt : eyb;
-        if ((top ? hast : hasb) && ex >= 1 && ex <= EXW - 2) {
-          const int d = top ? -1 : 1;  // towards the fluid
-          const real tanv = top ? p.tan_top : p.tan_bot;
-          const real rg = L.rho[ey + 2 * d][ex] + tanv * fabs(L.rho[ey + d][ex + 1] - L.rho[ey + d][ex - 1]);
-          const real Tw = wall_temperature(p, top, wx(x0 - HXW + ex));
-          L.psi[ey][ex] = pseudo(p, rg, Tw, err);
-        }
-      }
-      __syncthreads();
-    }
+    if (ghost_rows<real, EXW, EYW>(L, p, x0 - HXW, y0 - HYW, ny, tid, NT, wx, err)) __syncthreads();
   }
 
   // ---- phase 2: forces and velocity on the tile plus one node
@@ -272,43 +457,16 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real,
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int ex = HXW + tx, ey = HYW + ty + WAVES * r;
-    const int yg = y0 + ty + WAVES * r;
     Fx[r] = Fy[r] = S2[r] = real(0);
-    if (fluid_row(yg)) {
-      const real rho = L.rho[ey][ex];
-      real fx = real(0), fy = real(0);
-      if (!freeze) {
-        real sx, sy;
-        psi_stencil<real>(L, ex, ey, sx, sy);
-        const real c = -p.G * L.psi[ey][ex];
-        fx = c * sx + (rho - p.rho_ave) * p.gx;
-        fy = c * sy + (rho - p.rho_ave) * p.gy;
-        S2[r] = p.G * p.G * (sx * sx + sy * sy);  // |F_m|^2 / psi^2 of Li's correction (Eq. 8)
-      }
-      Fx[r] = fx;
-      Fy[r] = fy;
-      const real ir = L.irc[ey][ex] * p.cv;  // 1/rho
-      L.ux[ey][ex] = (L.ux[ey][ex] + real(0.5) * fx) * ir;
-      L.uy[ey][ex] = (L.uy[ey][ex] + real(0.5) * fy) * ir;
-    }
+    if (own[r]) node_force_velocity<real>(L, ex, ey, p, freeze, Fx[r], Fy[r], S2[r]);
   }
   for (int r = tid; r < URING; r += NT) {
     int ex, ey;
     uring_cell<S>(r, ex, ey);
     const int yg = y0 - HYW + ey;
     if (fluid_row(yg)) {
-      const real rho = L.rho[ey][ex];
-      real fx = real(0), fy = real(0);
-      if (!freeze) {
-        real sx, sy;
-        psi_stencil<real>(L, ex, ey, sx, sy);
-        const real c = -p.G * L.psi[ey][ex];
-        fx = c * sx + (rho - p.rho_ave) * p.gx;
-        fy = c * sy + (rho - p.rho_ave) * p.gy;
-      }
-      const real ir = L.irc[ey][ex] * p.cv;
-      L.ux[ey][ex] = (L.ux[ey][ex] + real(0.5) * fx) * ir;
-      L.uy[ey][ex] = (L.uy[ey][ex] + real(0.5) * fy) * ir;
+      real fx, fy, s2;
+      node_force_velocity<real>(L, ex, ey, p, freeze, fx, fy, s2);
     }
   }
   __syncthreads();
@@ -321,101 +479,13 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real,
     if (!INTERIOR && (xg >= nx || yg >= ny)) continue;
     const real rho = L.rho[ey][ex];
     const real ux = L.ux[ey][ex], uy = L.uy[ey][ex];
-    const real Tr = ((g[r][0] + g[r][1]) + (g[r][2] + g[r][3])) + g[r][4];  // T - T_ref
-    const real T = p.T_ref + Tr;
     const unsigned o = ob[r];
-
-    // div u = 3 sum_i w_i c_i . u(x + c_i); a ghost row carries -u of the fluid row next to it
-    real divu;
-    {
-      const bool gs_ = walls && yg == 0, gn_ = walls && yg == ny - 1;
-      const real uxE = L.ux[ey][ex + 1], uxW = L.ux[ey][ex - 1];
-      const real uyN = gn_ ? -uy : L.uy[ey + 1][ex];
-      const real uyS = gs_ ? -uy : L.uy[ey - 1][ex];
-      const real uxNE = gn_ ? -uxE : L.ux[ey + 1][ex + 1], uyNE = gn_ ? -L.uy[ey][ex + 1] : L.uy[ey + 1][ex + 1];
-      const real uxNW = gn_ ? -uxW : L.ux[ey + 1][ex - 1], uyNW = gn_ ? -L.uy[ey][ex - 1] : L.uy[ey + 1][ex - 1];
-      const real uxSW = gs_ ? -uxW : L.ux[ey - 1][ex - 1], uySW = gs_ ? -L.uy[ey][ex - 1] : L.uy[ey - 1][ex - 1];
-      const real uxSE = gs_ ? -uxE : L.ux[ey - 1][ex + 1], uySE = gs_ ? -L.uy[ey][ex + 1] : L.uy[ey - 1][ex + 1];
-      divu = real(1.0 / 3.0) * ((uxE - uxW) + (uyN - uyS)) +
-             real(1.0 / 12.0) * (((uxNE - uxSW) + (uxSE - uxNW)) + ((uyNE - uySW) + (uyNW - uySE)));
-    }
-
-    // grad T from m_1, m_2 of the D2Q5 populations (Eqs. 49-50)
-    const real dTx = -p.vs1 * (g[r][1] - g[r][3]) * p.inv_cs2h;
-    const real dTy = -p.vs1 * (g[r][2] - g[r][4]) * p.inv_cs2h;
-    const real rcv = rho * p.cv;
-    const real Q = -(rcv * (ux * dTx + uy * dTy) + T * dpdT[r] * divu);
-    const real Ssum = (p.flags & FL_NO_S) ? real(0) : rcv * real(0.5) * ((Tr - T1[r]) - (T1[r] - T2[r]));
+    const real divu = node_divu<real>(L, ex, ey, walls && yg == 0, walls && yg == ny - 1);
+    real fs_[9], gs_[5], Tr;
+    node_collide<real>(p, freeze, f[r], g[r], rho, ux, uy, Fx[r], Fy[r], S2[r], dpdT[r], divu, T1[r], T2[r], fs_,
+                       gs_, Tr);
     stb(Th, o, Tr);
     stb(sbase(Th + PB), o, T1[r]);
-
-    // ---- D2Q9 MRT collision with Li's forcing, moments of the orthogonal basis of Eq. (4).
-    // Applied as a correction f* = f + M^-1 dm with dm = -S (m - m_eq) + (1 - S/2) F (Eq. 5):
-    // dm_0 = 0, so mass is conserved to rounding (no product of rho with a rounded 1/9).
-    real fs_[9];
-    if (freeze) {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) fs_[i] = f[r][i];
-    } else {
-      const real* fi = f[r];
-      const real sa = (fi[1] + fi[2]) + (fi[3] + fi[4]);
-      const real sd = (fi[5] + fi[6]) + (fi[7] + fi[8]);
-      const real m1 = -real(4) * fi[0] - sa + real(2) * sd;
-      const real m2 = real(4) * fi[0] - real(2) * sa + sd;
-      const real m4 = real(-2) * (fi[1] - fi[3]) + ((fi[5] - fi[6]) + (fi[8] - fi[7]));
-      const real m6 = real(-2) * (fi[2] - fi[4]) + ((fi[5] + fi[6]) - (fi[7] + fi[8]));
-      const real m7 = (fi[1] - fi[2]) + (fi[3] - fi[4]);
-      const real m8 = (fi[5] - fi[6]) + (fi[7] - fi[8]);
-      const real uu = ux * ux + uy * uy;
-      const real fx = Fx[r], fy = Fy[r];
-      const real uF = ux * fx + uy * fy;
-      const real F1 = real(6) * uF + p.corr_e * S2[r];
-      const real F2 = -real(6) * uF - p.corr_eps * S2[r];
-      const real F7 = real(2) * (ux * fx - uy * fy);
-      const real F8 = ux * fy + uy * fx;
-      // m_eq of Eq. (7); the conserved moments j change by exactly F (s_j drops out)
-      const real d1 = -p.s_e * (m1 - rho * (real(-2) + real(3) * uu)) + (real(1) - real(0.5) * p.s_e) * F1;
-      const real d2 = -p.s_eps * (m2 - rho * (real(1) - real(3) * uu)) + (real(1) - real(0.5) * p.s_eps) * F2;
-      const real d4 = -p.s_q * (m4 + rho * ux) - (real(1) - real(0.5) * p.s_q) * fx;
-      const real d6 = -p.s_q * (m6 + rho * uy) - (real(1) - real(0.5) * p.s_q) * fy;
-      const real d7 = -p.s_p * (m7 - rho * (ux * ux - uy * uy)) + (real(1) - real(0.5) * p.s_p) * F7;
-      const real d8 = -p.s_p * (m8 - rho * ux * uy) + (real(1) - real(0.5) * p.s_p) * F8;
-      // M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-      const real b1 = d1 * real(1.0 / 36.0), b2 = d2 * real(1.0 / 36.0);
-      const real c3 = fx * real(1.0 / 6.0), c4 = d4 * real(1.0 / 12.0);
-      const real c5 = fy * real(1.0 / 6.0), c6 = d6 * real(1.0 / 12.0);
-      const real e7 = d7 * real(0.25), e8 = d8 * real(0.25);
-      const real axis = -b1 - real(2) * b2;
-      const real diag = real(2) * b1 + b2;
-      const real cx_ = c3 - real(2) * c4, cy_ = c5 - real(2) * c6;
-      const real dx_ = c3 + c4, dy_ = c5 + c6;
-      fs_[0] = fi[0] + (real(4) * (b2 - b1));
-      fs_[1] = fi[1] + ((axis + cx_) + e7);
-      fs_[2] = fi[2] + ((axis + cy_) - e7);
-      fs_[3] = fi[3] + ((axis - cx_) + e7);
-      fs_[4] = fi[4] + ((axis - cy_) - e7);
-      fs_[5] = fi[5] + ((diag + (dx_ + dy_)) + e8);
-      fs_[6] = fi[6] + ((diag - (dx_ - dy_)) - e8);
-      fs_[7] = fi[7] + ((diag - (dx_ + dy_)) + e8);
-      fs_[8] = fi[8] + ((diag + (dx_ - dy_)) - e8);
-    }
-
-    // ---- D2Q5 MRT collision (Eq. 39) with the non-orthogonal basis of Eq. (40)
-    real gs_[5];
-    {
-      const real* gi = g[r];
-      const real dm1 = p.vs1 * (gi[1] - gi[3]);
-      const real dm2 = p.vs1 * (gi[2] - gi[4]);
-      const real dm3 = p.vs3 * (((gi[1] + gi[2]) + (gi[3] + gi[4])) - p.wdot * Tr);
-      const real dm4 = p.vs4 * ((gi[1] - gi[2]) + (gi[3] - gi[4]));
-      const real src = Q + Ssum;
-      const real q34p = real(0.25) * (dm3 + dm4), q34m = real(0.25) * (dm3 - dm4);
-      gs_[0] = gi[0] + dm3 + p.w0h * src;
-      gs_[1] = gi[1] - (q34p + real(0.5) * dm1) + p.w1h * src;
-      gs_[3] = gi[3] - (q34p - real(0.5) * dm1) + p.w1h * src;
-      gs_[2] = gi[2] - (q34m + real(0.5) * dm2) + p.w1h * src;
-      gs_[4] = gi[4] - (q34m - real(0.5) * dm2) + p.w1h * src;
-    }
 
     // ---- streaming.  Interior tiles: a neighbour's byte offset differs from the node's by a
     // uniform amount, folded into the plane base.  Other tiles: wrapped offsets of the eight
@@ -514,19 +584,195 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>& D, StepLds<real,
       }
     }
   }
-
-  // A failing simulation flags every node.  One atomic per thread, or even per wavefront, on one
-  // word would serialise the launch, so a wavefront ORs its flags with ballots and sets only the
-  // bits the word does not hold yet.
-  const unsigned long long e1 = __ballot((err & ERR_RHO) != 0u), e2 = __ballot((err & ERR_T) != 0u),
-                           e4 = __ballot((err & ERR_PSI) != 0u);
-  if ((e1 | e2 | e4) != 0ull && (threadIdx.x & 63u) == 0u) {
-    const unsigned bits = (e1 ? ERR_RHO : 0u) | (e2 ? ERR_T : 0u) | (e4 ? ERR_PSI : 0u);
-    const unsigned held = __hip_atomic_load(D.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((held & bits) != bits) atomicOr(D.err, bits);
-  }
 }
 
+// ------------------------------------------------------------------------- two steps
+
+// First step of a two-step launch on the region the second step reads.  Region names, as
+// offsets around the tile (columns, rows): the first step loads M (MXH, MYH) = (HXW + 4, HYW + 3),
+// computes forces and velocities on C+1 = (HXW + 2, HYW + 2), collides C = (HXW + 1, HYW + 1),
+// and streams into the state arrays over the second step's load region (HXW, HYW).  Pushes that
+// leave that region are dropped; every kept slot is written exactly once.
+template <typename real, class S, bool INTERIOR>
+__device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<real, S>& L, bool odd, int x0, int y0,
+                                           real (&Tn1)[S::RPT], real (&Tn2)[S::RPT], unsigned& err) {
+  constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, MX = S::MX, MY = S::MY, MXH = S::MXH, MYH = S::MYH;
+  constexpr int MRING = MX * MY - TX * S::TY;
+  constexpr int RPN = (MRING + NT - 1) / NT;
+  constexpr int DX = MXH - HXW, DY = MYH - HYW;  // state cell (sx, sy) = M cell (sx + DX, sy + DY)
+  const int nx = D.nx, ny = D.ny;
+  constexpr ptrdiff_t SZ = sizeof(real);
+  const ptrdiff_t PB = (ptrdiff_t)nx * (ptrdiff_t)ny * SZ;
+  const gptr<const char> fs = (gptr<const char>)to_global<const real>(odd ? D.fB : D.fA);
+  const gptr<const char> gs = (gptr<const char>)to_global<const real>(odd ? D.gB : D.gA);
+  const gptr<const char> Th = (gptr<const char>)to_global<const real>(D.Th);
+  const DevParams<real> p = D.p;
+  const int walls = INTERIOR ? 0 : p.y_walls;
+  const bool tb = INTERIOR ? false : p.thermal_box != 0;
+  const bool freeze = (p.flags & FL_FREEZE_FLOW) != 0;
+  const bool tiny = nx < MX + 1 || ny < MY + 1;
+
+  const int tid = threadIdx.x;
+  const int tx = tid & (TX - 1);
+  const int ty = tid >> 6;
+
+  auto wx = [&](int v) { return INTERIOR ? v : wrapi(v, nx, tiny); };
+  auto wy = [&](int v) { return (INTERIOR || walls) ? v : wrapi(v, ny, tiny); };
+  auto fluid_row = [&](int y) { return INTERIOR || row_kind(y, ny, walls) == 0; };
+  auto fsp = [&](int i) { return sbase(fs + i * PB); };
+  auto gsp = [&](int i) { return sbase(gs + i * PB); };
+  auto in_c = [](int mx, int my) { return mx >= MXH - HXW - 1 && mx < MX - (MXH - HXW - 1) && my >= MYH - HYW - 1 &&
+                                          my < MY - (MYH - HYW - 1); };
+  auto in_u = [](int mx, int my) { return mx >= MXH - HXW - 2 && mx < MX - (MXH - HXW - 2) && my >= MYH - HYW - 2 &&
+                                          my < MY - (MYH - HYW - 2); };
+
+  // nodes of this thread: RPT own rows, then RPN cells of the ring of M
+  constexpr int NN = RPT + RPN;
+  real f[NN][9], g[NN][5], T1[NN], T2[NN], dpdT[NN];
+  int mx_[NN], my_[NN];
+  bool valid[NN], fl[NN];
+#pragma unroll
+  for (int n = 0; n < NN; ++n) {
+    if (n < RPT) {
+      mx_[n] = MXH + tx;
+      my_[n] = MYH + ty + WAVES * n;
+      valid[n] = true;
+    } else {
+      const int r = tid + (n - RPT) * NT;
+      valid[n] = r < MRING;
+      ring_cell<S::TY, MXH, MYH>(valid[n] ? r : 0, mx_[n], my_[n]);
+    }
+    const int xgl = x0 - MXH + mx_[n], ygl = y0 - MYH + my_[n];
+    fl[n] = valid[n] && fluid_row(ygl);
+    T1[n] = T2[n] = real(0);
+    if (fl[n]) {
+      const unsigned o = (unsigned)(wy(ygl) * nx + wx(xgl)) * (unsigned)SZ;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) f[n][i] = ldb<real>(fsp(i), o);
+#pragma unroll
+      for (int i = 0; i < 5; ++i) g[n][i] = ldb<real>(gsp(i), o);
+      if (in_c(mx_[n], my_[n])) {
+        T1[n] = ldb<real>(Th, o);
+        T2[n] = ldb<real>(sbase(Th + PB), o);
+      }
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NN; ++n) {
+    dpdT[n] = real(0);
+    if (fl[n]) dpdT[n] = node_macro_to_lds<real>(L.m1, mx_[n], my_[n], p, f[n], g[n], err);
+    else if (valid[n]) zero_lds_cell<real>(L.m1, mx_[n], my_[n]);
+  }
+  __syncthreads();
+
+  if (!INTERIOR && walls) {
+    if (ghost_rows<real, MX, MY>(L.m1, p, x0 - MXH, y0 - MYH, ny, tid, NT, wx, err)) __syncthreads();
+  }
+
+  real Fx[NN], Fy[NN], S2[NN];
+#pragma unroll
+  for (int n = 0; n < NN; ++n) {
+    Fx[n] = Fy[n] = S2[n] = real(0);
+    if (fl[n] && in_u(mx_[n], my_[n])) node_force_velocity<real>(L.m1, mx_[n], my_[n], p, freeze, Fx[n], Fy[n], S2[n]);
+  }
+  __syncthreads();
+
+  // collision of C and streaming into the state arrays
+  auto in_s = [](int sx, int sy) { return sx >= 0 && sx < EXW && sy >= 0 && sy < S::EYW; };
+#pragma unroll
+  for (int n = 0; n < NN; ++n) {
+    const int mx = mx_[n], my = my_[n];
+    if (!fl[n] || !in_c(mx, my)) continue;
+    const int xw = wx(x0 - MXH + mx), yw = wy(y0 - MYH + my);  // node of the grid (wrapped image)
+    const real rho = L.m1.rho[my][mx];
+    const real ux = L.m1.ux[my][mx], uy = L.m1.uy[my][mx];
+    const real divu = node_divu<real>(L.m1, mx, my, walls && yw == 0, walls && yw == ny - 1);
+    real fs_[9], gs_[5], Tr;
+    node_collide<real>(p, freeze, f[n], g[n], rho, ux, uy, Fx[n], Fy[n], S2[n], dpdT[n], divu, T1[n], T2[n], fs_, gs_,
+                       Tr);
+    if (n < RPT) {  // own node: history after this step
+      Tn1[n] = Tr;
+      Tn2[n] = T1[n];
+    }
+    const int sx = mx - DX, sy = my - DY;
+    auto putf = [&](int i, int dx, int dy, real v) {
+      if (in_s(sx + dx, sy + dy)) L.sf[i][sy + dy][sx + dx] = v;
+    };
+    auto putg = [&](int i, int dx, int dy, real v) {
+      if (in_s(sx + dx, sy + dy)) L.sg[i][sy + dy][sx + dx] = v;
+    };
+    const bool wall_n = walls && yw == ny - 1, wall_s = walls && yw == 0;
+    if (freeze) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) putf(i, 0, 0, fs_[i]);
+    } else {
+      putf(0, 0, 0, fs_[0]);
+      putf(1, 1, 0, fs_[1]);
+      putf(3, -1, 0, fs_[3]);
+      if (wall_n) {
+        putf(4, 0, 0, fs_[2]);
+        putf(7, 0, 0, fs_[5]);
+        putf(8, 0, 0, fs_[6]);
+      } else {
+        putf(2, 0, 1, fs_[2]);
+        putf(5, 1, 1, fs_[5]);
+        putf(6, -1, 1, fs_[6]);
+      }
+      if (wall_s) {
+        putf(2, 0, 0, fs_[4]);
+        putf(5, 0, 0, fs_[7]);
+        putf(6, 0, 0, fs_[8]);
+      } else {
+        putf(4, 0, -1, fs_[4]);
+        putf(7, -1, -1, fs_[7]);
+        putf(8, 1, -1, fs_[8]);
+      }
+    }
+    const real ircv = L.m1.irc[my][mx];
+    putg(0, 0, 0, g[n][0] + (gs_[0] - g[n][0]) * ircv);
+    const bool out_e = tb && xw == nx - 1, out_w = tb && xw == 0;
+    const bool out_n = (walls || tb) && yw == ny - 1, out_s = (walls || tb) && yw == 0;
+    const real two_w = real(2) * p.w1h;
+    if (out_e) {
+      const real up = -gs_[1] + two_w * (p.T_box - p.T_ref);
+      putg(3, 0, 0, g[n][3] + (up - g[n][3]) * ircv);
+    } else {
+      const real gold = L.m1.g[0][my][mx + 1];
+      putg(1, 1, 0, gold + (gs_[1] - gold) * L.m1.irc[my][mx + 1]);
+    }
+    if (out_w) {
+      const real up = -gs_[3] + two_w * (p.T_box - p.T_ref);
+      putg(1, 0, 0, g[n][1] + (up - g[n][1]) * ircv);
+    } else {
+      const real gold = L.m1.g[2][my][mx - 1];
+      putg(3, -1, 0, gold + (gs_[3] - gold) * L.m1.irc[my][mx - 1]);
+    }
+    if (out_n) {
+      const real Tn = tb ? p.T_box : p.T_top;
+      const real up = -gs_[2] + two_w * (Tn - p.T_ref);
+      putg(4, 0, 0, g[n][4] + (up - g[n][4]) * ircv);
+    } else {
+      const real gold = L.m1.g[1][my + 1][mx];
+      putg(2, 0, 1, gold + (gs_[2] - gold) * L.m1.irc[my + 1][mx]);
+    }
+    if (out_s) {
+      const real Ts = tb ? p.T_box : wall_temperature(p, 0, xw);
+      const real up = -gs_[4] + two_w * (Ts - p.T_ref);
+      putg(2, 0, 0, g[n][2] + (up - g[n][2]) * ircv);
+    } else {
+      const real gold = L.m1.g[3][my - 1][mx];
+      putg(4, 0, -1, gold + (gs_[4] - gold) * L.m1.irc[my - 1][mx]);
+    }
+  }
+  __syncthreads();  // state complete; the fields of the first step are dead (m2 aliases them)
+}
+
+// ------------------------------------------------------------------------- kernel
+
+// One workgroup per tile.  A launch of shape S advances every active instance by S::DEPTH steps
+// (one step if only one is left in its budget).  The device clock counts steps; the launch's
+// step is t = clock + k DEPTH.  Each launch swaps the A/B buffers once, so the source buffer is
+// B exactly when b_base plus the number of launches since t_base is odd.
 template <typename real, class S>
 __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __restrict__ table, int ninst,
                                                      const long long* __restrict__ clock, int k) {
@@ -545,30 +791,74 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
     else hi = mid - 1;
   }
   const InstDesc<real>& D = table[lo];
-  const long long t = *clock + k;
-  if (t < D.t_start || t >= D.t_end) return;
+  const long long t = *clock + (long long)k * S::DEPTH;
+  if (t < D.t_base || t >= D.t_end) return;
   const int tile = bid - D.tile_begin;
   if (tile < 0 || tile >= D.ntx * D.nty) return;
   const int by = tile / D.ntx;
   const int bx = tile - by * D.ntx;
   const int x0 = bx * TX, y0 = by * S::TY;
-  __shared__ StepLds<real, S::EYW> L;
-  // interior: the load region [x0-HXW, x0+TX+HXW) x [y0-HYW, y0+TY+HYW) lies inside the grid,
-  // so no wrap, ghost row, wall or Dirichlet edge is involved
+  const bool odd = ((D.b_base + (t - D.t_base) / S::DEPTH) & 1) != 0;
+  unsigned err = 0u;
+  // interior: the load region lies inside the grid, so no wrap, ghost row, wall or Dirichlet
+  // edge is involved
   const bool interior = x0 >= HXW && x0 + TX + HXW <= D.nx && y0 >= HYW && y0 + S::TY + HYW <= D.ny;
-  if (interior) step_tile<real, S, true>(D, L, t, x0, y0);
-  else step_tile<real, S, false>(D, L, t, x0, y0);
+  const LdsState<real, S> none{};
+  if constexpr (S::DEPTH == 2) {
+    __shared__ Step2Lds<real, S> L2;
+    if (D.t_end - t >= 2) {
+      real Tn1[S::RPT], Tn2[S::RPT];
+      const bool interior2 =
+          x0 >= S::MXH && x0 + TX + S::MXH <= D.nx && y0 >= S::MYH && y0 + S::TY + S::MYH <= D.ny;
+      if (interior2) first_step<real, S, true>(D, L2, odd, x0, y0, Tn1, Tn2, err);
+      else first_step<real, S, false>(D, L2, odd, x0, y0, Tn1, Tn2, err);
+      const LdsState<real, S> st{L2.sf, L2.sg, Tn1, Tn2};
+      if (interior) step_body<real, S, true, true>(D, L2.m2, odd, x0, y0, st, err);
+      else step_body<real, S, false, true>(D, L2.m2, odd, x0, y0, st, err);
+    } else {
+      if (interior) step_body<real, S, true, false>(D, L2.m2, odd, x0, y0, none, err);
+      else step_body<real, S, false, false>(D, L2.m2, odd, x0, y0, none, err);
+    }
+  } else {
+    __shared__ StepLds<real, S::EYW> L;
+    if (interior) step_body<real, S, true, false>(D, L, odd, x0, y0, none, err);
+    else step_body<real, S, false, false>(D, L, odd, x0, y0, none, err);
+  }
+  // A failing simulation flags every node.  One atomic per thread, or even per wavefront, on one
+  // word would serialise the launch, so a wavefront ORs its flags with ballots and sets only the
+  // bits the word does not hold yet.
+  const unsigned long long e1 = __ballot((err & ERR_RHO) != 0u), e2 = __ballot((err & ERR_T) != 0u),
+                           e4 = __ballot((err & ERR_PSI) != 0u);
+  if ((e1 | e2 | e4) != 0ull && (threadIdx.x & 63u) == 0u) {
+    const unsigned bits = (e1 ? ERR_RHO : 0u) | (e2 ? ERR_T : 0u) | (e4 ? ERR_PSI : 0u);
+    const unsigned held = __hip_atomic_load(D.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((held & bits) != bits) atomicOr(D.err, bits);
+  }
 }
 
-// Tile shapes compiled into the library, per precision: (tile height, wavefronts).  Index 0 is
-// the shape for small grids, index 1 the one for grids of many tiles; the others are candidates
-// for the autotuner.  All shapes give bit-identical results.
-#define LBM_F32_SHAPES(X) X(0, 16, 16) X(1, 16, 8) X(2, 8, 8) X(3, 32, 16) X(4, 8, 4) X(5, 4, 4)
-#define LBM_F64_SHAPES(X) X(0, 16, 8) X(1, 8, 8) X(2, 16, 16) X(3, 8, 4) X(4, 4, 4)
+// Tile shapes compiled into the library, per precision: (tile height, wavefronts, steps per
+// launch).  Index 0 is the shape for small grids, index 1 the one for grids of many tiles; the
+// others are candidates for the autotuner.  All shapes give bit-identical results.  Two-step
+// shapes need the grid to be larger than their wide halo region (lbm_shape_info reports it).
+#define LBM_F32_SHAPES(X) \
+  X(0, 16, 16, 1) X(1, 16, 8, 1) X(2, 8, 8, 1) X(3, 32, 16, 1) X(4, 8, 4, 1) X(5, 4, 4, 1) X(6, 16, 16, 2) X(7, 8, 8, 2)
+#define LBM_F64_SHAPES(X) X(0, 16, 8, 1) X(1, 8, 8, 1) X(2, 16, 16, 1) X(3, 8, 4, 1) X(4, 4, 4, 1)
 
 // Clock advance after a group of step launches (a kernel, so that it can live in a graph).
 __global__ void clock_advance_kernel(long long* clock, long long n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] = clock[0] + n;
+}
+
+// Step window of a single run, set on its stream before the call's launches: steps
+// [t_base, t_end) of the clock, starting from the B buffers if b_base is 1.  (A kernel takes its
+// arguments at enqueue, so no host buffer has to outlive the call.)
+template <typename real>
+__global__ void set_window_kernel(InstDesc<real>* d, long long t_base, int b_base, long long t_end) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    d->t_base = t_base;
+    d->b_base = b_base;
+    d->t_end = t_end;
+  }
 }
 
 }  // namespace lbm

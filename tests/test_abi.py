@@ -125,17 +125,34 @@ def test_tile_shapes_api(L):
         assert n >= 4
         got = shapes(prec)
         assert len(got) == n
-        for tx, ty, w in got:
-            assert tx == 64 and ty % w == 0 and 1 <= w <= 16 and ty in (4, 8, 16, 32)
+        for tx, ty, w, d in got:
+            assert tx == 64 and ty % w == 0 and 1 <= w <= 16 and ty in (4, 8, 16, 32) and d in (1, 2)
         assert len(set(got)) == n
-        tx, ty, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        assert L.lbm_shape_info(prec, n, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(w)) == -1
-        assert L.lbm_shape_info(prec, -1, None, None, None) == -1
-        assert L.lbm_shape_info(prec, 0, None, None, None) == 0
+        assert got[0][3] == 1 and (prec == 1) == all(d == 1 for *_, d in got)  # two-step shapes: FP32 only
+        tx, ty, w, d = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        assert L.lbm_shape_info(prec, n, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(w), ctypes.byref(d)) == -1
+        assert L.lbm_shape_info(prec, -1, None, None, None, None) == -1
+        assert L.lbm_shape_info(prec, 0, None, None, None, None) == 0
     assert L.lbm_shape_count(7) == 0
-    assert L.lbm_shape_info(7, 0, None, None, None) == -1
+    assert L.lbm_shape_info(7, 0, None, None, None, None) == -1
     # contexts and batches: NULL handles are rejected without touching a device
     assert L.lbm_set_shape(None, 0) == -1
     assert L.lbm_get_shape(None) == -1
     assert L.lbm_batch_set_shape(None, 0) == -1
     assert L.lbm_batch_get_shape(None) == -1
+
+
+def test_two_step_shapes_need_a_grid_larger_than_their_halo(L):
+    from paper_2205_00686_amd import _native, shape_fits, shapes
+    from workloads import Params
+    two = [k for k, s in enumerate(shapes(0)) if s[3] == 2]
+    assert two
+    for k in two:
+        ty = shapes(0)[k][1]
+        assert shape_fits(Params(nx=79, ny=ty + 11), k)
+        assert not shape_fits(Params(nx=78, ny=ty + 11), k)
+        assert not shape_fits(Params(nx=79, ny=ty + 10), k)
+    assert all(shape_fits(Params(nx=3, ny=3), k) for k, s in enumerate(shapes(0)) if s[3] == 1)
+    p = _native.LbmParams()
+    L.lbm_params_default(ctypes.byref(p), 2, 64)  # invalid parameters
+    assert L.lbm_shape_fits(ctypes.byref(p), 0) == 0

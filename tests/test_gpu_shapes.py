@@ -53,8 +53,24 @@ def test_every_shape_gives_identical_bits(lbm, sat):
     for name, w, prec, n in _cases(sat, lbm):
         ref = _run(lbm, w, prec, n, 0)
         for k in range(1, len(lbm.shapes(prec))):
+            if not lbm.shape_fits(w.params, k, prec):
+                continue
             print(f"\n[case] {name} shape {k} {lbm.shapes(prec)[k]}", flush=True)
             assert _run(lbm, w, prec, n, k) == ref, (name, k)
+            assert _run(lbm, w, prec, n + 1, k) == _run(lbm, w, prec, n + 1, 0), (name, k, "odd")
+
+
+def test_two_step_shape_rejected_on_small_grid(lbm, sat):
+    Tc, rl, rg = sat
+    w = droplet(Tc, rl, rg, nx=40, ny=36, R=9.0)
+    two = [k for k, sh in enumerate(lbm.shapes(lbm.LBM_FP32)) if sh[3] == 2]
+    s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    for k in two:
+        assert not lbm.shape_fits(w.params, k)
+        with pytest.raises(lbm.LbmError) as e:
+            s.set_shape(k)
+        assert e.value.status == -1
+    s.close()
 
 
 def test_shape_change_mid_run(lbm, sat):
@@ -64,27 +80,38 @@ def test_shape_change_mid_run(lbm, sat):
     s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
     assert s.shape in range(len(lbm.shapes(lbm.LBM_FP32)))
     s.set_shape(3).step(70)
+    s.set_shape(6).step(33)   # two steps per launch, odd count: the last launch does one
     s.set_shape(4).step(3)
-    s.set_shape(-1).step(77)
+    s.set_shape(7).step(1)
+    s.set_shape(6).step(2)
+    s.set_shape(-1).step(41)
     s.sync()
+    assert s.steps == 150
     assert s.save_state() == ref
     s.close()
 
 
 def test_batch_shapes_give_identical_bits(lbm, sat):
-    cases = [c for c in _cases(sat, lbm) if c[2] == lbm.LBM_FP32]
-    alone = [_run(lbm, w, prec, 90, 0) for _, w, prec, _ in cases]
+    Tc, rl, rg = sat
+    ws = [evaporation(Tc, rl, rg, nx=200, ny=130, R=30.0),
+          boiling(Tc, rl, rg, nx=300, ny=200, hot_width=10.0, gravity=3e-5),
+          droplet(Tc, rl, rg, nx=96, ny=80, R=20.0)]
+    budgets = [91, 60, 33]  # uneven and odd: two-step launches end some members with one step
+    alone = [_run(lbm, w, lbm.LBM_FP32, n, 0) for w, n in zip(ws, budgets)]
     for k in range(len(lbm.shapes(lbm.LBM_FP32))):
         print(f"\n[case] batch shape {k}", flush=True)
-        sol = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for _, w, _, _ in cases]
+        sol = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for w in ws]
         b = lbm.Batch(sol).set_shape(k)
         assert b.shape == k
-        for i in range(len(sol)):
-            b.set_budget(i, 90)
-        b.step(90)
+        for i, n in enumerate(budgets):
+            b.set_budget(i, n)
+        b.step(45)
+        b.step(7)
+        b.step(100)
         assert b.sync() == [0] * len(sol)
         b.close()
-        for s, ref in zip(sol, alone):
+        for s, ref, n in zip(sol, alone, budgets):
+            assert s.steps == n
             assert s.save_state() == ref, k
             s.close()
 
