@@ -3,7 +3,8 @@
 Workload: droplet evaporation in open space -- 512 x 512 grid, FP32 populations, droplet of
 radius 64 at the Maxwell densities of T_sat = 0.86 Tc in saturated vapour, box edges held at
 1.1 T_sat, initial T uniform at T_sat, periodic flow.  One benchmark step is one time step of the
-whole coupled D2Q9 + D2Q5 update (one fused kernel launch) over the grid.
+whole coupled D2Q9 + D2Q5 update over the grid (fused kernels, one or two steps per launch as the
+autotuned tile shape has it).
 
 Prints one JSON line: MLUPS over the timed steps, the roofline of the step kernel (algorithmic
 128 bytes per node update in FP32 divided by the kernel's average duration from HIP events on

@@ -184,6 +184,13 @@ static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref)
   d.thermal_box = p->thermal_box ? 1 : 0;
   d.flags = p->flags;
   d.T_ref = (real)T_ref;
+  d.om_e = (real)(1.0 - 0.5 * p->s_e);
+  d.om_eps = (real)(1.0 - 0.5 * p->s_eps);
+  d.om_q = (real)(1.0 - 0.5 * p->s_q);
+  d.om_p = (real)(1.0 - 0.5 / (3.0 * p->nu + 0.5));
+  d.opk = (real)(1.0 + pr_kappa(p));
+  d.GG = (real)(p->G * p->G);
+  d.two_w1h = (real)(p->wdot / 2.0);
   return d;
 }
 

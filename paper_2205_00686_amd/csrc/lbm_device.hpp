@@ -66,6 +66,10 @@ struct DevParams {
   real T_box, T_top, T_bot, hot_dT, hot_x0, inv_2s2;
   real tan_bot, tan_top;            // tan(pi/2 - theta) of the wetting rule (Eq. 54)
   real T_ref;                       // g and the history are stored relative to T_ref (see below)
+  // Derived on the host: without scalar floating-point units, a constant computed in the kernel
+  // costs a vector instruction per wavefront, as much as per-node arithmetic.
+  real om_e, om_eps, om_q, om_p;    // 1 - s/2 of the forcing term (Eq. 5)
+  real opk, GG, two_w1h;            // 1 + kappa; G^2; 2 w_1
   int y_walls, thermal_box;
   unsigned flags;
   int pad;
@@ -130,15 +134,15 @@ template <typename real>
 __device__ __forceinline__ void pr_eos(const DevParams<real>& p, real rho, real T, real& press, real& dpdT) {
   const real rs = frsqrt(T * p.Tc);  // 1/sqrt(T Tc)
   const real sq = T * rs;            // sqrt(T/Tc)
-  const real s = real(1) + p.kappa * (real(1) - sq);
+  const real s = p.opk - p.kappa * sq;
   const real br = p.b * rho;
   const real den1 = real(1) - br;
   const real den2 = real(1) + br * (real(2) - br);
   const real i12 = rcp(den1 * den2);
-  const real i1 = den2 * i12, i2 = den1 * i12;
-  const real rr = rho * rho;
-  press = rho * p.R * T * i1 - p.a * s * s * rr * i2;
-  dpdT = rho * p.R * i1 + p.a * p.kappa * s * rs * rr * i2;
+  const real rRi1 = rho * p.R * (den2 * i12);       // rho R / (1 - b rho)
+  const real t = p.a * s * (rho * rho) * (den1 * i12);  // a s rho^2 / (1 + 2 b rho - b^2 rho^2)
+  press = rRi1 * T - s * t;
+  dpdT = rRi1 + p.kappa * rs * t;
 }
 
 template <typename real>

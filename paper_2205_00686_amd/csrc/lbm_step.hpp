@@ -55,24 +55,37 @@ struct Step2Lds {
   real sg[5][S::EYW][EXW];
 };
 
-// Position of ring cell r of the region "tile plus hx columns and hy rows on each side":
-// hy full rows above, hy below, then the side columns of the tile rows.
-template <int TY_, int hx, int hy>
-__device__ __forceinline__ void ring_cell(int r, int& ex, int& ey) {
-  constexpr int W = TX + 2 * hx, H = TY_ + 2 * hy;
-  if (r < hy * W) {
+// Cells of the rectangular annulus between "tile plus (ai, bi)" and "tile plus (ao, bo)"
+// (columns, rows on each side of the TX x TY_ tile).
+template <int TY_, int ai, int bi, int ao, int bo>
+constexpr int annulus_cells() {
+  return (TX + 2 * ao) * (TY_ + 2 * bo) - (TX + 2 * ai) * (TY_ + 2 * bi);
+}
+
+// Position of cell r of that annulus, relative to the outer rectangle's corner: the top rows,
+// the bottom rows, then the side columns of the rows in between.
+template <int TY_, int ai, int bi, int ao, int bo>
+__device__ __forceinline__ void annulus_cell(int r, int& ex, int& ey) {
+  constexpr int W = TX + 2 * ao, H = TY_ + 2 * bo, tx = ao - ai, ty = bo - bi;
+  if (r < ty * W) {
     ey = r / W;
     ex = r - ey * W;
-  } else if (r < 2 * hy * W) {
-    const int q = r - hy * W;
-    ey = H - hy + q / W;
+  } else if (r < 2 * ty * W) {
+    const int q = r - ty * W;
+    ey = H - ty + q / W;
     ex = q % W;
   } else {
-    const int q = r - 2 * hy * W;
-    ey = hy + q / (2 * hx);
-    const int c = q % (2 * hx);
-    ex = c < hx ? c : TX + hx + (c - hx);
+    const int q = r - 2 * ty * W;
+    ey = ty + q / (2 * tx);
+    const int c = q % (2 * tx);
+    ex = c < tx ? c : W - tx + (c - tx);
   }
+}
+
+// Ring cell r of the region "tile plus hx columns and hy rows on each side"
+template <int TY_, int hx, int hy>
+__device__ __forceinline__ void ring_cell(int r, int& ex, int& ey) {
+  annulus_cell<TY_, 0, 0, hx, hy>(r, ex, ey);
 }
 
 // position of halo cell r of the velocity region (one node around the interior)
@@ -188,7 +201,7 @@ __device__ __forceinline__ void node_force_velocity(LDS& L, int ex, int ey, cons
     const real c = -p.G * L.psi[ey][ex];
     fx = c * sx + (rho - p.rho_ave) * p.gx;
     fy = c * sy + (rho - p.rho_ave) * p.gy;
-    s2 = p.G * p.G * (sx * sx + sy * sy);
+    s2 = p.GG * (sx * sx + sy * sy);
   }
   Fx = fx;
   Fy = fy;
@@ -224,8 +237,10 @@ __device__ __forceinline__ void node_collide(const DevParams<real>& p, bool free
                                              real (&gs_)[5], real& Tr) {
   Tr = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];  // T - T_ref
   const real T = p.T_ref + Tr;
-  const real dTx = -p.vs1 * (g[1] - g[3]) * p.inv_cs2h;
-  const real dTy = -p.vs1 * (g[2] - g[4]) * p.inv_cs2h;
+  const real dm1 = p.vs1 * (g[1] - g[3]);  // relaxed non-equilibrium parts of m_1, m_2 (Eq. 39)
+  const real dm2 = p.vs1 * (g[2] - g[4]);
+  const real dTx = -dm1 * p.inv_cs2h;
+  const real dTy = -dm2 * p.inv_cs2h;
   const real rcv = rho * p.cv;
   const real Q = -(rcv * (ux * dTx + uy * dTy) + T * dpdT * divu);
   const real Ssum = (p.flags & FL_NO_S) ? real(0) : rcv * real(0.5) * ((Tr - T1) - (T1 - T2));
@@ -253,12 +268,12 @@ __device__ __forceinline__ void node_collide(const DevParams<real>& p, bool free
     const real F7 = real(2) * (ux * fx - uy * fy);
     const real F8 = ux * fy + uy * fx;
     // m_eq of Eq. (7); the conserved moments j change by exactly F (s_j drops out)
-    const real d1 = -p.s_e * (m1 - rho * (real(-2) + real(3) * uu)) + (real(1) - real(0.5) * p.s_e) * F1;
-    const real d2 = -p.s_eps * (m2 - rho * (real(1) - real(3) * uu)) + (real(1) - real(0.5) * p.s_eps) * F2;
-    const real d4 = -p.s_q * (m4 + rho * ux) - (real(1) - real(0.5) * p.s_q) * fx;
-    const real d6 = -p.s_q * (m6 + rho * uy) - (real(1) - real(0.5) * p.s_q) * fy;
-    const real d7 = -p.s_p * (m7 - rho * (ux * ux - uy * uy)) + (real(1) - real(0.5) * p.s_p) * F7;
-    const real d8 = -p.s_p * (m8 - rho * ux * uy) + (real(1) - real(0.5) * p.s_p) * F8;
+    const real d1 = -p.s_e * (m1 - rho * (real(-2) + real(3) * uu)) + p.om_e * F1;
+    const real d2 = -p.s_eps * (m2 - rho * (real(1) - real(3) * uu)) + p.om_eps * F2;
+    const real d4 = -p.s_q * (m4 + rho * ux) - p.om_q * fx;
+    const real d6 = -p.s_q * (m6 + rho * uy) - p.om_q * fy;
+    const real d7 = -p.s_p * (m7 - rho * (ux * ux - uy * uy)) + p.om_p * F7;
+    const real d8 = -p.s_p * (m8 - rho * ux * uy) + p.om_p * F8;
     // M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
     const real b1 = d1 * real(1.0 / 36.0), b2 = d2 * real(1.0 / 36.0);
     const real c3 = fx * real(1.0 / 6.0), c4 = d4 * real(1.0 / 12.0);
@@ -282,8 +297,6 @@ __device__ __forceinline__ void node_collide(const DevParams<real>& p, bool free
   // ---- D2Q5 MRT collision (Eq. 39) with the non-orthogonal basis of Eq. (40)
   {
     const real* gi = g;
-    const real dm1 = p.vs1 * (gi[1] - gi[3]);
-    const real dm2 = p.vs1 * (gi[2] - gi[4]);
     const real dm3 = p.vs3 * (((gi[1] + gi[2]) + (gi[3] + gi[4])) - p.wdot * Tr);
     const real dm4 = p.vs4 * ((gi[1] - gi[2]) + (gi[3] - gi[4]));
     const real src = Q + Ssum;
@@ -547,7 +560,7 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
       stb(gdp(0), o, g[r][0] + (gs_[0] - g[r][0]) * ircv);
       const bool out_e = tb && xg == nx - 1, out_w = tb && xg == 0;
       const bool out_n = (walls || tb) && yg == ny - 1, out_s = (walls || tb) && yg == 0;
-      const real two_w = real(2) * p.w1h;
+      const real two_w = p.two_w1h;
       if (out_e) {
         const real up = -gs_[1] + two_w * (p.T_box - p.T_ref);
         stb(gdp(3), o, g[r][3] + (up - g[r][3]) * ircv);
@@ -732,7 +745,7 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
     putg(0, 0, 0, g[n][0] + (gs_[0] - g[n][0]) * ircv);
     const bool out_e = tb && xw == nx - 1, out_w = tb && xw == 0;
     const bool out_n = (walls || tb) && yw == ny - 1, out_s = (walls || tb) && yw == 0;
-    const real two_w = real(2) * p.w1h;
+    const real two_w = p.two_w1h;
     if (out_e) {
       const real up = -gs_[1] + two_w * (p.T_box - p.T_ref);
       putg(3, 0, 0, g[n][3] + (up - g[n][3]) * ircv);
