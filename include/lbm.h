@@ -90,8 +90,9 @@ void lbm_params_default(lbm_params* p, int32_t nx, int32_t ny);
    or lambda <= 0. */
 lbm_status lbm_validate(const lbm_params* p);
 
-/* Exact device bytes a context needs (populations f and g in two copies, the temperature
-   history, and a small control block); 0 if lbm_validate fails. */
+/* Exact device bytes a context needs (populations f and g and the temperature history, each
+   in two copies, and a small control block: 128 B per node in FP32, 256 in FP64, plus 48 KiB);
+   0 if lbm_validate fails. */
 size_t lbm_footprint_bytes(const lbm_params* p);
 
 /* Create a context on the current HIP device over caller-owned device memory dev_mem of

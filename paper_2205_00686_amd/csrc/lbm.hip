@@ -65,12 +65,15 @@ bool shape_fits(int precision, int k, int nx, int ny) {
   return nx >= TX + 2 * (HXW + 4) + 1 && ny >= d.ty + 2 * (HYW + 3) + 1;
 }
 
-// Shape used when none is requested: the 1-row-per-thread shape while the grid has fewer
-// tiles than about four per compute unit (the launch is a single wave of workgroups and its
-// latency matters), the 2-rows-per-thread shape (two workgroups resident per compute unit)
-// beyond.  The autotuner replaces this guess by a measurement.
+// Shape used when none is requested.  FP32: the two-step 64 x 16 shape where the grid is
+// large enough for it (it halves the HBM traffic and the fixed cost of a launch per step);
+// otherwise the 1-row-per-thread shape while the grid has fewer tiles than about four per compute
+// unit (a single wave of workgroups, whose latency matters), the 2-rows-per-thread shape beyond.
+// The autotuner replaces this guess by a measurement.
+constexpr int F32_TWO_STEP_DEFAULT = 6;
 int default_shape(int precision, int nx, int ny) {
   if (precision == LBM_FP64) return 0;
+  if (shape_fits(precision, F32_TWO_STEP_DEFAULT, nx, ny)) return F32_TWO_STEP_DEFAULT;
   return tiles_of(nx, ny, F32_SHAPES[0].ty) >= 1024 ? 1 : 0;
 }
 
@@ -88,7 +91,8 @@ struct lbm_ctx {
   void* gA = nullptr;
   void* fB = nullptr;
   void* gB = nullptr;
-  void* Th = nullptr;
+  void* ThA = nullptr;
+  void* ThB = nullptr;
   long long* d_clock = nullptr;
   unsigned* d_err = nullptr;
   double* d_diag = nullptr;
@@ -128,6 +132,19 @@ struct lbm_batch {
   std::vector<lbm_ctx*> graph_layout;  // active instances (in table order) the graph was captured for
   int graph_shape = -1;                // tile shape the graph was captured with
 };
+
+// Default shape of a batch: the two-step shape if every member fits it, else by total size.
+static int batch_default_shape(int precision, const std::vector<lbm_ctx*>& ctx) {
+  if (precision == LBM_FP64) return 0;
+  bool fit = true;
+  long long tiles = 0;
+  for (const lbm_ctx* h : ctx) {
+    fit = fit && shape_fits(precision, F32_TWO_STEP_DEFAULT, h->prm.nx, h->prm.ny);
+    tiles += tiles_of(h->prm.nx, h->prm.ny, F32_SHAPES[0].ty);
+  }
+  if (fit) return F32_TWO_STEP_DEFAULT;
+  return tiles >= 1024 ? 1 : 0;
+}
 
 // ------------------------------------------------------------------------------ helpers
 static lbm_status fail(lbm_ctx* h, lbm_status s, const std::string& msg) {
@@ -201,7 +218,8 @@ static InstDesc<real> make_desc(lbm_ctx* h, int ty) {
   D.gA = (real*)h->gA;
   D.fB = (real*)h->fB;
   D.gB = (real*)h->gB;
-  D.Th = (real*)h->Th;
+  D.ThA = (real*)h->ThA;
+  D.ThB = (real*)h->ThB;
   D.err = h->d_err;
   D.nx = h->prm.nx;
   D.ny = h->prm.ny;
@@ -294,7 +312,7 @@ size_t lbm_footprint_bytes(const lbm_params* p) {
   if (lbm_validate(p) != LBM_OK) return 0;
   const size_t N = (size_t)p->nx * (size_t)p->ny;
   const size_t r = p->precision == LBM_FP64 ? 8 : 4;
-  return CTRL_BYTES + partial_bytes() + 2 * align_up(9 * N * r) + 2 * align_up(5 * N * r) + align_up(2 * N * r);
+  return CTRL_BYTES + partial_bytes() + 2 * align_up(9 * N * r) + 2 * align_up(5 * N * r) + 2 * align_up(2 * N * r);
 }
 
 lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hip_stream, lbm_ctx** out) {
@@ -327,7 +345,8 @@ lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hi
   h->gA = q; q += align_up(5 * h->N * h->rsz);
   h->fB = q; q += align_up(9 * h->N * h->rsz);
   h->gB = q; q += align_up(5 * h->N * h->rsz);
-  h->Th = q;
+  h->ThA = q; q += align_up(2 * h->N * h->rsz);
+  h->ThB = q;
   h->shape_req = -1;
   h->shape = default_shape(p->precision, p->nx, p->ny);
   h->ntiles = tiles_of(p->nx, p->ny, shape_def(p->precision, h->shape).ty);
@@ -385,10 +404,10 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
   HIP_OR_FAIL(h, hipMemcpyAsync(stage + 3 * N, T, N * sizeof(double), hipMemcpyHostToDevice, h->stream));
   const int nb = (int)((N + 255) / 256);
   if (h->prm.precision == LBM_FP64) {
-    init_kernel<double><<<nb, 256, 0, h->stream>>>(stage, (double*)h->fA, (double*)h->gA, (double*)h->Th, N,
+    init_kernel<double><<<nb, 256, 0, h->stream>>>(stage, (double*)h->fA, (double*)h->gA, (double*)h->ThA, N,
                                                     1.0 - h->prm.wdot, h->prm.wdot / 4.0, h->T_ref);
   } else {
-    init_kernel<float><<<nb, 256, 0, h->stream>>>(stage, (float*)h->fA, (float*)h->gA, (float*)h->Th, N,
+    init_kernel<float><<<nb, 256, 0, h->stream>>>(stage, (float*)h->fA, (float*)h->gA, (float*)h->ThA, N,
                                                    1.0 - h->prm.wdot, h->prm.wdot / 4.0, h->T_ref);
   }
   HIP_OR_FAIL(h, hipGetLastError());
@@ -557,6 +576,9 @@ static void current_buffers(lbm_ctx* h, void*& f, void*& g, void*& fo) {
   fo = odd ? h->fA : h->fB;
 }
 
+// current temperature history (follows the buffers of f and g)
+static void* current_history(lbm_ctx* h) { return (h->gen & 1) ? h->ThB : h->ThA; }
+
 lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, double* T) {
   if (!h) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_read_fields before lbm_init");
@@ -622,7 +644,7 @@ lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
   const size_t N = h->N, r = h->rsz;
   HIP_OR_FAIL(h, hipMemcpyAsync(q, f, 9 * N * r, hipMemcpyDeviceToHost, h->stream));
   HIP_OR_FAIL(h, hipMemcpyAsync(q + 9 * N * r, g, 5 * N * r, hipMemcpyDeviceToHost, h->stream));
-  HIP_OR_FAIL(h, hipMemcpyAsync(q + 14 * N * r, h->Th, 2 * N * r, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(q + 14 * N * r, current_history(h), 2 * N * r, hipMemcpyDeviceToHost, h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   int64_t meta[3] = {h->steps, 0, 0};
   std::memcpy(&meta[1], &h->rho_ave, sizeof(double));
@@ -648,7 +670,7 @@ lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
   current_buffers(h, f, g, fo);
   HIP_OR_FAIL(h, hipMemcpyAsync(f, q, 9 * N * r, hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipMemcpyAsync(g, q + 9 * N * r, 5 * N * r, hipMemcpyHostToDevice, h->stream));
-  HIP_OR_FAIL(h, hipMemcpyAsync(h->Th, q + 14 * N * r, 2 * N * r, hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(current_history(h), q + 14 * N * r, 2 * N * r, hipMemcpyHostToDevice, h->stream));
   unsigned zero = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
   lbm_status s = upload_desc(h);
@@ -790,11 +812,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   b->pending_launches.assign(n, 0);
   b->stream = (hipStream_t)hip_stream;
   b->precision = prec;
-  {
-    long long tiles = 0;  // default shape from the size of the whole batch
-    for (int i = 0; i < n; ++i) tiles += tiles_of(ctxs[i]->prm.nx, ctxs[i]->prm.ny, shape_def(prec, 0).ty);
-    b->shape = (prec == LBM_FP32 && tiles >= 1024) ? 1 : 0;
-  }
+  b->shape = batch_default_shape(prec, b->ctx);
   b->base = (char*)dev_mem;
   b->bytes = bytes;
   b->d_clock = (long long*)b->base;
@@ -820,11 +838,7 @@ lbm_status lbm_batch_set_shape(lbm_batch* b, int k) {
   if (k >= 0)
     for (lbm_ctx* h : b->ctx)
       if (!shape_fits(b->precision, k, h->prm.nx, h->prm.ny)) return LBM_E_INVAL;
-  if (k < 0) {
-    long long tiles = 0;
-    for (lbm_ctx* h : b->ctx) tiles += tiles_of(h->prm.nx, h->prm.ny, shape_def(b->precision, 0).ty);
-    k = (b->precision == LBM_FP32 && tiles >= 1024) ? 1 : 0;
-  }
+  if (k < 0) k = batch_default_shape(b->precision, b->ctx);
   b->shape = k;  // tile counts change; the graph is recaptured at the next upload
   return LBM_OK;
 }

@@ -2,8 +2,10 @@
 //
 // Data layout in HBM (structure of arrays, x fastest, so that a wavefront of 64 lanes along
 // x reads and writes 64 consecutive values of one population):
-//   f[9][ny][nx], g[5][ny][nx]  in two copies A/B (read one, write the other, swap per step)
-//   Th[2][ny][nx]               temperature history T(t-1), T(t-2), updated in place
+//   f[9][ny][nx], g[5][ny][nx]  in two copies A/B (read one, write the other, swap per launch)
+//   Th[2][ny][nx]               temperature history T(t-1), T(t-2), also in two copies A/B: a
+//                               two-step launch reads the history of its neighbours' nodes,
+//                               which must not change under it
 //
 // Temperature storage: g_i is kept as g_i - what_i T_ref and the history as T - T_ref, with T_ref
 // a per-simulation constant (the mean initial temperature).  Relaxation, grad T, the
@@ -83,7 +85,8 @@ struct InstDesc {
   real* gA;
   real* fB;
   real* gB;
-  real* Th;
+  real* ThA;
+  real* ThB;
   unsigned* err;
   int nx, ny;
   int ntx, nty;        // tiles along x and y

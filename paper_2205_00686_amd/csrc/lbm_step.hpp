@@ -363,7 +363,8 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   const gptr<const char> gs = (gptr<const char>)to_global<const real>(odd ? D.gB : D.gA);
   const gptr<char> fd = (gptr<char>)to_global<real>(odd ? D.fA : D.fB);
   const gptr<char> gd = (gptr<char>)to_global<real>(odd ? D.gA : D.gB);
-  const gptr<char> Th = (gptr<char>)to_global<real>(D.Th);
+  const gptr<const char> Ths = (gptr<const char>)to_global<const real>(odd ? D.ThB : D.ThA);
+  const gptr<char> Thd = (gptr<char>)to_global<real>(odd ? D.ThA : D.ThB);
   const DevParams<real> p = D.p;
   const int walls = INTERIOR ? 0 : p.y_walls;
   const bool tb = INTERIOR ? false : p.thermal_box != 0;
@@ -410,8 +411,8 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
         for (int i = 0; i < 9; ++i) f[r][i] = ldb<real>(fsp(i), ob[r]);
 #pragma unroll
         for (int i = 0; i < 5; ++i) g[r][i] = ldb<real>(gsp(i), ob[r]);
-        T1[r] = ldb<real>(Th, ob[r]);
-        T2[r] = ldb<real>(sbase(Th + PB), ob[r]);
+        T1[r] = ldb<real>(Ths, ob[r]);
+        T2[r] = ldb<real>(sbase(Ths + PB), ob[r]);
       }
     } else {
 #pragma unroll
@@ -497,8 +498,8 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
     real fs_[9], gs_[5], Tr;
     node_collide<real>(p, freeze, f[r], g[r], rho, ux, uy, Fx[r], Fy[r], S2[r], dpdT[r], divu, T1[r], T2[r], fs_,
                        gs_, Tr);
-    stb(Th, o, Tr);
-    stb(sbase(Th + PB), o, T1[r]);
+    stb(Thd, o, Tr);
+    stb(sbase(Thd + PB), o, T1[r]);
 
     // ---- streaming.  Interior tiles: a neighbour's byte offset differs from the node's by a
     // uniform amount, folded into the plane base.  Other tiles: wrapped offsets of the eight
@@ -618,7 +619,7 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
   const ptrdiff_t PB = (ptrdiff_t)nx * (ptrdiff_t)ny * SZ;
   const gptr<const char> fs = (gptr<const char>)to_global<const real>(odd ? D.fB : D.fA);
   const gptr<const char> gs = (gptr<const char>)to_global<const real>(odd ? D.gB : D.gA);
-  const gptr<const char> Th = (gptr<const char>)to_global<const real>(D.Th);
+  const gptr<const char> Th = (gptr<const char>)to_global<const real>(odd ? D.ThB : D.ThA);
   const DevParams<real> p = D.p;
   const int walls = INTERIOR ? 0 : p.y_walls;
   const bool tb = INTERIOR ? false : p.thermal_box != 0;

@@ -60,6 +60,19 @@ def test_every_shape_gives_identical_bits(lbm, sat):
             assert _run(lbm, w, prec, n + 1, k) == _run(lbm, w, prec, n + 1, 0), (name, k, "odd")
 
 
+def test_shapes_identical_on_grids_of_many_workgroup_waves(lbm, sat):
+    """More tiles than the GPU holds at once: workgroups of later waves read halos that earlier
+    workgroups of the same launch have finished with (regression: the temperature history of a
+    neighbour's nodes must not be overwritten within a launch)."""
+    Tc, rl, rg = sat
+    for name, w in (("evaporation 1024x512", evaporation(Tc, rl, rg, nx=1024, ny=512, R=100.0)),
+                    ("boiling 512x1024", boiling(Tc, rl, rg, nx=512, ny=1024, hot_width=16.0))):
+        ref = _run(lbm, w, lbm.LBM_FP32, 7, 0)
+        for k in range(1, len(lbm.shapes(lbm.LBM_FP32))):
+            print(f"\n[case] {name} shape {k}", flush=True)
+            assert _run(lbm, w, lbm.LBM_FP32, 7, k) == ref, (name, k)
+
+
 def test_two_step_shape_rejected_on_small_grid(lbm, sat):
     Tc, rl, rg = sat
     w = droplet(Tc, rl, rg, nx=40, ny=36, R=9.0)
