@@ -148,6 +148,15 @@ lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, doub
    in a fixed order (deterministic).  Synchronises. */
 lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy);
 
+/* Vapour profile of the current state, for the bubble-departure readout of Section 4.3
+   (departure diameter against gravity): counts[y] = number of columns x in [x_lo, x_hi)
+   (taken modulo nx, so the window may wrap) whose density is below rho_threshold, for every
+   row y of the grid.  The density is summed in the working precision as in lbm_read_fields and
+   compared with rho_threshold rounded to that precision.  counts: caller-owned host array of ny
+   ints.  Computed on the device; synchronising.  LBM_E_INVAL for a window wider than nx or
+   empty, a non-finite threshold or NULL pointers; LBM_E_STATE before lbm_init. */
+lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi, int32_t* counts);
+
 /* Raw state to / from a host buffer of lbm_state_bytes() bytes: f[9][ny][nx], g[5][ny][nx],
    history[2][ny][nx] in the context's precision, then three 8-byte words: the step count
    (int64), rho_ave and T_ref (FP64).  The temperature populations are stored relative to

@@ -178,6 +178,15 @@ class Solver:
         _check(_native.lib().lbm_read_fields(self.handle, *(_dptr(a) for a in out)), self.handle)
         return tuple(out)
 
+    def vapour_rows(self, rho_threshold: float, x_lo: int = 0, x_hi: int = None) -> np.ndarray:
+        """Per row, the number of columns in [x_lo, x_hi) whose density is below rho_threshold
+        (computed on the device from the current state)."""
+        x_hi = self.nx if x_hi is None else int(x_hi)
+        out = np.zeros(self.ny, dtype=np.int32)
+        _check(_native.lib().lbm_vapour_rows(self.handle, float(rho_threshold), int(x_lo), x_hi,
+                                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), self.handle)
+        return out
+
     def diagnostics(self):
         m, e = ctypes.c_double(), ctypes.c_double()
         _check(_native.lib().lbm_diagnostics(self.handle, ctypes.byref(m), ctypes.byref(e)), self.handle)

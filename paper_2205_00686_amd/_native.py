@@ -18,7 +18,7 @@ LBM_FREEZE_FLOW, LBM_NO_S = 1, 2
 # every symbol include/lbm.h declares
 EXPORTS = (
     "lbm_params_default", "lbm_validate", "lbm_footprint_bytes", "lbm_create", "lbm_init", "lbm_step",
-    "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_shape_fits", "lbm_set_shape", "lbm_get_shape", "lbm_sync", "lbm_read_fields", "lbm_diagnostics", "lbm_state_bytes", "lbm_save_state",
+    "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_shape_fits", "lbm_set_shape", "lbm_get_shape", "lbm_sync", "lbm_read_fields", "lbm_vapour_rows", "lbm_diagnostics", "lbm_state_bytes", "lbm_save_state",
     "lbm_load_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
     "lbm_last_error", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
     "lbm_batch_remaining", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_sync", "lbm_batch_destroy",
@@ -82,6 +82,7 @@ def lib():
         "lbm_get_shape": ([vp], ctypes.c_int),
         "lbm_sync": ([vp], st),
         "lbm_read_fields": ([vp, dp, dp, dp, dp], st),
+        "lbm_vapour_rows": ([vp, d, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)], st),
         "lbm_diagnostics": ([vp, dp, dp], st),
         "lbm_state_bytes": ([vp], sz),
         "lbm_save_state": ([vp, vp, sz], st),

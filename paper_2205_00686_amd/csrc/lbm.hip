@@ -631,6 +631,30 @@ lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy) {
   return check_device_error(h);
 }
 
+lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi, int32_t* counts) {
+  if (!h || !counts || !std::isfinite(rho_threshold) || x_hi <= x_lo || x_hi - x_lo > h->prm.nx) return LBM_E_INVAL;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_vapour_rows before lbm_init");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  void *f, *g, *fo;
+  current_buffers(h, f, g, fo);
+  const int ny = h->prm.ny;
+  const int chunk = (int)(partial_bytes() / sizeof(int));  // rows per pass through the partials area
+  int* dcount = (int*)h->d_part;
+  for (int y0 = 0; y0 < ny; y0 += chunk) {
+    const int rows = std::min(chunk, ny - y0);
+    if (h->prm.precision == LBM_FP64)
+      vapour_rows_kernel<double><<<rows, VAP_NT, 0, h->stream>>>((const double*)f, h->prm.nx, h->N, y0, x_lo,
+                                                                 x_hi - x_lo, rho_threshold, dcount);
+    else
+      vapour_rows_kernel<float><<<rows, VAP_NT, 0, h->stream>>>((const float*)f, h->prm.nx, h->N, y0, x_lo,
+                                                                x_hi - x_lo, (float)rho_threshold, dcount);
+    HIP_OR_FAIL(h, hipGetLastError());
+    HIP_OR_FAIL(h, hipMemcpyAsync(counts + y0, dcount, rows * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  }
+  return check_device_error(h);
+}
+
 size_t lbm_state_bytes(const lbm_ctx* h) { return h ? 16 * h->N * h->rsz + 3 * sizeof(int64_t) : 0; }
 
 lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {

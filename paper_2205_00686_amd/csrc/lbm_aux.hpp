@@ -98,6 +98,34 @@ __global__ void fields_kernel(DevParams<real> p, const real* __restrict__ f, con
   if (err) atomicOr(errw, err);
 }
 
+// Vapour count per row for the bubble-departure readout: one workgroup per row y of the chunk
+// [y0, y0 + gridDim.x), counting the columns x of [x_lo, x_lo + width) (taken modulo nx) whose
+// density, summed in the working precision exactly as for the field readout, is below thr.
+constexpr int VAP_NT = 256;
+
+template <typename real>
+__global__ __launch_bounds__(VAP_NT) void vapour_rows_kernel(const real* __restrict__ f, int nx, size_t N, int y0,
+                                                             int x_lo, int width, real thr, int* __restrict__ counts) {
+  __shared__ int part[VAP_NT / 64];
+  const int y = y0 + blockIdx.x;
+  int c = 0;
+  for (int i = threadIdx.x; i < width; i += VAP_NT) {
+    const int x = wrapi(x_lo + i, nx, true);
+    const int o = y * nx + x;
+    const real rho = ((f[o] + f[N + o]) + (f[2 * N + o] + f[3 * N + o])) +
+                     ((f[4 * N + o] + f[5 * N + o]) + (f[6 * N + o] + f[7 * N + o])) + f[8 * N + o];
+    c += rho < thr ? 1 : 0;
+  }
+  for (int s = 32; s > 0; s >>= 1) c += __shfl_down(c, s, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < VAP_NT / 64; ++w) t += part[w];
+    counts[blockIdx.x] = t;
+  }
+}
+
 // Deterministic FP64 sums of rho and rho c_v T: each workgroup reduces a fixed contiguous
 // range in a fixed tree order into partials[2*block], a second single-workgroup pass adds the
 // partials in a fixed tree order.

@@ -146,7 +146,7 @@ def boiling(Tc, rho_l, rho_g, nx=1024, ny=2048, T_rel=0.86, dT_rel=0.2, gravity=
                lambda_=lambda_, **kw)
     rho = tanh_slab(nx, ny, fill * ny, rho_l, rho_g) + uniform_noise((ny, nx), noise, seed)
     return Workload("boiling", p, rho, _zeros(ny, nx), _zeros(ny, nx), np.full((ny, nx), T_sat), steps,
-                    {"T_sat": T_sat, "seed": seed})
+                    {"T_sat": T_sat, "seed": seed, "fill": fill})
 
 
 def head_limited_fill(rho_l, rho_g, p_sat, gravity, ny, fill=0.5, head_frac=0.5) -> float:
