@@ -188,7 +188,12 @@ const char* lbm_last_error(const lbm_ctx* h);
  */
 size_t lbm_batch_footprint_bytes(int n);
 
-/* Build a batch over ctxs[0..n) (all initialised, same precision), enqueueing on hip_stream. */
+/* Build a batch over ctxs[0..n) (all initialised, same precision), enqueueing on hip_stream.
+   The batch's work is ordered after everything already enqueued on the contexts' own streams
+   (their lbm_init, for instance), so a context may be initialised on a stream of its own.
+   While the batch exists its members are advanced only through it.  Once lbm_batch_sync has
+   returned, a member may be used on its own stream (lbm_read_fields, lbm_step, ...) or
+   destroyed.  LBM_E_DEVICE if the stream ordering cannot be set up. */
 lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t bytes, void* hip_stream,
                             lbm_batch** out);
 
@@ -213,6 +218,8 @@ int lbm_batch_get_shape(const lbm_batch* b);
    NULL).  The contexts' step counters are brought up to date. */
 lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status);
 
+/* Release the batch.  The caller-owned memory stays in use until the batch's stream has
+   drained.  The members are not touched, so they may be destroyed before the batch. */
 lbm_status lbm_batch_destroy(lbm_batch* b);
 
 #ifdef __cplusplus

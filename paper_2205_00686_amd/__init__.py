@@ -238,6 +238,8 @@ class Batch:
         self.mem = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.stream = stream if stream is not None else self.solvers[0].stream
         self.mem.record_stream(self.stream)
+        for s in self.solvers:  # the members' memory is also used on the batch's stream
+            s.mem.record_stream(self.stream)
         arr = (ctypes.c_void_p * n)(*[s.handle.value for s in self.solvers])
         h = ctypes.c_void_p()
         _check(L.lbm_batch_create(arr, n, ctypes.c_void_p(self.mem.data_ptr()), nbytes,

@@ -133,6 +133,24 @@ struct lbm_batch {
   int graph_shape = -1;                // tile shape the graph was captured with
 };
 
+// Orders the batch stream after every member's stream: one event recorded on each distinct
+// member stream and waited for on the batch stream.
+static hipError_t wait_for_members(hipStream_t bs, const std::vector<lbm_ctx*>& ctx) {
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  std::vector<hipStream_t> seen;
+  for (const lbm_ctx* h : ctx) {
+    if (e != hipSuccess) break;
+    if (h->stream == bs || std::find(seen.begin(), seen.end(), h->stream) != seen.end()) continue;
+    seen.push_back(h->stream);
+    e = hipEventRecord(ev, h->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(bs, ev, 0);
+  }
+  const hipError_t d = hipEventDestroy(ev);
+  return e != hipSuccess ? e : d;
+}
+
 // Default shape of a batch: the two-step shape if every member fits it, else by total size.
 static int batch_default_shape(int precision, const std::vector<lbm_ctx*>& ctx) {
   if (precision == LBM_FP64) return 0;
@@ -836,6 +854,11 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   b->pending_launches.assign(n, 0);
   b->stream = (hipStream_t)hip_stream;
   b->precision = prec;
+  // the batch's work follows whatever is already enqueued on the members' own streams
+  if (wait_for_members(b->stream, b->ctx) != hipSuccess) {
+    delete b;
+    return LBM_E_DEVICE;
+  }
   b->shape = batch_default_shape(prec, b->ctx);
   b->base = (char*)dev_mem;
   b->bytes = bytes;
@@ -1025,6 +1048,7 @@ lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status) {
 
 lbm_status lbm_batch_destroy(lbm_batch* b) {
   if (!b) return LBM_E_INVAL;
+  // the members are not touched: they may already be destroyed
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   delete b;
   return LBM_OK;

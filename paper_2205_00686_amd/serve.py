@@ -60,38 +60,60 @@ def summarize(reqs, t0, t1):
 
 class Server:
     def __init__(self, hbm_budget: int, max_slots: int = 64, chunk: int = 512, precision: int = LBM_FP32,
-                 keep_results: bool = True, prepare_workers: int = 4):
+                 keep_results: bool = True, prepare_workers: int = 4, streams: int = 4):
         self.hbm_budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.chunk = int(chunk)
         self.precision = precision
         self.keep_results = keep_results
         self.pool = cf.ThreadPoolExecutor(max_workers=prepare_workers)
+        self.n_streams = int(streams)
 
     def run(self, requests, realtime: bool = True, log=None):
         """Serve `requests` (sorted by arrival).  With realtime=False every request is considered
-        arrived at t=0 (pure throughput run).  Returns (requests, summary)."""
+        arrived at t=0 (pure throughput run).  Returns (requests, summary).
+
+        The host work of a round overlaps the GPU work of the chunk in flight: the batch runs on
+        a stream of its own and every request on one of a few request streams, so while chunk k
+        runs the server reads back the requests that finished with chunk k-1 and initialises the
+        ones admitted for chunk k+1."""
         import torch
 
+        batch_stream = _new_stream()
+        req_streams = [_new_stream() for _ in range(self.n_streams)]
         reqs = sorted(requests, key=lambda r: r.arrival)
         arriving = deque(reqs)
         queued = deque()
         prep = {}
-        active = {}        # rid -> (request, solver)
+        running = {}       # rid -> (request, solver): members of the batch
         remaining = {}
+        ready = []         # admitted and initialised, joining at the next launch
+        finishing = []     # finished with the last synced chunk, results not read yet
         batch, members = None, ()
+        inflight = False
         t0 = time.perf_counter()
         now = lambda: time.perf_counter() - t0  # noqa: E731
         used = 0
-        while arriving or queued or active:
-            # arrivals: start building their initial fields
+        admitted = 0
+        while arriving or queued or running or ready or finishing or inflight:
+            # ---- host work, overlapping the chunk in flight
             while arriving and (not realtime or arriving[0].arrival <= now()):
                 r = arriving.popleft()
                 r.t_arrive = r.arrival if realtime else 0.0
                 prep[r.rid] = self.pool.submit(r.make)
                 queued.append(r)
-            # admission in arrival order while a slot is free and the footprint fits
-            while queued and len(active) < self.max_slots:
+            for r, sol in finishing:
+                if r.error is None:
+                    fields = sol.fields()
+                    if self.keep_results:
+                        r.result = fields
+                r.t_done = now()
+                used -= r.footprint
+                sol.close()
+                if log:
+                    log(r)
+            finishing = []
+            while queued and len(running) + len(ready) < self.max_slots:
                 r = queued[0]
                 fut = prep[r.rid]
                 if not fut.done():
@@ -99,7 +121,7 @@ class Server:
                 w = fut.result()
                 need = footprint_bytes(w.params, self.precision)
                 if used + need > self.hbm_budget:
-                    if not active and need > self.hbm_budget:
+                    if not (running or ready or inflight) and need > self.hbm_budget:
                         queued.popleft()
                         r.error = "footprint exceeds the HBM budget"
                         r.t_done = now()
@@ -108,52 +130,65 @@ class Server:
                 queued.popleft()
                 del prep[r.rid]
                 try:
-                    s = Solver(w.params, precision=self.precision).init(w.rho, w.ux, w.uy, w.T)
+                    st = req_streams[admitted % len(req_streams)]
+                    sol = Solver(w.params, precision=self.precision, stream=st).init(w.rho, w.ux, w.uy, w.T)
                 except Exception as e:  # noqa: BLE001 -- a bad request must not stop the others
                     r.error = str(e)
                     r.t_done = now()
                     continue
+                admitted += 1
                 r.nodes, r.footprint, r.t_admit = w.nodes, need, now()
                 used += need
-                active[r.rid] = (r, s)
+                ready.append((r, sol))
+            # ---- the chunk in flight ends: finished and failed members leave the batch
+            if inflight:
+                status = batch.sync()
+                inflight = False
+                for j, i in enumerate(members):
+                    r, sol = running[i]
+                    remaining[i] -= min(self.chunk, remaining[i])
+                    if status[j] != 0:
+                        r.error = "numerical failure"
+                    if remaining[i] == 0 or r.error is not None:
+                        finishing.append((r, sol))
+                        del running[i], remaining[i]
+            for r, sol in ready:
+                running[r.rid] = (r, sol)
                 remaining[r.rid] = r.steps
-            if not active:
-                # idle: wait for the next arrival or a field preparation
-                if queued:
-                    cf.wait([prep[queued[0].rid]], timeout=0.05)
-                elif arriving and realtime:
-                    time.sleep(max(0.0, min(0.05, arriving[0].arrival - now())))
+            ready = []
+            if not running:
+                if batch is not None:  # no member left: release it before its members go
+                    batch.close()
+                    batch, members = None, ()
+                if not (finishing or queued or arriving):
+                    continue
+                if not finishing:
+                    # idle: wait for the next arrival or a field preparation
+                    if queued:
+                        cf.wait([prep[queued[0].rid]], timeout=0.05)
+                    elif arriving and realtime:
+                        time.sleep(max(0.0, min(0.05, arriving[0].arrival - now())))
                 continue
-            ids = tuple(sorted(active))
+            ids = tuple(sorted(running))
             if ids != members:
                 if batch is not None:
                     batch.close()
-                batch = Batch([active[i][1] for i in ids])
+                batch = Batch([running[i][1] for i in ids], stream=batch_stream)
                 members = ids
             for j, i in enumerate(ids):
                 batch.set_budget(j, min(self.chunk, remaining[i]))
             batch.step(self.chunk)
-            status = batch.sync()
-            for j, i in enumerate(ids):
-                r, s = active[i]
-                remaining[i] -= min(self.chunk, remaining[i])
-                if status[j] != 0:
-                    r.error = "numerical failure"
-                if remaining[i] == 0 or r.error is not None:
-                    if r.error is None:
-                        fields = s.fields()
-                        if self.keep_results:
-                            r.result = fields
-                    r.t_done = now()
-                    used -= r.footprint
-                    s.close()
-                    del active[i], remaining[i]
-                    if log:
-                        log(r)
+            inflight = True
         if batch is not None:
             batch.close()
         torch.cuda.synchronize()
         return reqs, summarize(reqs, 0.0, now())
+
+
+def _new_stream():
+    """A stream of default priority on the current device."""
+    import torch
+    return torch.cuda.Stream()
 
 
 def fifo(requests, precision: int = LBM_FP32, realtime: bool = True, keep_results: bool = True, log=None,

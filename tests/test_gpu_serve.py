@@ -77,3 +77,45 @@ def test_failing_request_is_isolated(lbm):
     s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
     s.step(150)
     assert np.array_equal(s.fields()[0], done[2].result[0])
+
+
+def test_batch_orders_member_streams(lbm):
+    """Members initialised on streams of their own, batched on a third stream and, after the
+    batch is gone, advanced on their own streams again: same bits as one stream throughout."""
+    import torch
+    base = Params()
+    Tc = lbm.critical_temperature(base)
+    rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
+    makes = [lambda: evaporation(Tc, rl, rg, nx=160, ny=120, R=20.0, superheat=1.2),
+             lambda: boiling(Tc, rl, rg, nx=128, ny=160, hot_width=8.0, seed=9)]
+    alone = []
+    for make in makes:
+        w = make()
+        s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+        s.step(90)
+        s.step(33)
+        alone.append(s.fields())
+        s.close()
+    streams = [torch.cuda.Stream() for _ in makes]
+    sols = []
+    for make, st in zip(makes, streams):
+        w = make()
+        sols.append(lbm.Solver(w.params, stream=st).init(w.rho, w.ux, w.uy, w.T))
+    b = lbm.Batch(sols, stream=torch.cuda.Stream())
+    for i in range(len(sols)):
+        b.set_budget(i, 90)
+    b.step(90)
+    assert b.sync() == [0] * len(sols)
+    b.close()
+    for s in sols:
+        s.step(33)
+    for s, exp in zip(sols, alone):
+        assert s.steps == 123
+        for got, e in zip(s.fields(), exp):
+            assert np.array_equal(got, e)
+    # members may be destroyed before their batch once it is synchronised
+    b = lbm.Batch(sols)
+    b.sync()
+    for s in sols:
+        s.close()
+    b.close()

@@ -14,7 +14,7 @@ class FakeSolver:
     live = 0
     peak_live = 0
 
-    def __init__(self, params, precision=None):
+    def __init__(self, params, precision=None, stream=None):
         self.params = params
         self.steps = 0
         if params.get("bad"):
@@ -35,12 +35,13 @@ class FakeSolver:
         cls = type(self)
         cls.live_bytes -= self.params["fp"]
         cls.live -= 1
+        self.closed = True
 
 
 class FakeBatch:
     launches = []
 
-    def __init__(self, solvers):
+    def __init__(self, solvers, stream=None):
         self.solvers = list(solvers)
         self.budget = [0] * len(self.solvers)
 
@@ -58,7 +59,8 @@ class FakeBatch:
         return [-4 if getattr(s, "failed", False) else 0 for s in self.solvers]
 
     def close(self):
-        pass
+        # the server releases a batch before any of its members
+        assert not any(getattr(s, "closed", False) for s in self.solvers)
 
 
 @pytest.fixture
@@ -68,6 +70,7 @@ def fake(monkeypatch):
     monkeypatch.setattr(serve, "Solver", FakeSolver)
     monkeypatch.setattr(serve, "Batch", FakeBatch)
     monkeypatch.setattr(serve, "footprint_bytes", lambda p, prec: p["fp"])
+    monkeypatch.setattr(serve, "_new_stream", lambda: None)
     import torch
     monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
     return serve
@@ -91,6 +94,13 @@ def test_every_request_gets_its_steps_within_limits(fake):
     # continuous batching: several requests shared launches
     assert max(FakeBatch.launches) > 1
     assert summary["node_updates"] == sum(r.nodes * r.steps for r in done)
+
+
+def test_batch_released_before_members_when_all_finish_together(fake):
+    # two rounds in which every running request finishes in the same chunk
+    reqs = [_req(i, steps=64, fp=10) for i in range(2)] + [_req(2 + i, steps=128, fp=10, arrival=0.0) for i in range(2)]
+    done, summary = fake.Server(hbm_budget=20, max_slots=2, chunk=64).run(reqs, realtime=False)
+    assert summary["completed"] == 4 and FakeSolver.live == 0
 
 
 def test_admission_is_in_arrival_order(fake):
