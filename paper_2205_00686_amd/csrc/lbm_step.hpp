@@ -102,6 +102,30 @@ __device__ __forceinline__ void uring_cell(int r, int& ex, int& ey) {
   }
 }
 
+// Code variant of a tile.  Variant 0: interior tile (load region inside the grid, away from
+// walls and Dirichlet edges): no index wrapping and no boundary tests.  Variants 1-4: any tile,
+// compiled for the simulation's boundary kinds, so that a tile pays only for the boundary code
+// its simulation can need: 1 + (Dirichlet temperature box) + 2 (walls at y = 0, ny - 1).
+template <int V>
+struct Variant {
+  static constexpr bool INTERIOR = V == 0;
+  static constexpr bool TB = V != 0 && ((V - 1) & 1) != 0;
+  static constexpr bool WALLS = V != 0 && ((V - 1) & 2) != 0;
+};
+__device__ __forceinline__ int general_variant(int thermal_box, int y_walls) {
+  return 1 + (thermal_box != 0 ? 1 : 0) + (y_walls != 0 ? 2 : 0);
+}
+// Calls fn(std::integral_constant<int, v>) for the general variant v (1-4).
+template <class Fn>
+__device__ __forceinline__ void with_general_variant(int v, Fn&& fn) {
+  switch (v) {
+    case 1: fn(std::integral_constant<int, 1>{}); break;
+    case 2: fn(std::integral_constant<int, 2>{}); break;
+    case 3: fn(std::integral_constant<int, 3>{}); break;
+    default: fn(std::integral_constant<int, 4>{}); break;
+  }
+}
+
 // Row classification in a walled domain: 0 fluid row, 1 bottom ghost (y=-1), 2 top ghost
 // (y=ny), 3 unused.  Periodic domains have fluid rows only (wrapped).
 __device__ __forceinline__ int row_kind(int y, int ny, int walls) {
@@ -347,12 +371,12 @@ struct LdsState {
   const real* T2;
 };
 
-// One step of one tile.  INTERIOR tiles (load region entirely inside the grid, away from walls
+// One step of one tile (code variant V, see Variant).  Interior tiles (load region entirely inside the grid, away from walls
 // and Dirichlet edges) need no index wrapping and no boundary tests; the general variant
 // handles periodic wrap, wall ghost rows, bounce-back and anti-bounce-back.  Both variants
 // perform the same arithmetic on every node.  FROM_LDS: f and g come from `st` (second step of
 // a two-step launch) instead of the global source buffers.
-template <typename real, class S, bool INTERIOR, bool FROM_LDS>
+template <typename real, class S, int V, bool FROM_LDS>
 __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real, S::EYW>& L, bool odd, int x0, int y0,
                                           const LdsState<real, S>& st, unsigned& err) {
   constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, RING = S::RING, URING = S::URING, EYW = S::EYW;
@@ -366,8 +390,9 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   const gptr<const char> Ths = (gptr<const char>)to_global<const real>(odd ? D.ThB : D.ThA);
   const gptr<char> Thd = (gptr<char>)to_global<real>(odd ? D.ThA : D.ThB);
   const DevParams<real> p = D.p;
-  const int walls = INTERIOR ? 0 : p.y_walls;
-  const bool tb = INTERIOR ? false : p.thermal_box != 0;
+  constexpr bool INTERIOR = Variant<V>::INTERIOR;
+  constexpr int walls = Variant<V>::WALLS ? 1 : 0;
+  constexpr bool tb = Variant<V>::TB;
   const bool freeze = (p.flags & FL_FREEZE_FLOW) != 0;
   const bool tiny = nx < EXW + 1 || ny < EYW + 1;  // periodic images closer than one halo
 
@@ -462,7 +487,7 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   __syncthreads();
 
   // ---- phase 1b: wetting ghost rows
-  if (!INTERIOR && walls) {
+  if constexpr (walls != 0) {
     if (ghost_rows<real, EXW, EYW>(L, p, x0 - HXW, y0 - HYW, ny, tid, NT, wx, err)) __syncthreads();
   }
 
@@ -607,7 +632,7 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
 // computes forces and velocities on C+1 = (HXW + 2, HYW + 2), collides C = (HXW + 1, HYW + 1),
 // and streams into the state arrays over the second step's load region (HXW, HYW).  Pushes that
 // leave that region are dropped; every kept slot is written exactly once.
-template <typename real, class S, bool INTERIOR>
+template <typename real, class S, int V>
 __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<real, S>& L, bool odd, int x0, int y0,
                                            real (&Tn1)[S::RPT], real (&Tn2)[S::RPT], unsigned& err) {
   constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, MX = S::MX, MY = S::MY, MXH = S::MXH, MYH = S::MYH;
@@ -621,8 +646,9 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
   const gptr<const char> gs = (gptr<const char>)to_global<const real>(odd ? D.gB : D.gA);
   const gptr<const char> Th = (gptr<const char>)to_global<const real>(odd ? D.ThB : D.ThA);
   const DevParams<real> p = D.p;
-  const int walls = INTERIOR ? 0 : p.y_walls;
-  const bool tb = INTERIOR ? false : p.thermal_box != 0;
+  constexpr bool INTERIOR = Variant<V>::INTERIOR;
+  constexpr int walls = Variant<V>::WALLS ? 1 : 0;
+  constexpr bool tb = Variant<V>::TB;
   const bool freeze = (p.flags & FL_FREEZE_FLOW) != 0;
   const bool tiny = nx < MX + 1 || ny < MY + 1;
 
@@ -679,7 +705,7 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
   }
   __syncthreads();
 
-  if (!INTERIOR && walls) {
+  if constexpr (walls != 0) {
     if (ghost_rows<real, MX, MY>(L.m1, p, x0 - MXH, y0 - MYH, ny, tid, NT, wx, err)) __syncthreads();
   }
 
@@ -817,6 +843,7 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
   // interior: the load region lies inside the grid, so no wrap, ghost row, wall or Dirichlet
   // edge is involved
   const bool interior = x0 >= HXW && x0 + TX + HXW <= D.nx && y0 >= HYW && y0 + S::TY + HYW <= D.ny;
+  const int gv = general_variant(D.p.thermal_box, D.p.y_walls);
   const LdsState<real, S> none{};
   if constexpr (S::DEPTH == 2) {
     __shared__ Step2Lds<real, S> L2;
@@ -824,19 +851,19 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
       real Tn1[S::RPT], Tn2[S::RPT];
       const bool interior2 =
           x0 >= S::MXH && x0 + TX + S::MXH <= D.nx && y0 >= S::MYH && y0 + S::TY + S::MYH <= D.ny;
-      if (interior2) first_step<real, S, true>(D, L2, odd, x0, y0, Tn1, Tn2, err);
-      else first_step<real, S, false>(D, L2, odd, x0, y0, Tn1, Tn2, err);
+      if (interior2) first_step<real, S, 0>(D, L2, odd, x0, y0, Tn1, Tn2, err);
+      else with_general_variant(gv, [&](auto v) { first_step<real, S, decltype(v)::value>(D, L2, odd, x0, y0, Tn1, Tn2, err); });
       const LdsState<real, S> st{L2.sf, L2.sg, Tn1, Tn2};
-      if (interior) step_body<real, S, true, true>(D, L2.m2, odd, x0, y0, st, err);
-      else step_body<real, S, false, true>(D, L2.m2, odd, x0, y0, st, err);
+      if (interior) step_body<real, S, 0, true>(D, L2.m2, odd, x0, y0, st, err);
+      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, true>(D, L2.m2, odd, x0, y0, st, err); });
     } else {
-      if (interior) step_body<real, S, true, false>(D, L2.m2, odd, x0, y0, none, err);
-      else step_body<real, S, false, false>(D, L2.m2, odd, x0, y0, none, err);
+      if (interior) step_body<real, S, 0, false>(D, L2.m2, odd, x0, y0, none, err);
+      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false>(D, L2.m2, odd, x0, y0, none, err); });
     }
   } else {
     __shared__ StepLds<real, S::EYW> L;
-    if (interior) step_body<real, S, true, false>(D, L, odd, x0, y0, none, err);
-    else step_body<real, S, false, false>(D, L, odd, x0, y0, none, err);
+    if (interior) step_body<real, S, 0, false>(D, L, odd, x0, y0, none, err);
+    else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false>(D, L, odd, x0, y0, none, err); });
   }
   // A failing simulation flags every node.  One atomic per thread, or even per wavefront, on one
   // word would serialise the launch, so a wavefront ORs its flags with ballots and sets only the
