@@ -33,6 +33,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 FREEZE_FLOW = 1
 NO_S = 2
 FREEZE_THERMAL = 4
+BGK = 8  # D2Q5 with the BGK collision of Eq. (21) instead of the MRT one of Eq. (39)
 
 
 def build(force: bool = True) -> str:
@@ -59,7 +60,7 @@ class _CParams(ctypes.Structure):
         ("T_box", ctypes.c_double), ("T_top", ctypes.c_double), ("T_bot", ctypes.c_double),
         ("hot_dT", ctypes.c_double), ("hot_x0", ctypes.c_double), ("hot_sigma", ctypes.c_double),
         ("theta_bot_deg", ctypes.c_double), ("theta_top_deg", ctypes.c_double),
-        ("flags", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("thermal_q", ctypes.c_int32),
     ]
 
 
@@ -221,9 +222,14 @@ class Oracle:
             raise OracleError(f"numerical failure (code {rc})")
         return tuple(out)  # rho, ux, uy, T
 
+    @property
+    def q(self) -> int:
+        """Velocities of the thermal lattice (5 or 9)."""
+        return 9 if int(getattr(self.prm, "thermal_q", 5)) == 9 else 5
+
     def state(self):
         f = np.zeros((9, self.ny, self.nx))
-        g = np.zeros((5, self.ny, self.nx))
+        g = np.zeros((self.q, self.ny, self.nx))
         h = np.zeros((2, self.ny, self.nx))
         lib().orc_get_state(self._h, _dp(f), _dp(g), _dp(h))
         return f, g, h
@@ -263,4 +269,4 @@ def run(prm, rho, ux, uy, T, steps: int):
 
 
 __all__ = ["build", "num_threads", "Tc", "eos_p", "eos_dpdT", "psi", "maxwell", "feq", "meq", "force_moments",
-           "Oracle", "OracleError", "run", "FREEZE_FLOW", "NO_S"]
+           "Oracle", "OracleError", "run", "FREEZE_FLOW", "NO_S", "BGK"]

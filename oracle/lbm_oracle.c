@@ -40,6 +40,12 @@
  *         upstream population.
  *   R-AVE  rho_ave of the buoyancy force is the mean of the initial density (mass is
  *         conserved on the closed and periodic domains used here), unless given.
+ *   R-Q9   The D2Q9 thermal lattice the paper compares against (Sections 1 and 3.1): the BGK
+ *         equation of Eq. (21) with the linear equilibrium what_i T of Eq. (22) on the D2Q9
+ *         velocities, what_i = the D2Q9 weights (chat_s^2 = 1/3), G_i and S_i of Eqs. (23)-(24)
+ *         with the same weights, lambda = chat_s^2 (tau_g - 1/2) as after Eq. (53), and grad T
+ *         from the non-equilibrium first moment as in Eqs. (49)-(50):
+ *         chat_s^2 dT/dx = -(1/tau_g) sum_i c_ix g_i (the equilibrium part of that sum is 0).
  */
 #include <math.h>
 #ifdef _OPENMP
@@ -52,6 +58,7 @@
 #define ORC_FREEZE_FLOW 1u /* test-only: populations f frozen, u = j/rho, no force */
 #define ORC_NO_S 2u        /* test-only: correction term S_i of Eq. (24) switched off */
 #define ORC_FREEZE_THERMAL 4u /* test-only: populations g frozen (isothermal flow) */
+#define ORC_BGK 8u            /* D2Q5 with the BGK collision of Eq. (21) instead of Eq. (39) */
 
 /* Parameters of the problem statement (Sections 2-4 of the paper). */
 typedef struct {
@@ -65,6 +72,7 @@ typedef struct {
   double T_box, T_top, T_bot, hot_dT, hot_x0, hot_sigma;
   double theta_bot_deg, theta_top_deg;
   uint32_t flags;
+  int32_t thermal_q;            /* thermal lattice: 5 (D2Q5, Eqs. 26 and 39; 0 means 5) or 9 (R-Q9) */
 } orc_params;
 
 /* ---------------------------------------------------------------- lattices (Eqs. 2, 3, 26) */
@@ -89,7 +97,17 @@ static int opposite5(int i) {
 
 /* D2Q5 weights: what_0 = 1 - wdot, what_{1..4} = wdot/4, chat_s^2 = wdot/2 (Eq. 26). */
 static double what5(const orc_params* p, int i) { return i == 0 ? 1.0 - p->wdot : p->wdot / 4.0; }
-static double chat_s2(const orc_params* p) { return p->wdot / 2.0; }
+static double chat_s2_5(const orc_params* p) { return p->wdot / 2.0; }
+
+/* The thermal lattice in use: number of velocities, velocities, weights, chat_s^2 (R-Q9). */
+static int qg(const orc_params* p) { return p->thermal_q == 9 ? 9 : 5; }
+static int gcx(const orc_params* p, int i) { return qg(p) == 9 ? CX[i] : HX[i]; }
+static int gcy(const orc_params* p, int i) { return qg(p) == 9 ? CY[i] : HY[i]; }
+static double gw(const orc_params* p, int i) { return qg(p) == 9 ? W9[i] : what5(p, i); }
+static double chat_s2(const orc_params* p) { return qg(p) == 9 ? CS2 : chat_s2_5(p); }
+static int gopp(const orc_params* p, int i) { return qg(p) == 9 ? opposite9(i) : opposite5(i); }
+/* BGK collision (Eq. 21) for D2Q9, or for D2Q5 when asked for */
+static int bgk(const orc_params* p) { return qg(p) == 9 || (p->flags & ORC_BGK) != 0; }
 
 /* ------------------------------------------------------------ transformation matrices */
 /* Eq. (4), with row 3 read as the Lallemand-Luo epsilon row (reading R-M). */
@@ -296,6 +314,7 @@ void orc_free(orc_state* s);
 
 orc_state* orc_new(const orc_params* prm) {
   if (prm->nx < 3 || prm->ny < 3) return NULL;
+  if (prm->thermal_q != 0 && prm->thermal_q != 5 && prm->thermal_q != 9) return NULL;
   orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
   s->p = *prm;
   s->nx = prm->nx;
@@ -305,9 +324,9 @@ orc_state* orc_new(const orc_params* prm) {
   s->f = calloc(9 * n, sizeof(double));
   s->fn = calloc(9 * n, sizeof(double));
   s->fs = calloc(9 * n, sizeof(double));
-  s->g = calloc(5 * n, sizeof(double));
-  s->gn = calloc(5 * n, sizeof(double));
-  s->gs = calloc(5 * n, sizeof(double));
+  s->g = calloc(9 * n, sizeof(double)); /* room for either thermal lattice */
+  s->gn = calloc(9 * n, sizeof(double));
+  s->gs = calloc(9 * n, sizeof(double));
   double** fields[] = {&s->T1, &s->T2, &s->rho, &s->T, &s->jx, &s->jy, &s->psi, &s->dpdT, &s->Fmx,
                        &s->Fmy, &s->Fnx, &s->Fny, &s->ux, &s->uy, &s->divu, &s->Q, &s->Sc};
   for (size_t k = 0; k < sizeof(fields) / sizeof(fields[0]); ++k) *fields[k] = calloc(n, sizeof(double));
@@ -350,7 +369,7 @@ void orc_init(orc_state* s, const double* rho, const double* ux, const double* u
     double fe[9];
     orc_feq(rho[k], ux[k], uy[k], fe);
     for (int i = 0; i < 9; ++i) s->f[i * n + k] = fe[i];
-    for (int i = 0; i < 5; ++i) s->g[i * n + k] = what5(&s->p, i) * T[k];
+    for (int i = 0; i < qg(&s->p); ++i) s->g[i * n + k] = gw(&s->p, i) * T[k];
     s->T1[k] = T[k];
     s->T2[k] = T[k];
     sum += rho[k];
@@ -407,7 +426,7 @@ static int compute_macro(orc_state* s) {
         jx += CX[i] * fi;
         jy += CY[i] * fi;
       }
-      for (int i = 0; i < 5; ++i) T += s->g[i * n + k];
+      for (int i = 0; i < qg(p); ++i) T += s->g[i * n + k];
       s->rho[k] = r;
       s->jx[k] = jx;
       s->jy[k] = jy;
@@ -492,14 +511,26 @@ static int step_once(orc_state* s) {
       }
       dv *= 1.0 / CS2;
       s->divu[k] = dv;
-      /* grad T from the non-equilibrium moments m_1, m_2 (Eqs. 49, 50); m_eq_1 = m_eq_2 = 0 (Eq. 47) */
-      double mh[5];
-      for (int r = 0; r < 5; ++r) {
-        mh[r] = 0.0;
-        for (int c = 0; c < 5; ++c) mh[r] += s->Mh[r][c] * s->g[c * n + k];
+      /* grad T from the non-equilibrium moments m_1, m_2 (Eqs. 49, 50); m_eq_1 = m_eq_2 = 0 (Eq. 47).
+         D2Q9 (R-Q9): the first moment sum_i c_i g_i with the single rate 1/tau_g. */
+      double dTx, dTy;
+      if (qg(p) == 9) {
+        double mx = 0.0, my = 0.0;
+        for (int i = 0; i < 9; ++i) {
+          mx += CX[i] * s->g[i * n + k];
+          my += CY[i] * s->g[i * n + k];
+        }
+        dTx = -s->Lam[1] * mx / cs2h;
+        dTy = -s->Lam[1] * my / cs2h;
+      } else {
+        double mh[5];
+        for (int r = 0; r < 5; ++r) {
+          mh[r] = 0.0;
+          for (int c = 0; c < 5; ++c) mh[r] += s->Mh[r][c] * s->g[c * n + k];
+        }
+        dTx = -s->Lam[1] * mh[1] / cs2h;
+        dTy = -s->Lam[2] * mh[2] / cs2h;
       }
-      double dTx = -s->Lam[1] * mh[1] / cs2h;
-      double dTy = -s->Lam[2] * mh[2] / cs2h;
       double rcv = s->rho[k] * p->cv;
       /* Q = -[rho c_v u . grad T + T (dp/dT)_rho div u] (Eq. 20) */
       s->Q[k] = -(rcv * (s->ux[k] * dTx + s->uy[k] * dTy) + s->T[k] * s->dpdT[k] * dv);
@@ -531,6 +562,24 @@ static int step_once(orc_state* s) {
       }
   }
 
+  /* BGK collision (Eq. 21): g* = g - (g - what T) / tau_g + G + S, for the D2Q9 thermal
+     lattice (R-Q9) or the BGK variant of the D2Q5 model */
+  if (bgk(p)) {
+    const double itau = s->Lam[1];
+#pragma omp parallel for
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        size_t k = idx(s, x, y);
+        double Tk = s->T[k];
+        for (int i = 0; i < qg(p); ++i) {
+          double gi = s->g[i * n + k];
+          double geq = gw(p, i) * Tk;                          /* Eq. (22) */
+          double Gi = gw(p, i) * s->Q[k];                      /* Eq. (23) */
+          double Si = gw(p, i) * s->Sc[k];                     /* Eq. (24) */
+          s->gs[i * n + k] = gi - itau * (gi - geq) + Gi + Si;
+        }
+      }
+  } else
   /* D2Q5 MRT collision (Eq. 39): g* = g - Mh^-1 Lambda (Mh g - m_eq) + G + S */
 #pragma omp parallel for
   for (int y = 0; y < ny; ++y)
@@ -574,21 +623,21 @@ static int step_once(orc_state* s) {
 
   /* Streaming of g with the modified collision term (Eq. 39, reading R-BLEND), the
      upstream population replaced by anti-bounce-back at Dirichlet edges (reading R-DIR). */
-  if (p->flags & ORC_FREEZE_THERMAL) memcpy(s->gn, s->g, 5 * n * sizeof(double));
+  if (p->flags & ORC_FREEZE_THERMAL) memcpy(s->gn, s->g, 9 * n * sizeof(double));
   else
 #pragma omp parallel for
   for (int y = 0; y < ny; ++y)
     for (int x = 0; x < nx; ++x) {
       size_t k = idx(s, x, y);
       double rcv = s->rho[k] * p->cv;
-      for (int i = 0; i < 5; ++i) {
-        int xu = x - HX[i], yu = y - HY[i];
+      for (int i = 0; i < qg(p); ++i) {
+        int xu = x - gcx(p, i), yu = y - gcy(p, i);
         int outside_y = (p->y_walls || p->thermal_box) && (yu < 0 || yu >= ny);
         int outside_x = p->thermal_box && (xu < 0 || xu >= nx);
         double up;
         if (outside_x || outside_y) {
           double Tw = p->thermal_box ? p->T_box : wall_T(s, yu < 0 ? -1 : +1, x);
-          up = -s->gs[opposite5(i) * n + k] + 2.0 * what5(p, i) * Tw;
+          up = -s->gs[gopp(p, i) * n + k] + 2.0 * gw(p, i) * Tw;
         } else {
           up = s->gs[i * n + idx(s, wrap(xu, nx), wrap(yu, ny))];
         }
@@ -641,16 +690,16 @@ int orc_fields(orc_state* s, double* rho, double* ux, double* uy, double* T) {
   return 0;
 }
 
-/* Raw state: f[9][ny][nx], g[5][ny][nx], history[2][ny][nx] (T(t-1), T(t-2)). */
+/* Raw state: f[9][ny][nx], g[Q][ny][nx] (Q = 5 or 9), history[2][ny][nx] (T(t-1), T(t-2)). */
 void orc_get_state(const orc_state* s, double* f, double* g, double* hist) {
   memcpy(f, s->f, 9 * s->n * sizeof(double));
-  memcpy(g, s->g, 5 * s->n * sizeof(double));
+  memcpy(g, s->g, qg(&s->p) * s->n * sizeof(double));
   memcpy(hist, s->T1, s->n * sizeof(double));
   memcpy(hist + s->n, s->T2, s->n * sizeof(double));
 }
 void orc_set_state(orc_state* s, const double* f, const double* g, const double* hist) {
   memcpy(s->f, f, 9 * s->n * sizeof(double));
-  memcpy(s->g, g, 5 * s->n * sizeof(double));
+  memcpy(s->g, g, qg(&s->p) * s->n * sizeof(double));
   memcpy(s->T1, hist, s->n * sizeof(double));
   memcpy(s->T2, hist + s->n, s->n * sizeof(double));
   s->err = 0;
@@ -665,7 +714,7 @@ void orc_diagnostics(const orc_state* s, double* mass, double* energy, double* s
       size_t k = idx(s, x, y);
       double r = 0, T = 0;
       for (int i = 0; i < 9; ++i) r += s->f[i * s->n + k];
-      for (int i = 0; i < 5; ++i) T += s->g[i * s->n + k];
+      for (int i = 0; i < qg(&s->p); ++i) T += s->g[i * s->n + k];
       rm += r;
       re += r * s->p.cv * T;
     }

@@ -22,6 +22,7 @@ import numpy as np
 FREEZE_FLOW = 1
 NO_S = 2
 FREEZE_THERMAL = 4
+BGK = 8
 
 
 @dataclass
@@ -65,6 +66,8 @@ class Params:
     theta_bot_deg: float = 90.0
     theta_top_deg: float = 90.0
     flags: int = 0
+    # thermal lattice: 5 (D2Q5, the paper's model) or 9 (D2Q9 with the BGK collision of Eq. 21)
+    thermal_q: int = 5
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
