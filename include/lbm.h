@@ -47,17 +47,25 @@ typedef enum {
 
 enum { LBM_FP32 = 0, LBM_FP64 = 1 };
 
-/* test-only flags: they zero terms inside the one step kernel, they add no code path */
+/* Flags.  LBM_FREEZE_FLOW and LBM_NO_S are for tests: they zero terms inside the one step
+   kernel and add no code path.  LBM_BGK selects the BGK model of Eq. (21) for the D2Q5 thermal
+   lattice: every D2Q5 rate is set to 1/tau_g (vs3 and vs4 are then ignored), which is the MRT
+   step of Eq. (39) with Lambda = I / tau_g. */
 enum {
   LBM_FREEZE_FLOW = 1u, /* populations f are not updated; u = (sum c_i f_i)/rho, no force */
-  LBM_NO_S = 2u         /* correction term S_i of Eq. (24) switched off */
+  LBM_NO_S = 2u,        /* correction term S_i of Eq. (24) switched off */
+  LBM_BGK = 8u          /* D2Q5 thermal populations with the BGK collision of Eq. (21) */
 };
 
 /* Parameters of the problem statement.  lbm_params_default() fills the paper's values. */
 typedef struct {
   int32_t nx, ny;        /* grid size, each >= 3 */
   int32_t precision;     /* LBM_FP32: populations stored and collided in FP32; LBM_FP64 */
-  int32_t reserved0;
+  /* thermal lattice: 5 (D2Q5 with the MRT of Eq. 39, the paper's model; 0 also means 5) or 9
+     (D2Q9 with the BGK collision of Eq. 21, the linear equilibrium of Eq. 22 with the D2Q9
+     weights, chat_s^2 = 1/3, grad T from the first moment as in Eqs. 49-50).  D2Q9 ignores
+     wdot, vs3 and vs4; it runs on the one-step tile shapes only. */
+  int32_t thermal_q;
   /* Peng-Robinson EOS (Eq. 10): a = 3/49, b = 2/21, R = 1, acentric factor 0.344;
      interaction strength G = -1 (Eq. 9) */
   double a, b, R, acentric, G;
@@ -77,7 +85,7 @@ typedef struct {
      T_top; applied by halfway anti-bounce-back */
   double T_box, T_top, T_bot, hot_dT, hot_x0, hot_sigma;
   double theta_bot_deg, theta_top_deg; /* contact angles of the geometric wetting rule (Eq. 54) */
-  uint32_t flags;        /* LBM_FREEZE_FLOW | LBM_NO_S, tests only */
+  uint32_t flags;        /* LBM_FREEZE_FLOW | LBM_NO_S (tests only) | LBM_BGK */
   uint32_t reserved1;
 } lbm_params;
 
@@ -86,13 +94,13 @@ void lbm_params_default(lbm_params* p, int32_t nx, int32_t ny);
 
 /* Check a parameter set without touching the device.  LBM_E_INVAL if nx or ny < 3, one
    population plane (nx * ny values) exceeds 2^32 - 1 bytes (about 1.07e9 nodes in FP32,
-   5.4e8 in FP64), a relaxation rate is outside (0, 2), wdot outside (0, 1), c_v <= 0, nu <= 0
-   or lambda <= 0. */
+   5.4e8 in FP64), a relaxation rate is outside (0, 2), wdot outside (0, 1), c_v <= 0, nu <= 0,
+   lambda <= 0, thermal_q is not 0, 5 or 9, or flags holds an unknown bit. */
 lbm_status lbm_validate(const lbm_params* p);
 
 /* Exact device bytes a context needs (populations f and g and the temperature history, each
-   in two copies, and a small control block: 128 B per node in FP32, 256 in FP64, plus 48 KiB);
-   0 if lbm_validate fails. */
+   in two copies, and a small control block: 128 B per node in FP32 with the D2Q5 thermal
+   lattice, 160 B with D2Q9; twice that in FP64; plus 48 KiB); 0 if lbm_validate fails. */
 size_t lbm_footprint_bytes(const lbm_params* p);
 
 /* Create a context on the current HIP device over caller-owned device memory dev_mem of
@@ -121,8 +129,9 @@ int64_t lbm_steps_done(const lbm_ctx* h);
    grouped into workgroups and launches: every shape gives bit-identical results.
    lbm_shape_info: LBM_E_INVAL for an unknown precision or k; NULL outputs are skipped.
    A two-step shape keeps the first step's result for the tile and its halo in LDS, which needs
-   a grid larger than that halo region: lbm_shape_fits tells whether shape k can run the grid
-   of *p (1) or not (0, also for invalid parameters). */
+   a grid larger than that halo region and the D2Q5 thermal lattice (the D2Q9 populations do
+   not fit in LDS twice): lbm_shape_fits tells whether shape k can run the simulation of *p (1)
+   or not (0, also for invalid parameters). */
 int lbm_shape_count(int32_t precision);
 lbm_status lbm_shape_info(int32_t precision, int k, int* tile_x, int* tile_y, int* waves, int* steps_per_launch);
 int lbm_shape_fits(const lbm_params* p, int k);
@@ -157,8 +166,8 @@ lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy);
    empty, a non-finite threshold or NULL pointers; LBM_E_STATE before lbm_init. */
 lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi, int32_t* counts);
 
-/* Raw state to / from a host buffer of lbm_state_bytes() bytes: f[9][ny][nx], g[5][ny][nx],
-   history[2][ny][nx] in the context's precision, then three 8-byte words: the step count
+/* Raw state to / from a host buffer of lbm_state_bytes() bytes: f[9][ny][nx], g[Q][ny][nx]
+   (Q = 5 or 9, the thermal lattice), history[2][ny][nx] in the context's precision, then three 8-byte words: the step count
    (int64), rho_ave and T_ref (FP64).  The temperature populations are stored relative to
    T_ref (the mean initial temperature): the buffer holds g_i - what_i T_ref and T - T_ref for
    the history.  Resuming from a saved state reproduces an uninterrupted run bit for bit. */
@@ -180,7 +189,7 @@ const char* lbm_strerror(lbm_status s);
 const char* lbm_last_error(const lbm_ctx* h);
 
 /* ------------------------------------------------------------------------------------
- * Batched execution: many initialised contexts (uneven grids and parameters, same precision,
+ * Batched execution: many initialised contexts (uneven grids and parameters, same precision and
  * same device) advanced together, each step one kernel launch over the tiles of every
  * active instance; launches are captured in a HIP graph and replayed.  Each instance's
  * arithmetic is exactly that of its own lbm_step, so results are bit-identical to running it
@@ -188,7 +197,8 @@ const char* lbm_last_error(const lbm_ctx* h);
  */
 size_t lbm_batch_footprint_bytes(int n);
 
-/* Build a batch over ctxs[0..n) (all initialised, same precision), enqueueing on hip_stream.
+/* Build a batch over ctxs[0..n) (all initialised, same precision and thermal lattice),
+   enqueueing on hip_stream.
    The batch's work is ordered after everything already enqueued on the contexts' own streams
    (their lbm_init, for instance), so a context may be initialised on a stream of its own.
    While the batch exists its members are advanced only through it.  Once lbm_batch_sync has

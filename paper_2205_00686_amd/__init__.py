@@ -16,10 +16,10 @@ import math
 import numpy as np
 
 from . import _native
-from ._native import LBM_FP32, LBM_FP64, LBM_FREEZE_FLOW, LBM_NO_S, NativeLibraryMissing
+from ._native import LBM_BGK, LBM_FP32, LBM_FP64, LBM_FREEZE_FLOW, LBM_NO_S, NativeLibraryMissing
 
 __all__ = ["Solver", "Batch", "LbmError", "params_struct", "coexistence", "critical_temperature",
-           "footprint_bytes", "shapes", "shape_fits", "LBM_FP32", "LBM_FP64", "LBM_FREEZE_FLOW", "LBM_NO_S",
+           "footprint_bytes", "shapes", "shape_fits", "LBM_FP32", "LBM_FP64", "LBM_FREEZE_FLOW", "LBM_NO_S", "LBM_BGK",
            "NativeLibraryMissing"]
 
 
@@ -122,6 +122,7 @@ class Solver:
         self.precision = precision
         self.params = params_struct(prm, precision)
         self.nx, self.ny = int(prm.nx), int(prm.ny)
+        self.q = 9 if int(self.params.thermal_q) == 9 else 5  # velocities of the thermal lattice
         nbytes = int(L.lbm_footprint_bytes(ctypes.byref(self.params)))
         if nbytes == 0:
             raise LbmError(-1, "invalid parameters (lbm_validate)")
@@ -205,21 +206,25 @@ class Solver:
         _check(_native.lib().lbm_load_state(self.handle, buf, len(data)), self.handle)
 
     def state(self, absolute: bool = True):
-        """(f[9], g[5], history[2]) host copies.  The library stores g_i - what_i T_ref and
-        T - T_ref; with absolute=True they are shifted back (FP64), otherwise returned raw in the
-        working precision together with nothing else changed."""
+        """(f[9], g[Q], history[2]) host copies (Q = 5 or 9).  The library stores g_i - what_i T_ref
+        and T - T_ref; with absolute=True they are shifted back (FP64), otherwise returned raw in
+        the working precision."""
         raw = self.save_state()
         dt = np.float64 if self.precision == LBM_FP64 else np.float32
-        n = self.nx * self.ny
-        a = np.frombuffer(raw, dtype=dt, count=16 * n)
+        n, Q = self.nx * self.ny, self.q
+        planes = 9 + Q + 2
+        a = np.frombuffer(raw, dtype=dt, count=planes * n)
         f = a[:9 * n].reshape(9, self.ny, self.nx)
-        g = a[9 * n:14 * n].reshape(5, self.ny, self.nx)
-        h = a[14 * n:16 * n].reshape(2, self.ny, self.nx)
+        g = a[9 * n:(9 + Q) * n].reshape(Q, self.ny, self.nx)
+        h = a[(9 + Q) * n:planes * n].reshape(2, self.ny, self.nx)
         if not absolute:
             return f, g, h
-        T_ref = float(np.frombuffer(raw, dtype=np.float64, count=1, offset=16 * n * a.itemsize + 16)[0])
-        wd = float(self.params.wdot)
-        w = np.array([1.0 - wd] + [wd / 4.0] * 4)[:, None, None]
+        T_ref = float(np.frombuffer(raw, dtype=np.float64, count=1, offset=planes * n * a.itemsize + 16)[0])
+        if Q == 9:
+            w = np.array([4.0 / 9.0] + [1.0 / 9.0] * 4 + [1.0 / 36.0] * 4)[:, None, None]
+        else:
+            wd = float(self.params.wdot)
+            w = np.array([1.0 - wd] + [wd / 4.0] * 4)[:, None, None]
         return f.astype(np.float64), g.astype(np.float64) + w * T_ref, h.astype(np.float64) + T_ref
 
 

@@ -13,12 +13,13 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NUMERIC, LBM_E_STATE = 0, -1, -2, -3, -4, -5
 LBM_FP32, LBM_FP64 = 0, 1
-LBM_FREEZE_FLOW, LBM_NO_S = 1, 2
+LBM_FREEZE_FLOW, LBM_NO_S, LBM_BGK = 1, 2, 8
 
 # every symbol include/lbm.h declares
 EXPORTS = (
     "lbm_params_default", "lbm_validate", "lbm_footprint_bytes", "lbm_create", "lbm_init", "lbm_step",
-    "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_shape_fits", "lbm_set_shape", "lbm_get_shape", "lbm_sync", "lbm_read_fields", "lbm_vapour_rows", "lbm_diagnostics", "lbm_state_bytes", "lbm_save_state",
+    "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_shape_fits", "lbm_set_shape", "lbm_get_shape",
+    "lbm_sync", "lbm_read_fields", "lbm_vapour_rows", "lbm_diagnostics", "lbm_state_bytes", "lbm_save_state",
     "lbm_load_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
     "lbm_last_error", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
     "lbm_batch_remaining", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_sync", "lbm_batch_destroy",
@@ -32,7 +33,7 @@ class NativeLibraryMissing(RuntimeError):
 class LbmParams(ctypes.Structure):
     """Mirror of lbm_params (include/lbm.h)."""
     _fields_ = [
-        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("precision", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("precision", ctypes.c_int32), ("thermal_q", ctypes.c_int32),
         ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double), ("acentric", ctypes.c_double),
         ("G", ctypes.c_double),
         ("nu", ctypes.c_double), ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double),

@@ -57,11 +57,16 @@ int shape_count(int precision) { return precision == LBM_FP64 ? N_F64_SHAPES : N
 const ShapeDef& shape_def(int precision, int k) { return precision == LBM_FP64 ? F64_SHAPES[k] : F32_SHAPES[k]; }
 int tiles_of(int nx, int ny, int ty) { return ((nx + TX - 1) / TX) * ((ny + ty - 1) / ty); }
 
+// Velocities of the thermal lattice of a parameter set (5 or 9).
+int qg_of(const lbm_params* p) { return p->thermal_q == 9 ? 9 : 5; }
+
 // A two-step shape keeps a consistent image of its wide halo region in LDS only if no grid node
-// appears in it twice: the grid must be larger than the region in both directions.
-bool shape_fits(int precision, int k, int nx, int ny) {
+// appears in it twice: the grid must be larger than the region in both directions.  Its LDS
+// holds the D2Q5 thermal populations; D2Q9 runs on the one-step shapes.
+bool shape_fits(int precision, int qg, int k, int nx, int ny) {
   const ShapeDef& d = shape_def(precision, k);
   if (d.depth == 1) return true;
+  if (qg != 5) return false;
   return nx >= TX + 2 * (HXW + 4) + 1 && ny >= d.ty + 2 * (HYW + 3) + 1;
 }
 
@@ -71,9 +76,9 @@ bool shape_fits(int precision, int k, int nx, int ny) {
 // unit (a single wave of workgroups, whose latency matters), the 2-rows-per-thread shape beyond.
 // The autotuner replaces this guess by a measurement.
 constexpr int F32_TWO_STEP_DEFAULT = 6;
-int default_shape(int precision, int nx, int ny) {
+int default_shape(int precision, int qg, int nx, int ny) {
   if (precision == LBM_FP64) return 0;
-  if (shape_fits(precision, F32_TWO_STEP_DEFAULT, nx, ny)) return F32_TWO_STEP_DEFAULT;
+  if (shape_fits(precision, qg, F32_TWO_STEP_DEFAULT, nx, ny)) return F32_TWO_STEP_DEFAULT;
   return tiles_of(nx, ny, F32_SHAPES[0].ty) >= 1024 ? 1 : 0;
 }
 
@@ -121,6 +126,7 @@ struct lbm_batch {
   std::vector<int64_t> pending_launches;  // launches that advanced each instance since the last sync
   hipStream_t stream = nullptr;
   int precision = 0;
+  int qg = 5;                    // thermal lattice of every member
   char* base = nullptr;
   size_t bytes = 0;
   void* d_table = nullptr;
@@ -152,12 +158,12 @@ static hipError_t wait_for_members(hipStream_t bs, const std::vector<lbm_ctx*>& 
 }
 
 // Default shape of a batch: the two-step shape if every member fits it, else by total size.
-static int batch_default_shape(int precision, const std::vector<lbm_ctx*>& ctx) {
+static int batch_default_shape(int precision, int qg, const std::vector<lbm_ctx*>& ctx) {
   if (precision == LBM_FP64) return 0;
   bool fit = true;
   long long tiles = 0;
   for (const lbm_ctx* h : ctx) {
-    fit = fit && shape_fits(precision, F32_TWO_STEP_DEFAULT, h->prm.nx, h->prm.ny);
+    fit = fit && shape_fits(precision, qg, F32_TWO_STEP_DEFAULT, h->prm.nx, h->prm.ny);
     tiles += tiles_of(h->prm.nx, h->prm.ny, F32_SHAPES[0].ty);
   }
   if (fit) return F32_TWO_STEP_DEFAULT;
@@ -196,13 +202,21 @@ static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref)
   d.corr_e = (real)(p->sigma / (1.0 / p->s_e - 0.5));
   d.corr_eps = (real)(p->sigma / (1.0 / p->s_eps - 0.5));
   d.cv = (real)p->cv;
+  d.qg = qg_of(p);
+  // thermal lattice weights, sound speed and the rate tied to lambda (Eqs. 26 and 53; for D2Q9
+  // the D2Q9 weights with chat_s^2 = 1/3)
+  const double cs2h = d.qg == 9 ? 1.0 / 3.0 : p->wdot / 2.0;
+  const double vs1 = 1.0 / (p->lambda / cs2h + 0.5);
   d.wdot = (real)p->wdot;
-  d.w0h = (real)(1.0 - p->wdot);
-  d.w1h = (real)(p->wdot / 4.0);
-  d.vs1 = (real)(1.0 / (p->lambda / (p->wdot / 2.0) + 0.5));
-  d.vs3 = (real)p->vs3;
-  d.vs4 = (real)p->vs4;
-  d.inv_cs2h = (real)(2.0 / p->wdot);
+  d.w0h = (real)(d.qg == 9 ? 4.0 / 9.0 : 1.0 - p->wdot);
+  d.w1h = (real)(d.qg == 9 ? 1.0 / 9.0 : p->wdot / 4.0);
+  d.w2h = (real)(d.qg == 9 ? 1.0 / 36.0 : 0.0);
+  d.vs1 = (real)vs1;
+  // BGK (Eq. 21) on D2Q5 is the MRT step with every rate 1/tau_g
+  const bool bgk = (p->flags & LBM_BGK) != 0;
+  d.vs3 = (real)(bgk ? vs1 : p->vs3);
+  d.vs4 = (real)(bgk ? vs1 : p->vs4);
+  d.inv_cs2h = (real)(1.0 / cs2h);
   d.gx = (real)p->gx;
   d.gy = (real)p->gy;
   d.rho_ave = (real)rho_ave;
@@ -225,7 +239,8 @@ static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref)
   d.om_p = (real)(1.0 - 0.5 / (3.0 * p->nu + 0.5));
   d.opk = (real)(1.0 + pr_kappa(p));
   d.GG = (real)(p->G * p->G);
-  d.two_w1h = (real)(p->wdot / 2.0);
+  d.two_w1h = (real)(d.qg == 9 ? 2.0 / 9.0 : p->wdot / 2.0);
+  d.two_w2h = (real)(d.qg == 9 ? 2.0 / 36.0 : 0.0);
   return d;
 }
 
@@ -273,6 +288,19 @@ static bool set_device(lbm_ctx* h) {
   return true;
 }
 
+// One launch of the step kernel of tile shape S and thermal lattice QG over `grid` workgroups.
+// Two-step shapes exist for the D2Q5 lattice only (shape_fits keeps the others from here).
+template <typename real, class S>
+static void launch_shape(int qg, int grid, hipStream_t st, const void* table, int ninst, const long long* clk,
+                         int k) {
+  const InstDesc<real>* t = (const InstDesc<real>*)table;
+  if (qg == 9) {
+    if constexpr (S::DEPTH == 1) step_kernel<real, S, 9><<<grid, S::NT, 0, st>>>(t, ninst, clk, k);
+  } else {
+    step_kernel<real, S, 5><<<grid, S::NT, 0, st>>>(t, ninst, clk, k);
+  }
+}
+
 // ------------------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -310,7 +338,7 @@ lbm_status lbm_validate(const lbm_params* p) {
   if (!(p->nu > 0.0) || !(p->lambda > 0.0) || !(p->cv > 0.0)) return LBM_E_INVAL;
   if (!(p->wdot > 0.0 && p->wdot < 1.0)) return LBM_E_INVAL;
   const double sp = 1.0 / (3.0 * p->nu + 0.5);
-  const double vs1 = 1.0 / (p->lambda / (p->wdot / 2.0) + 0.5);
+  const double vs1 = 1.0 / (p->lambda / (p->thermal_q == 9 ? 1.0 / 3.0 : p->wdot / 2.0) + 0.5);
   if (!rate_ok(p->s_e) || !rate_ok(p->s_eps) || !rate_ok(p->s_q) || !rate_ok(sp) || !rate_ok(vs1) ||
       !rate_ok(p->vs3) || !rate_ok(p->vs4))
     return LBM_E_INVAL;
@@ -323,6 +351,8 @@ lbm_status lbm_validate(const lbm_params* p) {
       return LBM_E_INVAL;
   }
   if (p->thermal_box && !finite_pos(p->T_box)) return LBM_E_INVAL;
+  if (p->thermal_q != 0 && p->thermal_q != 5 && p->thermal_q != 9) return LBM_E_INVAL;
+  if ((p->flags & ~(uint32_t)(LBM_FREEZE_FLOW | LBM_NO_S | LBM_BGK)) != 0) return LBM_E_INVAL;
   return LBM_OK;
 }
 
@@ -330,7 +360,8 @@ size_t lbm_footprint_bytes(const lbm_params* p) {
   if (lbm_validate(p) != LBM_OK) return 0;
   const size_t N = (size_t)p->nx * (size_t)p->ny;
   const size_t r = p->precision == LBM_FP64 ? 8 : 4;
-  return CTRL_BYTES + partial_bytes() + 2 * align_up(9 * N * r) + 2 * align_up(5 * N * r) + 2 * align_up(2 * N * r);
+  const size_t q = (size_t)qg_of(p);
+  return CTRL_BYTES + partial_bytes() + 2 * align_up(9 * N * r) + 2 * align_up(q * N * r) + 2 * align_up(2 * N * r);
 }
 
 lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hip_stream, lbm_ctx** out) {
@@ -359,14 +390,15 @@ lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hi
   q += CTRL_BYTES;
   h->d_part = (double*)q;
   q += partial_bytes();
+  const size_t qg = (size_t)qg_of(p);
   h->fA = q; q += align_up(9 * h->N * h->rsz);
-  h->gA = q; q += align_up(5 * h->N * h->rsz);
+  h->gA = q; q += align_up(qg * h->N * h->rsz);
   h->fB = q; q += align_up(9 * h->N * h->rsz);
-  h->gB = q; q += align_up(5 * h->N * h->rsz);
+  h->gB = q; q += align_up(qg * h->N * h->rsz);
   h->ThA = q; q += align_up(2 * h->N * h->rsz);
   h->ThB = q;
   h->shape_req = -1;
-  h->shape = default_shape(p->precision, p->nx, p->ny);
+  h->shape = default_shape(p->precision, qg_of(p), p->nx, p->ny);
   h->ntiles = tiles_of(p->nx, p->ny, shape_def(p->precision, h->shape).ty);
   *out = h;
   return LBM_OK;
@@ -421,12 +453,17 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
   HIP_OR_FAIL(h, hipMemcpyAsync(stage + 2 * N, uy, N * sizeof(double), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipMemcpyAsync(stage + 3 * N, T, N * sizeof(double), hipMemcpyHostToDevice, h->stream));
   const int nb = (int)((N + 255) / 256);
+  const int qg = qg_of(&h->prm);
+  // weights of the thermal lattice (Eq. 26; the D2Q9 weights for qg = 9)
+  const double w0 = qg == 9 ? 4.0 / 9.0 : 1.0 - h->prm.wdot;
+  const double w1 = qg == 9 ? 1.0 / 9.0 : h->prm.wdot / 4.0;
+  const double w2 = qg == 9 ? 1.0 / 36.0 : 0.0;
   if (h->prm.precision == LBM_FP64) {
-    init_kernel<double><<<nb, 256, 0, h->stream>>>(stage, (double*)h->fA, (double*)h->gA, (double*)h->ThA, N,
-                                                    1.0 - h->prm.wdot, h->prm.wdot / 4.0, h->T_ref);
+    init_kernel<double><<<nb, 256, 0, h->stream>>>(stage, (double*)h->fA, (double*)h->gA, (double*)h->ThA, N, qg,
+                                                    w0, w1, w2, h->T_ref);
   } else {
-    init_kernel<float><<<nb, 256, 0, h->stream>>>(stage, (float*)h->fA, (float*)h->gA, (float*)h->ThA, N,
-                                                   1.0 - h->prm.wdot, h->prm.wdot / 4.0, h->T_ref);
+    init_kernel<float><<<nb, 256, 0, h->stream>>>(stage, (float*)h->fA, (float*)h->gA, (float*)h->ThA, N, qg, w0,
+                                                   w1, w2, h->T_ref);
   }
   HIP_OR_FAIL(h, hipGetLastError());
   unsigned zero = 0;
@@ -447,16 +484,15 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
   return LBM_OK;
 }
 
-// one launch of the step kernel of tile shape `shape` over `grid` workgroups
-static void launch_step(int precision, int shape, int grid, hipStream_t st, const void* table, int ninst,
+static void launch_step(int precision, int qg, int shape, int grid, hipStream_t st, const void* table, int ninst,
                         const long long* clk, int k) {
-#define LBM_LAUNCH_F32(kk, ty, w, d)                                                                         \
-  case kk:                                                                                                   \
-    step_kernel<float, Shape<ty, w, d>><<<grid, 64 * w, 0, st>>>((const InstDesc<float>*)table, ninst, clk, k); \
+#define LBM_LAUNCH_F32(kk, ty, w, d) \
+  case kk:                           \
+    launch_shape<float, Shape<ty, w, d>>(qg, grid, st, table, ninst, clk, k); \
     break;
-#define LBM_LAUNCH_F64(kk, ty, w, d)                                                                           \
-  case kk:                                                                                                     \
-    step_kernel<double, Shape<ty, w, d>><<<grid, 64 * w, 0, st>>>((const InstDesc<double>*)table, ninst, clk, k); \
+#define LBM_LAUNCH_F64(kk, ty, w, d) \
+  case kk:                           \
+    launch_shape<double, Shape<ty, w, d>>(qg, grid, st, table, ninst, clk, k); \
     break;
   if (precision == LBM_FP64) {
     switch (shape) { LBM_F64_SHAPES(LBM_LAUNCH_F64) default: break; }
@@ -471,7 +507,7 @@ static void launch_step(int precision, int shape, int grid, hipStream_t st, cons
 static lbm_status launch_steps(lbm_ctx* h, int n) {
   const int d = shape_def(h->prm.precision, h->shape).depth;
   for (int k = 0; k < n; ++k)
-    launch_step(h->prm.precision, h->shape, h->ntiles, h->stream, h->d_desc, 1, h->d_clock, k);
+    launch_step(h->prm.precision, qg_of(&h->prm), h->shape, h->ntiles, h->stream, h->d_desc, 1, h->d_clock, k);
   clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n * d);
   HIP_OR_FAIL(h, hipGetLastError());
   return LBM_OK;
@@ -552,15 +588,15 @@ lbm_status lbm_shape_info(int precision, int k, int* tile_x, int* tile_y, int* w
 
 int lbm_shape_fits(const lbm_params* p, int k) {
   if (!p || lbm_validate(p) != LBM_OK || k < 0 || k >= shape_count(p->precision)) return 0;
-  return shape_fits(p->precision, k, p->nx, p->ny) ? 1 : 0;
+  return shape_fits(p->precision, qg_of(p), k, p->nx, p->ny) ? 1 : 0;
 }
 
 lbm_status lbm_set_shape(lbm_ctx* h, int k) {
   if (!h || k < -1 || k >= shape_count(h->prm.precision)) return LBM_E_INVAL;
-  if (k >= 0 && !shape_fits(h->prm.precision, k, h->prm.nx, h->prm.ny))
+  if (k >= 0 && !shape_fits(h->prm.precision, qg_of(&h->prm), k, h->prm.nx, h->prm.ny))
     return fail(h, LBM_E_INVAL, "two-step tile shape on a grid smaller than its halo region");
   h->shape_req = k;
-  const int s = k < 0 ? default_shape(h->prm.precision, h->prm.nx, h->prm.ny) : k;
+  const int s = k < 0 ? default_shape(h->prm.precision, qg_of(&h->prm), h->prm.nx, h->prm.ny) : k;
   if (s == h->shape) return LBM_OK;
   h->shape = s;
   h->ntiles = tiles_of(h->prm.nx, h->prm.ny, shape_def(h->prm.precision, s).ty);
@@ -634,11 +670,11 @@ lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy) {
   per = std::max<size_t>(per, RED_NT);
   const int nparts = (int)((N + per - 1) / per);
   if (h->prm.precision == LBM_FP64)
-    diag_partial_kernel<double><<<nparts, RED_NT, 0, h->stream>>>((const double*)f, (const double*)g, N, h->prm.cv,
-                                                                   h->T_ref, per, h->d_part);
+    diag_partial_kernel<double><<<nparts, RED_NT, 0, h->stream>>>(
+        (const double*)f, (const double*)g, N, qg_of(&h->prm), h->prm.cv, h->T_ref, per, h->d_part);
   else
-    diag_partial_kernel<float><<<nparts, RED_NT, 0, h->stream>>>((const float*)f, (const float*)g, N, h->prm.cv,
-                                                                  h->T_ref, per, h->d_part);
+    diag_partial_kernel<float><<<nparts, RED_NT, 0, h->stream>>>(
+        (const float*)f, (const float*)g, N, qg_of(&h->prm), h->prm.cv, h->T_ref, per, h->d_part);
   diag_final_kernel<<<1, RED_NT, 0, h->stream>>>(h->d_part, nparts, h->d_diag);
   HIP_OR_FAIL(h, hipGetLastError());
   double out[2];
@@ -673,7 +709,10 @@ lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi,
   return check_device_error(h);
 }
 
-size_t lbm_state_bytes(const lbm_ctx* h) { return h ? 16 * h->N * h->rsz + 3 * sizeof(int64_t) : 0; }
+// planes of the raw state: f (9), g (5 or 9), history (2)
+static size_t state_planes(const lbm_ctx* h) { return 9 + (size_t)qg_of(&h->prm) + 2; }
+
+size_t lbm_state_bytes(const lbm_ctx* h) { return h ? state_planes(h) * h->N * h->rsz + 3 * sizeof(int64_t) : 0; }
 
 lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
   if (!h || !host) return LBM_E_INVAL;
@@ -684,14 +723,16 @@ lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
   current_buffers(h, f, g, fo);
   char* q = (char*)host;
   const size_t N = h->N, r = h->rsz;
+  const size_t Q = (size_t)qg_of(&h->prm);
   HIP_OR_FAIL(h, hipMemcpyAsync(q, f, 9 * N * r, hipMemcpyDeviceToHost, h->stream));
-  HIP_OR_FAIL(h, hipMemcpyAsync(q + 9 * N * r, g, 5 * N * r, hipMemcpyDeviceToHost, h->stream));
-  HIP_OR_FAIL(h, hipMemcpyAsync(q + 14 * N * r, current_history(h), 2 * N * r, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(q + 9 * N * r, g, Q * N * r, hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(q + (9 + Q) * N * r, current_history(h), 2 * N * r, hipMemcpyDeviceToHost,
+                                h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   int64_t meta[3] = {h->steps, 0, 0};
   std::memcpy(&meta[1], &h->rho_ave, sizeof(double));
   std::memcpy(&meta[2], &h->T_ref, sizeof(double));
-  std::memcpy(q + 16 * N * r, meta, sizeof(meta));
+  std::memcpy(q + state_planes(h) * N * r, meta, sizeof(meta));
   return check_device_error(h);
 }
 
@@ -702,7 +743,7 @@ lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
   const char* q = (const char*)host;
   const size_t N = h->N, r = h->rsz;
   int64_t meta[3];
-  std::memcpy(meta, q + 16 * N * r, sizeof(meta));
+  std::memcpy(meta, q + state_planes(h) * N * r, sizeof(meta));
   if (meta[0] < 0) return fail(h, LBM_E_INVAL, "corrupt state: negative step count");
   h->steps = meta[0];
   h->gen = 0;  // the state goes to the A buffers
@@ -710,9 +751,11 @@ lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
   std::memcpy(&h->T_ref, &meta[2], sizeof(double));
   void *f, *g, *fo;
   current_buffers(h, f, g, fo);
+  const size_t Q = (size_t)qg_of(&h->prm);
   HIP_OR_FAIL(h, hipMemcpyAsync(f, q, 9 * N * r, hipMemcpyHostToDevice, h->stream));
-  HIP_OR_FAIL(h, hipMemcpyAsync(g, q + 9 * N * r, 5 * N * r, hipMemcpyHostToDevice, h->stream));
-  HIP_OR_FAIL(h, hipMemcpyAsync(current_history(h), q + 14 * N * r, 2 * N * r, hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(g, q + 9 * N * r, Q * N * r, hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(current_history(h), q + (9 + Q) * N * r, 2 * N * r, hipMemcpyHostToDevice,
+                                h->stream));
   unsigned zero = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
   lbm_status s = upload_desc(h);
@@ -844,8 +887,10 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   if (!dev_mem || ((uintptr_t)dev_mem % ALIGN) != 0) return LBM_E_INVAL;
   if (bytes < lbm_batch_footprint_bytes(n)) return LBM_E_NOMEM;
   const int prec = ctxs[0] ? ctxs[0]->prm.precision : -1;
+  const int qg = ctxs[0] ? qg_of(&ctxs[0]->prm) : 0;
   for (int i = 0; i < n; ++i)
-    if (!ctxs[i] || !ctxs[i]->initialised || ctxs[i]->prm.precision != prec) return LBM_E_INVAL;
+    if (!ctxs[i] || !ctxs[i]->initialised || ctxs[i]->prm.precision != prec || qg_of(&ctxs[i]->prm) != qg)
+      return LBM_E_INVAL;
   lbm_batch* b = new (std::nothrow) lbm_batch();
   if (!b) return LBM_E_NOMEM;
   b->ctx.assign(ctxs, ctxs + n);
@@ -854,12 +899,13 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   b->pending_launches.assign(n, 0);
   b->stream = (hipStream_t)hip_stream;
   b->precision = prec;
+  b->qg = qg;
   // the batch's work follows whatever is already enqueued on the members' own streams
   if (wait_for_members(b->stream, b->ctx) != hipSuccess) {
     delete b;
     return LBM_E_DEVICE;
   }
-  b->shape = batch_default_shape(prec, b->ctx);
+  b->shape = batch_default_shape(prec, qg, b->ctx);
   b->base = (char*)dev_mem;
   b->bytes = bytes;
   b->d_clock = (long long*)b->base;
@@ -884,8 +930,8 @@ lbm_status lbm_batch_set_shape(lbm_batch* b, int k) {
   if (!b || k < -1 || k >= shape_count(b->precision)) return LBM_E_INVAL;
   if (k >= 0)
     for (lbm_ctx* h : b->ctx)
-      if (!shape_fits(b->precision, k, h->prm.nx, h->prm.ny)) return LBM_E_INVAL;
-  if (k < 0) k = batch_default_shape(b->precision, b->ctx);
+      if (!shape_fits(b->precision, b->qg, k, h->prm.nx, h->prm.ny)) return LBM_E_INVAL;
+  if (k < 0) k = batch_default_shape(b->precision, b->qg, b->ctx);
   b->shape = k;  // tile counts change; the graph is recaptured at the next upload
   return LBM_OK;
 }
@@ -967,7 +1013,8 @@ static lbm_status batch_upload(lbm_batch* b, int64_t todo) {
 static lbm_status batch_launch(lbm_batch* b, int nl) {
   const int n = (int)b->ctx.size();
   const int d = shape_def(b->precision, b->shape).depth;
-  for (int s = 0; s < nl; ++s) launch_step(b->precision, b->shape, b->total_tiles, b->stream, b->d_table, n, b->d_clock, s);
+  for (int s = 0; s < nl; ++s)
+    launch_step(b->precision, b->qg, b->shape, b->total_tiles, b->stream, b->d_table, n, b->d_clock, s);
   clock_advance_kernel<<<1, 64, 0, b->stream>>>(b->d_clock, (long long)nl * d);
   HIP_OR_FAIL(b->ctx[0], hipGetLastError());
   return LBM_OK;

@@ -6,10 +6,12 @@ namespace lbm {
 
 // f_i = f_i^eq(rho, u) (Eq. 3), g_i = what_i T (Eq. 22), both history levels = T.
 // Inputs are FP64 fields staged in device memory: in[0..N) rho, [N..2N) ux, [2N..3N) uy,
-// [3N..4N) T.
+// [3N..4N) T.  Thermal weights: w0h (rest), w1h (axes), w2h (diagonals of the D2Q9 thermal
+// lattice, qg = 9).
 template <typename real>
 __global__ void init_kernel(const double* __restrict__ in, real* __restrict__ f, real* __restrict__ g,
-                            real* __restrict__ Th, size_t N, double w0h, double w1h, double T_ref) {
+                            real* __restrict__ Th, size_t N, int qg, double w0h, double w1h, double w2h,
+                            double T_ref) {
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const double rho = in[k], ux = in[N + k], uy = in[2 * N + k], T = in[3 * N + k];
@@ -26,17 +28,25 @@ __global__ void init_kernel(const double* __restrict__ in, real* __restrict__ f,
   g[k] = (real)(w0h * Tr);
 #pragma unroll
   for (int i = 1; i < 5; ++i) g[i * N + k] = (real)(w1h * Tr);
+  if (qg == 9) {
+#pragma unroll
+    for (int i = 5; i < 9; ++i) g[i * N + k] = (real)(w2h * Tr);
+  }
   Th[k] = (real)Tr;
   Th[N + k] = (real)Tr;
 }
 
-// rho and T - T_ref at a fluid node (already wrapped)
+// rho and T - T_ref at a fluid node (already wrapped), summed in the order of the step kernel
 template <typename real>
 __device__ __forceinline__ void rho_T(const real* __restrict__ f, const real* __restrict__ g, size_t N, int o,
-                                      real& rho, real& Tr) {
+                                      int qg, real& rho, real& Tr) {
   rho = ((f[o] + f[N + o]) + (f[2 * N + o] + f[3 * N + o])) +
         ((f[4 * N + o] + f[5 * N + o]) + (f[6 * N + o] + f[7 * N + o])) + f[8 * N + o];
-  Tr = ((g[o] + g[N + o]) + (g[2 * N + o] + g[3 * N + o])) + g[4 * N + o];
+  if (qg == 9)
+    Tr = ((g[o] + g[N + o]) + (g[2 * N + o] + g[3 * N + o])) +
+         ((g[4 * N + o] + g[5 * N + o]) + (g[6 * N + o] + g[7 * N + o])) + g[8 * N + o];
+  else
+    Tr = ((g[o] + g[N + o]) + (g[2 * N + o] + g[3 * N + o])) + g[4 * N + o];
 }
 
 // psi at (x, y) with wrapping and, in walled domains, the wetting ghost rows (Eq. 54)
@@ -50,13 +60,13 @@ __device__ real psi_any(const DevParams<real>& p, const real* __restrict__ f, co
     const int top = y == ny;
     const int y1 = top ? ny - 1 : 0, y2 = top ? ny - 2 : 1;
     real r2, r1p, r1m, tt;
-    rho_T(f, g, N, y2 * nx + x, r2, tt);
-    rho_T(f, g, N, y1 * nx + wrapi(x + 1, nx, true), r1p, tt);
-    rho_T(f, g, N, y1 * nx + wrapi(x - 1, nx, true), r1m, tt);
+    rho_T(f, g, N, y2 * nx + x, p.qg, r2, tt);
+    rho_T(f, g, N, y1 * nx + wrapi(x + 1, nx, true), p.qg, r1p, tt);
+    rho_T(f, g, N, y1 * nx + wrapi(x - 1, nx, true), p.qg, r1m, tt);
     rho = r2 + (top ? p.tan_top : p.tan_bot) * fabs(r1p - r1m);
     T = wall_temperature(p, top, x);
   } else {
-    rho_T(f, g, N, y * nx + x, rho, T);
+    rho_T(f, g, N, y * nx + x, p.qg, rho, T);
     T = p.T_ref + T;
   }
   return pseudo(p, rho, T, err);
@@ -74,7 +84,7 @@ __global__ void fields_kernel(DevParams<real> p, const real* __restrict__ f, con
   unsigned err = 0u;
   const int o = (int)k;
   real rho, Tr;
-  rho_T(f, g, N, o, rho, Tr);
+  rho_T(f, g, N, o, p.qg, rho, Tr);
   real jx = (f[N + o] - f[3 * N + o]) + ((f[5 * N + o] - f[6 * N + o]) + (f[8 * N + o] - f[7 * N + o]));
   real jy = (f[2 * N + o] - f[4 * N + o]) + ((f[5 * N + o] + f[6 * N + o]) - (f[7 * N + o] + f[8 * N + o]));
   real fx = real(0), fy = real(0);
@@ -133,15 +143,15 @@ constexpr int RED_NT = 256;
 
 template <typename real>
 __global__ __launch_bounds__(RED_NT) void diag_partial_kernel(const real* __restrict__ f, const real* __restrict__ g,
-                                                              size_t N, double cv, double T_ref, size_t per_block,
-                                                              double* __restrict__ partials) {
+                                                              size_t N, int qg, double cv, double T_ref,
+                                                              size_t per_block, double* __restrict__ partials) {
   __shared__ double sm[RED_NT], se[RED_NT];
   const size_t begin = (size_t)blockIdx.x * per_block;
   const size_t end = begin + per_block < N ? begin + per_block : N;
   double m = 0.0, e = 0.0;
   for (size_t k = begin + threadIdx.x; k < end; k += RED_NT) {
     real rho, Tr;
-    rho_T(f, g, N, (int)k, rho, Tr);
+    rho_T(f, g, N, (int)k, qg, rho, Tr);
     m += (double)rho;
     e += (double)rho * cv * (T_ref + (double)Tr);
   }

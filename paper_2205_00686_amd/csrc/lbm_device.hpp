@@ -53,6 +53,7 @@ constexpr unsigned ERR_PSI = 4u;   // pseudopotential argument < 0
 
 constexpr unsigned FL_FREEZE_FLOW = 1u;
 constexpr unsigned FL_NO_S = 2u;
+constexpr unsigned FL_BGK = 8u;
 
 // Constants of one simulation, derived once on the host in FP64 and stored in the working
 // precision.
@@ -62,8 +63,8 @@ struct DevParams {
   real inv_Tc, inv_G;
   real s_e, s_eps, s_q, s_p;        // D2Q9 MRT rates (Eq. 5)
   real corr_e, corr_eps;            // sigma / (1/s - 1/2) of Li's forcing (Eq. 8)
-  real cv, wdot, w0h, w1h;          // D2Q5 weights (Eq. 26)
-  real vs1, vs3, vs4, inv_cs2h;     // D2Q5 MRT rates; 1/chat_s^2
+  real cv, wdot, w0h, w1h, w2h;     // thermal weights: D2Q5 (Eq. 26; w2h unused) or D2Q9 (rest, axis, diagonal)
+  real vs1, vs3, vs4, inv_cs2h;     // D2Q5 MRT rates (vs1 = 1/tau_g, also the D2Q9 BGK rate); 1/chat_s^2
   real gx, gy, rho_ave;             // buoyancy
   real T_box, T_top, T_bot, hot_dT, hot_x0, inv_2s2;
   real tan_bot, tan_top;            // tan(pi/2 - theta) of the wetting rule (Eq. 54)
@@ -71,10 +72,10 @@ struct DevParams {
   // Derived on the host: without scalar floating-point units, a constant computed in the kernel
   // costs a vector instruction per wavefront, as much as per-node arithmetic.
   real om_e, om_eps, om_q, om_p;    // 1 - s/2 of the forcing term (Eq. 5)
-  real opk, GG, two_w1h;            // 1 + kappa; G^2; 2 w_1
+  real opk, GG, two_w1h, two_w2h;   // 1 + kappa; G^2; 2 w_axis, 2 w_diagonal
   int y_walls, thermal_box;
   unsigned flags;
-  int pad;
+  int qg;                           // velocities of the thermal lattice: 5 or 9
 };
 
 // One simulation as seen by the step kernel.  The step kernel serves single runs (a one-entry

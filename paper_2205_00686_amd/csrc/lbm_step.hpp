@@ -28,19 +28,20 @@
 
 namespace lbm {
 
-// Per-node fields a step keeps in LDS, over a MY x MX region.
-template <typename real, int MY, int MX>
+// Per-node fields a step keeps in LDS, over a MY x MX region (QG: velocities of the thermal
+// lattice, 5 or 9).
+template <typename real, int MY, int MX, int QG = 5>
 struct MacroLds {
   real rho[MY][MX];
   real irc[MY][MX];  // 1 / (rho c_v), needed at the streaming destination
   real psi[MY][MX];
   real ux[MY][MX];   // holds j_x after phase 1, u_x after phase 2
   real uy[MY][MX];
-  real g[4][MY][MX];  // pre-collision g_1..g_4 (needed at the streaming destination)
+  real g[QG - 1][MY][MX];  // pre-collision g_1..g_{QG-1} (needed at the streaming destination)
 };
 
-template <typename real, int EYW>
-using StepLds = MacroLds<real, EYW, EXW>;
+template <typename real, int EYW, int QG = 5>
+using StepLds = MacroLds<real, EYW, EXW, QG>;
 
 // LDS of a two-step launch: the first step's fields over the wide region, aliased by the second
 // step's fields once the first step has streamed; the state between the two steps (f and g
@@ -161,13 +162,20 @@ __device__ __forceinline__ void stb(gptr<char> base, unsigned off, real v) {
 
 // rho, j, T of a node and its LDS entries (Eqs. 11 and 25), psi with error checks; returns
 // (dp/dT)_rho for the node's own collision
-template <typename real, class LDS>
+// T - T_ref = sum of the thermal populations (Eq. 25), in a fixed order per lattice
+template <typename real, int QG>
+__device__ __forceinline__ real thermal_sum(const real (&g)[QG]) {
+  if constexpr (QG == 9) return ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7])) + g[8];
+  else return ((g[0] + g[1]) + (g[2] + g[3])) + g[4];
+}
+
+template <typename real, int QG, class LDS>
 __device__ __forceinline__ real node_macro_to_lds(LDS& L, int ex, int ey, const DevParams<real>& p,
-                                                  const real (&f)[9], const real (&g)[5], unsigned& err) {
+                                                  const real (&f)[9], const real (&g)[QG], unsigned& err) {
   const real rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const real jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
   const real jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
-  const real T = p.T_ref + (((g[0] + g[1]) + (g[2] + g[3])) + g[4]);
+  const real T = p.T_ref + thermal_sum<real, QG>(g);
   real psi = real(0), dpdT = real(0);
   if (!(rho > real(0)) || !isfinite(rho)) {
     err |= ERR_RHO;
@@ -183,10 +191,8 @@ __device__ __forceinline__ real node_macro_to_lds(LDS& L, int ex, int ey, const 
   L.psi[ey][ex] = psi;
   L.ux[ey][ex] = jx;
   L.uy[ey][ex] = jy;
-  L.g[0][ey][ex] = g[1];
-  L.g[1][ey][ex] = g[2];
-  L.g[2][ey][ex] = g[3];
-  L.g[3][ey][ex] = g[4];
+#pragma unroll
+  for (int k = 0; k < QG - 1; ++k) L.g[k][ey][ex] = g[k + 1];
   return dpdT;
 }
 
@@ -197,8 +203,9 @@ __device__ __forceinline__ void zero_lds_cell(LDS& L, int ex, int ey) {
   L.psi[ey][ex] = real(0);
   L.ux[ey][ex] = real(0);
   L.uy[ey][ex] = real(0);
+  constexpr int NG = (int)(sizeof(L.g) / sizeof(L.g[0]));
 #pragma unroll
-  for (int k = 0; k < 4; ++k) L.g[k][ey][ex] = real(0);
+  for (int k = 0; k < NG; ++k) L.g[k][ey][ex] = real(0);
 }
 
 // Stencil of the interaction force: F_m = -G psi(x) (sx, sy) with (sx, sy) =
@@ -251,18 +258,26 @@ __device__ __forceinline__ real node_divu(const LDS& L, int ex, int ey, bool gs_
          real(1.0 / 12.0) * (((uxNE - uxSW) + (uxSE - uxNW)) + ((uyNE - uySW) + (uyNW - uySE)));
 }
 
-// Collision of one node: grad T from m_1, m_2 of the D2Q5 populations (Eqs. 49-50), Q (Eq. 20),
-// S (Eq. 24), the D2Q9 MRT collision with Li's forcing and the D2Q5 MRT collision (Eq. 39).
+// Collision of one node: grad T from the relaxed non-equilibrium first moments of the thermal
+// populations (Eqs. 49-50), Q (Eq. 20), S (Eq. 24), the D2Q9 MRT collision with Li's forcing,
+// and the thermal collision: D2Q5 MRT (Eq. 39), or BGK (Eq. 21) on the D2Q9 thermal lattice.
 // Tr = T - T_ref of the node; T1, T2 are T(t-1) - T_ref and T(t-2) - T_ref.
-template <typename real>
+template <typename real, int QG>
 __device__ __forceinline__ void node_collide(const DevParams<real>& p, bool freeze, const real (&f)[9],
-                                             const real (&g)[5], real rho, real ux, real uy, real fx, real fy,
+                                             const real (&g)[QG], real rho, real ux, real uy, real fx, real fy,
                                              real S2, real dpdT, real divu, real T1, real T2, real (&fs_)[9],
-                                             real (&gs_)[5], real& Tr) {
-  Tr = ((g[0] + g[1]) + (g[2] + g[3])) + g[4];  // T - T_ref
+                                             real (&gs_)[QG], real& Tr) {
+  Tr = thermal_sum<real, QG>(g);  // T - T_ref
   const real T = p.T_ref + Tr;
-  const real dm1 = p.vs1 * (g[1] - g[3]);  // relaxed non-equilibrium parts of m_1, m_2 (Eq. 39)
-  const real dm2 = p.vs1 * (g[2] - g[4]);
+  // first moments sum_i c_i g_i (their equilibrium parts vanish), relaxed by 1/tau_g
+  real dm1, dm2;
+  if constexpr (QG == 9) {
+    dm1 = p.vs1 * ((g[1] - g[3]) + ((g[5] - g[6]) + (g[8] - g[7])));
+    dm2 = p.vs1 * ((g[2] - g[4]) + ((g[5] + g[6]) - (g[7] + g[8])));
+  } else {
+    dm1 = p.vs1 * (g[1] - g[3]);
+    dm2 = p.vs1 * (g[2] - g[4]);
+  }
   const real dTx = -dm1 * p.inv_cs2h;
   const real dTy = -dm2 * p.inv_cs2h;
   const real rcv = rho * p.cv;
@@ -318,8 +333,19 @@ __device__ __forceinline__ void node_collide(const DevParams<real>& p, bool free
     fs_[8] = fi[8] + ((diag + (dx_ - dy_)) - e8);
   }
 
-  // ---- D2Q5 MRT collision (Eq. 39) with the non-orthogonal basis of Eq. (40)
-  {
+  if constexpr (QG == 9) {
+    // ---- BGK collision (Eq. 21) with the linear equilibrium w_i T (Eq. 22); the stored g and
+    // Tr are shifted by w_i T_ref and T_ref alike, so g - g_eq is unchanged by the shift
+    const real src = Q + Ssum;
+    const real e0 = p.w0h * Tr, e1 = p.w1h * Tr, e2 = p.w2h * Tr;
+    const real s0 = p.w0h * src, s1 = p.w1h * src, s2 = p.w2h * src;
+    gs_[0] = g[0] + (p.vs1 * (e0 - g[0]) + s0);
+#pragma unroll
+    for (int i = 1; i < 5; ++i) gs_[i] = g[i] + (p.vs1 * (e1 - g[i]) + s1);
+#pragma unroll
+    for (int i = 5; i < 9; ++i) gs_[i] = g[i] + (p.vs1 * (e2 - g[i]) + s2);
+  } else {
+    // ---- D2Q5 MRT collision (Eq. 39) with the non-orthogonal basis of Eq. (40)
     const real* gi = g;
     const real dm3 = p.vs3 * (((gi[1] + gi[2]) + (gi[3] + gi[4])) - p.wdot * Tr);
     const real dm4 = p.vs4 * ((gi[1] - gi[2]) + (gi[3] - gi[4]));
@@ -376,9 +402,10 @@ struct LdsState {
 // handles periodic wrap, wall ghost rows, bounce-back and anti-bounce-back.  Both variants
 // perform the same arithmetic on every node.  FROM_LDS: f and g come from `st` (second step of
 // a two-step launch) instead of the global source buffers.
-template <typename real, class S, int V, bool FROM_LDS>
-__device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real, S::EYW>& L, bool odd, int x0, int y0,
-                                          const LdsState<real, S>& st, unsigned& err) {
+template <typename real, class S, int V, bool FROM_LDS, int QG = 5>
+__device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real, S::EYW, QG>& L, bool odd, int x0,
+                                          int y0, const LdsState<real, S>& st, unsigned& err) {
+  static_assert(!FROM_LDS || QG == 5, "the two-step state in LDS holds D2Q5 thermal populations");
   constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, RING = S::RING, URING = S::URING, EYW = S::EYW;
   const int nx = D.nx, ny = D.ny;
   constexpr ptrdiff_t SZ = sizeof(real);
@@ -414,7 +441,7 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   constexpr int RPN = (RING + NT - 1) / NT;  // halo ring nodes per thread
   const int xg = x0 + tx;
   const int xw = wx(xg);
-  real f[RPT][9], g[RPT][5], T1[RPT], T2[RPT], dpdT[RPT];
+  real f[RPT][9], g[RPT][QG], T1[RPT], T2[RPT], dpdT[RPT];
   unsigned ob[RPT];  // byte offset of the own node in a plane
   bool own[RPT];
 #pragma unroll
@@ -424,18 +451,18 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
     own[r] = fluid_row(yg);
     ob[r] = (unsigned)(wy(yg) * nx + xw) * (unsigned)SZ;
     if (own[r]) {
-      if (FROM_LDS) {
+      if constexpr (FROM_LDS) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[r][i] = st.sf[i][ey][HXW + tx];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) g[r][i] = st.sg[i][ey][HXW + tx];
+        for (int i = 0; i < QG; ++i) g[r][i] = st.sg[i][ey][HXW + tx];
         T1[r] = st.T1[r];
         T2[r] = st.T2[r];
       } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[r][i] = ldb<real>(fsp(i), ob[r]);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) g[r][i] = ldb<real>(gsp(i), ob[r]);
+        for (int i = 0; i < QG; ++i) g[r][i] = ldb<real>(gsp(i), ob[r]);
         T1[r] = ldb<real>(Ths, ob[r]);
         T2[r] = ldb<real>(sbase(Ths + PB), ob[r]);
       }
@@ -443,11 +470,11 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[r][i] = real(0);
 #pragma unroll
-      for (int i = 0; i < 5; ++i) g[r][i] = real(0);
+      for (int i = 0; i < QG; ++i) g[r][i] = real(0);
       T1[r] = T2[r] = real(0);
     }
   }
-  real fr[RPN][9], gr[RPN][5];
+  real fr[RPN][9], gr[RPN][QG];
   int rex[RPN], rey[RPN];
   bool rin[RPN], rfl[RPN];
 #pragma unroll
@@ -458,17 +485,17 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
     const int yg = y0 - HYW + rey[q];
     rfl[q] = rin[q] && fluid_row(yg);
     if (rfl[q]) {
-      if (FROM_LDS) {
+      if constexpr (FROM_LDS) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) fr[q][i] = st.sf[i][rey[q]][rex[q]];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) gr[q][i] = st.sg[i][rey[q]][rex[q]];
+        for (int i = 0; i < QG; ++i) gr[q][i] = st.sg[i][rey[q]][rex[q]];
       } else {
         const unsigned o = (unsigned)(wy(yg) * nx + wx(x0 - HXW + rex[q])) * (unsigned)SZ;
 #pragma unroll
         for (int i = 0; i < 9; ++i) fr[q][i] = ldb<real>(fsp(i), o);
 #pragma unroll
-        for (int i = 0; i < 5; ++i) gr[q][i] = ldb<real>(gsp(i), o);
+        for (int i = 0; i < QG; ++i) gr[q][i] = ldb<real>(gsp(i), o);
       }
     }
   }
@@ -476,12 +503,12 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   for (int r = 0; r < RPT; ++r) {
     const int ey = HYW + ty + WAVES * r;
     dpdT[r] = real(0);
-    if (own[r]) dpdT[r] = node_macro_to_lds<real>(L, HXW + tx, ey, p, f[r], g[r], err);
+    if (own[r]) dpdT[r] = node_macro_to_lds<real, QG>(L, HXW + tx, ey, p, f[r], g[r], err);
     else zero_lds_cell<real>(L, HXW + tx, ey);
   }
 #pragma unroll
   for (int q = 0; q < RPN; ++q) {
-    if (rfl[q]) (void)node_macro_to_lds<real>(L, rex[q], rey[q], p, fr[q], gr[q], err);
+    if (rfl[q]) (void)node_macro_to_lds<real, QG>(L, rex[q], rey[q], p, fr[q], gr[q], err);
     else if (rin[q]) zero_lds_cell<real>(L, rex[q], rey[q]);
   }
   __syncthreads();
@@ -520,9 +547,9 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
     const real ux = L.ux[ey][ex], uy = L.uy[ey][ex];
     const unsigned o = ob[r];
     const real divu = node_divu<real>(L, ex, ey, walls && yg == 0, walls && yg == ny - 1);
-    real fs_[9], gs_[5], Tr;
-    node_collide<real>(p, freeze, f[r], g[r], rho, ux, uy, Fx[r], Fy[r], S2[r], dpdT[r], divu, T1[r], T2[r], fs_,
-                       gs_, Tr);
+    real fs_[9], gs_[QG], Tr;
+    node_collide<real, QG>(p, freeze, f[r], g[r], rho, ux, uy, Fx[r], Fy[r], S2[r], dpdT[r], divu, T1[r], T2[r],
+                           fs_, gs_, Tr);
     stb(Thd, o, Tr);
     stb(sbase(Thd + PB), o, T1[r]);
 
@@ -581,7 +608,34 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
     //   g_i(y, t+1) = g_i(y, t) + [g*_i(y - c_i) - g_i(y, t)] / (rho(y, t) c_v)
     // An edge with a Dirichlet temperature replaces the upstream term by anti-bounce-back,
     // -g*_i(y) + 2 what_i T_w, for the population entering y in the opposite direction.
-    {
+    if constexpr (QG == 9) {
+      // D2Q9 thermal lattice: a population whose destination lies beyond a Dirichlet edge
+      // (x edges of the temperature box; y edges of the box or the walls, corners included)
+      // returns to the node in the opposite direction by anti-bounce-back at the temperature of
+      // that edge; every other one is pushed and blended at its destination.
+      const real ircv = L.irc[ey][ex];
+      stb(gdp(0), o, g[r][0] + (gs_[0] - g[r][0]) * ircv);
+      constexpr int CXg[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+      constexpr int CYg[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+      constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#pragma unroll
+      for (int i = 1; i < 9; ++i) {
+        const int dx = CXg[i], dy = CYg[i];
+        const bool out_x = tb && ((dx > 0 && xg == nx - 1) || (dx < 0 && xg == 0));
+        const bool out_y = (walls || tb) && ((dy > 0 && yg == ny - 1) || (dy < 0 && yg == 0));
+        if (out_x || out_y) {
+          const real Tw = tb ? p.T_box : dy < 0 ? wall_temperature(p, 0, xw) : p.T_top;
+          const real two_w = i < 5 ? p.two_w1h : p.two_w2h;
+          const int b = OPP[i];
+          const real up = -gs_[i] + two_w * (Tw - p.T_ref);
+          stb(gdp(b), o, g[r][b] + (up - g[r][b]) * ircv);
+        } else {
+          const real gold = L.g[i - 1][ey + dy][ex + dx];
+          auto bp = dst(gdp(i), dx, dy, off);
+          stb(bp, off, gold + (gs_[i] - gold) * L.irc[ey + dy][ex + dx]);
+        }
+      }
+    } else {
       const real ircv = L.irc[ey][ex];
       stb(gdp(0), o, g[r][0] + (gs_[0] - g[r][0]) * ircv);
       const bool out_e = tb && xg == nx - 1, out_w = tb && xg == 0;
@@ -700,7 +754,7 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
 #pragma unroll
   for (int n = 0; n < NN; ++n) {
     dpdT[n] = real(0);
-    if (fl[n]) dpdT[n] = node_macro_to_lds<real>(L.m1, mx_[n], my_[n], p, f[n], g[n], err);
+    if (fl[n]) dpdT[n] = node_macro_to_lds<real, 5>(L.m1, mx_[n], my_[n], p, f[n], g[n], err);
     else if (valid[n]) zero_lds_cell<real>(L.m1, mx_[n], my_[n]);
   }
   __syncthreads();
@@ -728,7 +782,7 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
     const real ux = L.m1.ux[my][mx], uy = L.m1.uy[my][mx];
     const real divu = node_divu<real>(L.m1, mx, my, walls && yw == 0, walls && yw == ny - 1);
     real fs_[9], gs_[5], Tr;
-    node_collide<real>(p, freeze, f[n], g[n], rho, ux, uy, Fx[n], Fy[n], S2[n], dpdT[n], divu, T1[n], T2[n], fs_, gs_,
+    node_collide<real, 5>(p, freeze, f[n], g[n], rho, ux, uy, Fx[n], Fy[n], S2[n], dpdT[n], divu, T1[n], T2[n], fs_, gs_,
                        Tr);
     if (n < RPT) {  // own node: history after this step
       Tn1[n] = Tr;
@@ -813,9 +867,10 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
 // (one step if only one is left in its budget).  The device clock counts steps; the launch's
 // step is t = clock + k DEPTH.  Each launch swaps the A/B buffers once, so the source buffer is
 // B exactly when b_base plus the number of launches since t_base is odd.
-template <typename real, class S>
+template <typename real, class S, int QG>
 __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __restrict__ table, int ninst,
                                                      const long long* __restrict__ clock, int k) {
+  static_assert(QG == 5 || (QG == 9 && S::DEPTH == 1), "D2Q9 thermal populations: one step per launch");
   // ---- which simulation and which tile (uniform per workgroup).  Workgroups are dispatched to
   // the 8 XCDs round-robin; remap so that each XCD takes a contiguous range of tiles: neighbouring
   // tiles then share one L2, where their halo reads hit and where the partial cache lines of the
@@ -861,9 +916,9 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
       else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false>(D, L2.m2, odd, x0, y0, none, err); });
     }
   } else {
-    __shared__ StepLds<real, S::EYW> L;
-    if (interior) step_body<real, S, 0, false>(D, L, odd, x0, y0, none, err);
-    else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false>(D, L, odd, x0, y0, none, err); });
+    __shared__ StepLds<real, S::EYW, QG> L;
+    if (interior) step_body<real, S, 0, false, QG>(D, L, odd, x0, y0, none, err);
+    else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false, QG>(D, L, odd, x0, y0, none, err); });
   }
   // A failing simulation flags every node.  One atomic per thread, or even per wavefront, on one
   // word would serialise the launch, so a wavefront ORs its flags with ballots and sets only the

@@ -47,8 +47,15 @@ def test_validate_and_footprint(L):
     assert 128 * n <= fp <= 128 * n + 64 * 1024  # f, g and history twice, FP32, plus a small control block
     p.precision = 1
     assert 256 * n <= L.lbm_footprint_bytes(ctypes.byref(p)) <= 256 * n + 64 * 1024
+    # D2Q9 thermal lattice: 4 more populations in two copies, 160 B per node in FP32
+    p.thermal_q = 9
+    assert 320 * n <= L.lbm_footprint_bytes(ctypes.byref(p)) <= 320 * n + 64 * 1024
+    p.precision = 0
+    assert 160 * n <= L.lbm_footprint_bytes(ctypes.byref(p)) <= 160 * n + 64 * 1024
+    p.flags = _native.LBM_BGK | _native.LBM_NO_S
+    assert L.lbm_validate(ctypes.byref(p)) == 0
     for field, bad in (("nx", 2), ("ny", 1), ("nu", -0.1), ("s_e", 2.0), ("wdot", 1.0), ("cv", 0.0),
-                       ("precision", 7), ("lambda_", 0.0)):
+                       ("precision", 7), ("lambda_", 0.0), ("thermal_q", 7), ("flags", 4)):
         q = _native.LbmParams()
         L.lbm_params_default(ctypes.byref(q), 64, 64)
         setattr(q, field, bad)
@@ -153,6 +160,10 @@ def test_two_step_shapes_need_a_grid_larger_than_their_halo(L):
         assert not shape_fits(Params(nx=78, ny=ty + 11), k)
         assert not shape_fits(Params(nx=79, ny=ty + 10), k)
     assert all(shape_fits(Params(nx=3, ny=3), k) for k, s in enumerate(shapes(0)) if s[3] == 1)
+    # the LDS of a two-step launch holds D2Q5 thermal populations only
+    for k in two:
+        assert not shape_fits(Params(nx=512, ny=512, thermal_q=9), k)
+    assert all(shape_fits(Params(nx=512, ny=512, thermal_q=9), k) for k, s in enumerate(shapes(0)) if s[3] == 1)
     p = _native.LbmParams()
     L.lbm_params_default(ctypes.byref(p), 2, 64)  # invalid parameters
     assert L.lbm_shape_fits(ctypes.byref(p), 0) == 0
