@@ -14,6 +14,7 @@ the library's stream), and the FP64 CPU oracle timed on a bounded sample of the 
   python bench.py --mode batch [--instances 64 --steps 2000]     batched gravity sweep vs plain
   python bench.py --mode serve [--requests 256 --rate 20]        continuous batching vs FIFO
   python bench.py --mode fritz [--gravities 1e-5,...,6e-5]       bubble departure diameter vs gravity
+  python bench.py --mode lattice                                 thermal lattice: D2Q5 MRT / BGK vs D2Q9
 """
 from __future__ import annotations
 
@@ -203,6 +204,94 @@ def run_serve_mode(args):
     print(json.dumps(out), flush=True)
 
 
+LATTICES = (("D2Q5-MRT", {}), ("D2Q5-BGK", {"flags": 8}), ("D2Q9-BGK", {"thermal_q": 9}))
+
+
+def _time_solver(s, steps):
+    """ms per step of Solver s over `steps` graph-replayed steps (HIP events on its stream)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.step(steps)
+    e1.record(s.stream)
+    e1.synchronize()
+    s.sync()
+    return e0.elapsed_time(e1) / steps
+
+
+def _pulse_error(lbm, kw, rho0, n=128, s0=8.0, A=0.005, steps=400):
+    """Frozen-flow Gaussian temperature pulse on the GPU (FP32) against the exact diffusion
+    solution with D = lambda / (rho c_v): max |T - T_exact| / A, or the step of a numerical failure."""
+    import numpy as np
+    from workloads import FREEZE_FLOW, Params
+    p = Params(nx=n, ny=n, **kw)
+    p = p.replace(flags=p.flags | FREEZE_FLOW)
+    T0 = 0.86 * lbm.critical_temperature(p)
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    r2 = (x - n / 2) ** 2 + (y - n / 2) ** 2
+    T = T0 + A * np.exp(-r2 / (2 * s0 ** 2))
+    s = lbm.Solver(p).init(np.full((n, n), rho0), 0 * T, 0 * T, T)
+    try:
+        for k in range(steps // 50):
+            s.step(50)
+            s.sync()
+    except lbm.LbmError:
+        s.close()
+        return {"diverged_by_step": (k + 1) * 50}
+    Tn = s.fields()[3]
+    s.close()
+    D = p.lambda_ / (rho0 * p.cv)
+    s2 = s0 ** 2 + 2 * D * steps
+    Ta = T0 + A * s0 ** 2 / s2 * np.exp(-r2 / (2 * s2))
+    return {"max_err_over_A": float(np.abs(Tn - Ta).max() / A)}
+
+
+def run_lattice_mode(args):
+    """Thermal-lattice ablation (the paper's efficiency argument for the D2Q5 lattice): the
+    D2Q5 model with the MRT collision of Eq. (39), its BGK variant (Eq. 21) and the D2Q9
+    thermal lattice with the BGK collision, on the evaporation workload at 512 x 512 and at
+    2048 x 2048 (a working set far beyond the 256 MB Infinity Cache), FP32.  Each variant runs at
+    its best one-step tile shape (D2Q9 has no two-step shape), and the D2Q5 MRT also at its best
+    shape overall.  Plus the frozen-flow Gaussian pulse error of each variant at rho c_v = 5 and 1."""
+    import paper_2205_00686_amd as lbm
+    from paper_2205_00686_amd import autotune
+    from workloads import Params, evaporation
+
+    base = Params()
+    Tc = lbm.critical_temperature(base)
+    rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
+    one_step = [k for k, sh in enumerate(lbm.shapes(lbm.LBM_FP32)) if sh[3] == 1]
+    rows = []
+    for nx, ny in ((512, 512), (2048, 2048)):
+        steps = args.steps if nx == 512 else max(200, args.steps // 16)
+        for name, kw in LATTICES:
+            w = evaporation(Tc, rl, rg, nx=nx, ny=ny, R=nx / 8.0, superheat=1.10, **kw)
+            bytes_lu = 160 if kw.get("thermal_q") == 9 else 128
+            s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+            s.step(args.warmup)
+            cand = [("one-step", one_step)] + ([("any", None)] if name == "D2Q5-MRT" else [])
+            for label, c in cand:
+                r = autotune.tune_solver(s, candidates=c, use_cache=False)
+                ms = _time_solver(s, steps)
+                rows.append({"grid": f"{nx}x{ny}", "lattice": name, "shapes": label,
+                             "shape": shape_text(lbm, lbm.LBM_FP32, r.shape), "bytes_per_lu": bytes_lu,
+                             "us_per_step": round(ms * 1e3, 3), "mlups": round(w.nodes / (ms * 1e-3) / 1e6, 1),
+                             "roofline_frac": round(w.nodes * bytes_lu / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+                print(f"[bench] {rows[-1]}", file=sys.stderr, flush=True)
+            s.close()
+    pulses = {}
+    for name, kw in LATTICES:
+        for rho0 in (1.0, 0.2):
+            pulses[f"{name} rho_cv={rho0 * 5:g}"] = _pulse_error(lbm, kw, rho0)
+    print(f"[bench] pulse errors {pulses}", file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "mode": "thermal-lattice ablation", "unit": "MLUPS", "n_gpus": 1, "dtype": "f32",
+           "config": {"workload": "droplet evaporation (R = nx/8, edges at 1.1 T_sat), FP32, 512x512 and 2048x2048",
+                      "steps_512": args.steps, "warmup": args.warmup},
+           "runs": rows, "gaussian_pulse": pulses}
+    print(json.dumps(out), flush=True)
+
+
 def run_fritz_mode(args):
     """Bubble departure diameter against gravity (the study of Section 4.3): one batched sweep,
     the first departure per gravity, and the least-squares slope of log D_d against log g."""
@@ -240,7 +329,7 @@ def run_fritz_mode(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "fritz"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "fritz", "lattice"], default="plain")
     ap.add_argument("--gravities", default="1e-5,1.5e-5,2e-5,3e-5,4e-5,6e-5")
     ap.add_argument("--dT-rel", type=float, default=0.19)
     ap.add_argument("--hot-width", type=float, default=8.0)
@@ -274,6 +363,9 @@ def main():
             args.nx, args.ny = 150, 300
         args.steps = args.steps or 200000
         return run_fritz_mode(args)
+    if args.mode == "lattice":
+        args.steps = args.steps or 4000
+        return run_lattice_mode(args)
     if args.steps is None:
         args.steps = 10000 if args.mode == "batch" else 20000
     if args.mode == "batch":

@@ -84,7 +84,7 @@ def _device_tag(device) -> str:
 
 def solver_key(s: Solver) -> str:
     c = s.params
-    return (f"{_device_tag(s.mem.device)}|p{s.precision}|{s.nx}x{s.ny}|walls{int(c.y_walls)}"
+    return (f"{_device_tag(s.mem.device)}|p{s.precision}|q{s.q}|{s.nx}x{s.ny}|walls{int(c.y_walls)}"
             f"|box{int(c.thermal_box)}")
 
 
@@ -94,7 +94,7 @@ def batch_key(b: Batch) -> str:
     # grids of a batch enter through their multiset; a long list is summarised by a digest
     import hashlib
     digest = hashlib.sha1(",".join(sizes).encode()).hexdigest()[:16]
-    return f"{_device_tag(s0.mem.device)}|p{s0.precision}|batch{len(sizes)}|{digest}"
+    return f"{_device_tag(s0.mem.device)}|p{s0.precision}|q{s0.q}|batch{len(sizes)}|{digest}"
 
 
 def _time(step, stream, steps, repeats):
