@@ -60,7 +60,7 @@ class _CParams(ctypes.Structure):
         ("T_box", ctypes.c_double), ("T_top", ctypes.c_double), ("T_bot", ctypes.c_double),
         ("hot_dT", ctypes.c_double), ("hot_x0", ctypes.c_double), ("hot_sigma", ctypes.c_double),
         ("theta_bot_deg", ctypes.c_double), ("theta_top_deg", ctypes.c_double),
-        ("flags", ctypes.c_uint32), ("thermal_q", ctypes.c_int32),
+        ("flags", ctypes.c_uint32), ("thermal_q", ctypes.c_int32), ("open_top", ctypes.c_int32),
     ]
 
 
@@ -103,6 +103,7 @@ def lib():
         L.orc_set_state.argtypes = [vp, dp, dp, dp]; L.orc_set_state.restype = None
         L.orc_diagnostics.argtypes = [vp, dp, dp, dp, dp]; L.orc_diagnostics.restype = None
         L.orc_rho_ave.argtypes = [vp]; L.orc_rho_ave.restype = d
+        L.orc_get_post.argtypes = [vp, dp]; L.orc_get_post.restype = None
         L.orc_steps.argtypes = [vp]; L.orc_steps.restype = ctypes.c_long
         L.orc_num_threads.argtypes = []; L.orc_num_threads.restype = ctypes.c_int
         L.orc_matrices.argtypes = [vp, dp, dp, dp, dp]; L.orc_matrices.restype = None
@@ -233,6 +234,12 @@ class Oracle:
         h = np.zeros((2, self.ny, self.nx))
         lib().orc_get_state(self._h, _dp(f), _dp(g), _dp(h))
         return f, g, h
+
+    def post_collision(self):
+        """f* of the last step, [9][ny][nx]."""
+        fs = np.zeros((9, self.ny, self.nx))
+        lib().orc_get_post(self._h, _dp(fs))
+        return fs
 
     def set_state(self, f, g, h):
         f, g, h = _c64(f), _c64(g), _c64(h)

@@ -46,6 +46,14 @@
  *         with the same weights, lambda = chat_s^2 (tau_g - 1/2) as after Eq. (53), and grad T
  *         from the non-equilibrium first moment as in Eqs. (49)-(50):
  *         chat_s^2 dT/dx = -(1/tau_g) sum_i c_ix g_i (the equilibrium part of that sum is 0).
+ *   R-OPEN The open top boundary the paper takes from Lou et al. (Section 4.2, 4.3) is not written
+ *         out.  Reading: the convective outflow condition for the populations that enter the top
+ *         row from outside (c_y = -1),
+ *           f_i(x, N, t+1) = [f_i(x, N, t) + U f_i(x, N-1, t+1)] / (1 + U),
+ *         with U = the local normal velocity j_y / rho of the top node at time t, clipped to
+ *         [0, 1]; populations leaving through the top are dropped; the ghost row above carries the
+ *         pseudopotential and the velocity of the top row (zero gradient); the temperature keeps
+ *         the Dirichlet value T_top (R-DIR).  The bottom stays a wall (R-WALL).
  */
 #include <math.h>
 #ifdef _OPENMP
@@ -73,6 +81,7 @@ typedef struct {
   double theta_bot_deg, theta_top_deg;
   uint32_t flags;
   int32_t thermal_q;            /* thermal lattice: 5 (D2Q5, Eqs. 26 and 39; 0 means 5) or 9 (R-Q9) */
+  int32_t open_top;             /* with y_walls: the top is the open boundary of R-OPEN */
 } orc_params;
 
 /* ---------------------------------------------------------------- lattices (Eqs. 2, 3, 26) */
@@ -314,6 +323,7 @@ void orc_free(orc_state* s);
 
 orc_state* orc_new(const orc_params* prm) {
   if (prm->nx < 3 || prm->ny < 3) return NULL;
+  if (prm->open_top && !prm->y_walls) return NULL;
   if (prm->thermal_q != 0 && prm->thermal_q != 5 && prm->thermal_q != 9) return NULL;
   orc_state* s = (orc_state*)calloc(1, sizeof(orc_state));
   s->p = *prm;
@@ -397,8 +407,9 @@ static void u_at(const orc_state* s, int x, int y, double* ux, double* uy) {
   if (s->p.y_walls) {
     if (y < 0 || y >= s->ny) {
       int yf = y < 0 ? 0 : s->ny - 1;
-      *ux = -s->ux[idx(s, x, yf)];
-      *uy = -s->uy[idx(s, x, yf)];
+      double sign = (y >= s->ny && s->p.open_top) ? 1.0 : -1.0; /* R-OPEN above the top, R-DIVU at walls */
+      *ux = sign * s->ux[idx(s, x, yf)];
+      *uy = sign * s->uy[idx(s, x, yf)];
       return;
     }
   } else {
@@ -451,6 +462,10 @@ static int compute_macro(orc_state* s) {
       s->ghost_rho_t[x] = rt;
       s->ghost_psi_b[x] = orc_psi(p, rb, wall_T(s, -1, x));
       s->ghost_psi_t[x] = orc_psi(p, rt, wall_T(s, +1, x));
+      if (p->open_top) { /* R-OPEN: zero gradient above the open top */
+        s->ghost_rho_t[x] = s->rho[idx(s, x, ny - 1)];
+        s->ghost_psi_t[x] = s->psi[idx(s, x, ny - 1)];
+      }
       if (s->ghost_psi_b[x] < 0 || s->ghost_psi_t[x] < 0) return 2;
     }
   }
@@ -612,6 +627,7 @@ static int step_once(orc_state* s) {
         size_t k = idx(s, x, y);
         for (int i = 0; i < 9; ++i) {
           int xd = x + CX[i], yd = y + CY[i];
+          if (p->y_walls && yd >= ny && p->open_top) continue; /* leaves through the open top */
           if (p->y_walls && (yd < 0 || yd >= ny)) {
             s->fn[opposite9(i) * n + k] = s->fs[i * n + k];
           } else {
@@ -619,6 +635,21 @@ static int step_once(orc_state* s) {
           }
         }
       }
+    if (p->y_walls && p->open_top) {
+      /* R-OPEN: the populations entering the top row from outside */
+      for (int x = 0; x < nx; ++x) {
+        size_t k = idx(s, x, ny - 1), kb = idx(s, x, ny - 2);
+        double r = 0.0, jy = 0.0;
+        for (int i = 0; i < 9; ++i) {
+          r += s->f[i * n + k];
+          jy += CY[i] * s->f[i * n + k];
+        }
+        double U = jy / r;
+        U = U < 0.0 ? 0.0 : (U > 1.0 ? 1.0 : U);
+        for (int i = 0; i < 9; ++i)
+          if (CY[i] == -1) s->fn[i * n + k] = (s->f[i * n + k] + U * s->fn[i * n + kb]) / (1.0 + U);
+      }
+    }
   }
 
   /* Streaming of g with the modified collision term (Eq. 39, reading R-BLEND), the
@@ -728,6 +759,9 @@ void orc_diagnostics(const orc_state* s, double* mass, double* energy, double* s
 }
 
 double orc_rho_ave(const orc_state* s) { return s->rho_ave; }
+
+/* post-collision populations f* of the last step (for bookkeeping checks in the tests) */
+void orc_get_post(const orc_state* s, double* fs) { memcpy(fs, s->fs, 9 * s->n * sizeof(double)); }
 
 /* threads the grid loops run on */
 int orc_num_threads(void) {

@@ -68,6 +68,8 @@ class Params:
     flags: int = 0
     # thermal lattice: 5 (D2Q5, the paper's model) or 9 (D2Q9 with the BGK collision of Eq. 21)
     thermal_q: int = 5
+    # with y_walls: the top is an open (outflow) boundary instead of a wall
+    open_top: int = 0
 
     def replace(self, **kw) -> "Params":
         return dataclasses.replace(self, **kw)
@@ -137,6 +139,24 @@ def evaporation(Tc, rho_l, rho_g, nx=512, ny=512, R=64.0, T_rel=0.86, superheat=
         T = np.where(rho > 0.5 * (rho_l + rho_g), T_sat, T_box)
     return Workload("evaporation", p, rho, _zeros(ny, nx), _zeros(ny, nx), T, steps,
                     {"R": R, "T_sat": T_sat})
+
+
+def heated_droplet(Tc, rho_l, rho_g, nx=200, ny=100, R=35.0, T_rel=0.86, T_h_rel=0.95, T_s_rel=None,
+                   lambda_=0.08, theta=90.0, steps=20000, **kw) -> Workload:
+    """Droplet on a heated wall under an open top (Section 4.2): a half disk of radius R centred on
+    the bottom wall at x = nx/2 (Eq. 56, width 5), contact angle theta, wall at T_h, open top
+    held at T_s (T_sat unless given), periodic in x, initial T = T_sat everywhere.  The paper
+    gives neither T_h nor T_s: T_h = 0.95 Tc (about 10 % above T_sat) and T_s = T_sat are proposed
+    here.  Its 'thermal diffusivity 0.08' is taken as the conductivity lambda.  The paper first
+    runs the droplet without evaporation until its contact angle settles: T_h_rel = T_rel gives
+    that unheated stage."""
+    T_sat = T_rel * Tc
+    T_s = (T_s_rel * Tc) if T_s_rel is not None else T_sat
+    p = Params(nx=nx, ny=ny, y_walls=1, open_top=1, T_bot=T_h_rel * Tc, T_top=T_s, theta_bot_deg=theta,
+               theta_top_deg=90.0, lambda_=lambda_, **kw)
+    rho = tanh_disk(nx, ny, nx / 2.0, 0.0, R, rho_l, rho_g)
+    return Workload("heated_droplet", p, rho, _zeros(ny, nx), _zeros(ny, nx), np.full((ny, nx), T_sat), steps,
+                    {"R": R, "T_sat": T_sat, "T_h": T_h_rel * Tc, "T_s": T_s})
 
 
 def boiling(Tc, rho_l, rho_g, nx=1024, ny=2048, T_rel=0.86, dT_rel=0.2, gravity=2e-5, hot_width=32.0,
