@@ -86,7 +86,13 @@ typedef struct {
   double T_box, T_top, T_bot, hot_dT, hot_x0, hot_sigma;
   double theta_bot_deg, theta_top_deg; /* contact angles of the geometric wetting rule (Eq. 54) */
   uint32_t flags;        /* LBM_FREEZE_FLOW | LBM_NO_S (tests only) | LBM_BGK */
-  uint32_t reserved1;
+  /* with y_walls = 1: the top is an open boundary (the outflow condition the paper uses for
+     its open-top problems, Sections 4.2-4.3, read as the convective outflow condition of the
+     populations entering the top row: f_i(x,N,t+1) = [f_i(x,N,t) + U f_i(x,N-1,t+1)]/(1+U),
+     U = j_y/rho of the top node at time t clipped to [0,1]; zero-gradient pseudopotential and
+     velocity above it; the temperature stays T_top).  Runs on the one-step tile shapes of a
+     single context (not in a batch); mass leaves and enters through the top. */
+  int32_t open_top;
 } lbm_params;
 
 /* Fill *p with the paper's parameter values (Sections 2 and 4) for an nx x ny FP32 grid. */
@@ -95,7 +101,8 @@ void lbm_params_default(lbm_params* p, int32_t nx, int32_t ny);
 /* Check a parameter set without touching the device.  LBM_E_INVAL if nx or ny < 3, one
    population plane (nx * ny values) exceeds 2^32 - 1 bytes (about 1.07e9 nodes in FP32,
    5.4e8 in FP64), a relaxation rate is outside (0, 2), wdot outside (0, 1), c_v <= 0, nu <= 0,
-   lambda <= 0, thermal_q is not 0, 5 or 9, or flags holds an unknown bit. */
+   lambda <= 0, thermal_q is not 0, 5 or 9, flags holds an unknown bit, or open_top is set
+   without y_walls. */
 lbm_status lbm_validate(const lbm_params* p);
 
 /* Exact device bytes a context needs (populations f and g and the temperature history, each
@@ -129,9 +136,10 @@ int64_t lbm_steps_done(const lbm_ctx* h);
    grouped into workgroups and launches: every shape gives bit-identical results.
    lbm_shape_info: LBM_E_INVAL for an unknown precision or k; NULL outputs are skipped.
    A two-step shape keeps the first step's result for the tile and its halo in LDS, which needs
-   a grid larger than that halo region and the D2Q5 thermal lattice (the D2Q9 populations do
-   not fit in LDS twice): lbm_shape_fits tells whether shape k can run the simulation of *p (1)
-   or not (0, also for invalid parameters). */
+   a grid larger than that halo region, the D2Q5 thermal lattice (the D2Q9 populations do not
+   fit in LDS twice) and no open top (its boundary pass runs between steps): lbm_shape_fits
+   tells whether shape k can run the simulation of *p (1) or not (0, also for invalid
+   parameters). */
 int lbm_shape_count(int32_t precision);
 lbm_status lbm_shape_info(int32_t precision, int k, int* tile_x, int* tile_y, int* waves, int* steps_per_launch);
 int lbm_shape_fits(const lbm_params* p, int k);
@@ -197,8 +205,8 @@ const char* lbm_last_error(const lbm_ctx* h);
  */
 size_t lbm_batch_footprint_bytes(int n);
 
-/* Build a batch over ctxs[0..n) (all initialised, same precision and thermal lattice),
-   enqueueing on hip_stream.
+/* Build a batch over ctxs[0..n) (all initialised, same precision and thermal lattice, none with
+   an open top), enqueueing on hip_stream.
    The batch's work is ordered after everything already enqueued on the contexts' own streams
    (their lbm_init, for instance), so a context may be initialised on a stream of its own.
    While the batch exists its members are advanced only through it.  Once lbm_batch_sync has

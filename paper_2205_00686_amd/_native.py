@@ -45,7 +45,7 @@ class LbmParams(ctypes.Structure):
         ("T_box", ctypes.c_double), ("T_top", ctypes.c_double), ("T_bot", ctypes.c_double),
         ("hot_dT", ctypes.c_double), ("hot_x0", ctypes.c_double), ("hot_sigma", ctypes.c_double),
         ("theta_bot_deg", ctypes.c_double), ("theta_top_deg", ctypes.c_double),
-        ("flags", ctypes.c_uint32), ("reserved1", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32), ("open_top", ctypes.c_int32),
     ]
 
 

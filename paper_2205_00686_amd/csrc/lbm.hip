@@ -60,13 +60,16 @@ int tiles_of(int nx, int ny, int ty) { return ((nx + TX - 1) / TX) * ((ny + ty -
 // Velocities of the thermal lattice of a parameter set (5 or 9).
 int qg_of(const lbm_params* p) { return p->thermal_q == 9 ? 9 : 5; }
 
+// Whether a simulation can use the two-step shapes: their LDS holds the D2Q5 thermal
+// populations, and an open top needs its boundary pass between steps.
+bool two_step_ok(const lbm_params* p) { return qg_of(p) == 5 && !(p->y_walls && p->open_top); }
+
 // A two-step shape keeps a consistent image of its wide halo region in LDS only if no grid node
-// appears in it twice: the grid must be larger than the region in both directions.  Its LDS
-// holds the D2Q5 thermal populations; D2Q9 runs on the one-step shapes.
-bool shape_fits(int precision, int qg, int k, int nx, int ny) {
+// appears in it twice: the grid must be larger than the region in both directions.
+bool shape_fits(int precision, bool two_ok, int k, int nx, int ny) {
   const ShapeDef& d = shape_def(precision, k);
   if (d.depth == 1) return true;
-  if (qg != 5) return false;
+  if (!two_ok) return false;
   return nx >= TX + 2 * (HXW + 4) + 1 && ny >= d.ty + 2 * (HYW + 3) + 1;
 }
 
@@ -76,9 +79,9 @@ bool shape_fits(int precision, int qg, int k, int nx, int ny) {
 // unit (a single wave of workgroups, whose latency matters), the 2-rows-per-thread shape beyond.
 // The autotuner replaces this guess by a measurement.
 constexpr int F32_TWO_STEP_DEFAULT = 6;
-int default_shape(int precision, int qg, int nx, int ny) {
+int default_shape(int precision, bool two_ok, int nx, int ny) {
   if (precision == LBM_FP64) return 0;
-  if (shape_fits(precision, qg, F32_TWO_STEP_DEFAULT, nx, ny)) return F32_TWO_STEP_DEFAULT;
+  if (shape_fits(precision, two_ok, F32_TWO_STEP_DEFAULT, nx, ny)) return F32_TWO_STEP_DEFAULT;
   return tiles_of(nx, ny, F32_SHAPES[0].ty) >= 1024 ? 1 : 0;
 }
 
@@ -158,12 +161,12 @@ static hipError_t wait_for_members(hipStream_t bs, const std::vector<lbm_ctx*>& 
 }
 
 // Default shape of a batch: the two-step shape if every member fits it, else by total size.
-static int batch_default_shape(int precision, int qg, const std::vector<lbm_ctx*>& ctx) {
+static int batch_default_shape(int precision, const std::vector<lbm_ctx*>& ctx) {
   if (precision == LBM_FP64) return 0;
   bool fit = true;
   long long tiles = 0;
   for (const lbm_ctx* h : ctx) {
-    fit = fit && shape_fits(precision, qg, F32_TWO_STEP_DEFAULT, h->prm.nx, h->prm.ny);
+    fit = fit && shape_fits(precision, two_step_ok(&h->prm), F32_TWO_STEP_DEFAULT, h->prm.nx, h->prm.ny);
     tiles += tiles_of(h->prm.nx, h->prm.ny, F32_SHAPES[0].ty);
   }
   if (fit) return F32_TWO_STEP_DEFAULT;
@@ -231,6 +234,7 @@ static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref)
   d.tan_top = (real)std::tan(M_PI / 2.0 - p->theta_top_deg * M_PI / 180.0);
   d.y_walls = p->y_walls ? 1 : 0;
   d.thermal_box = p->thermal_box ? 1 : 0;
+  d.open_top = (p->y_walls && p->open_top) ? 1 : 0;
   d.flags = p->flags;
   d.T_ref = (real)T_ref;
   d.om_e = (real)(1.0 - 0.5 * p->s_e);
@@ -352,6 +356,7 @@ lbm_status lbm_validate(const lbm_params* p) {
   }
   if (p->thermal_box && !finite_pos(p->T_box)) return LBM_E_INVAL;
   if (p->thermal_q != 0 && p->thermal_q != 5 && p->thermal_q != 9) return LBM_E_INVAL;
+  if (p->open_top && !p->y_walls) return LBM_E_INVAL;
   if ((p->flags & ~(uint32_t)(LBM_FREEZE_FLOW | LBM_NO_S | LBM_BGK)) != 0) return LBM_E_INVAL;
   return LBM_OK;
 }
@@ -398,7 +403,7 @@ lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hi
   h->ThA = q; q += align_up(2 * h->N * h->rsz);
   h->ThB = q;
   h->shape_req = -1;
-  h->shape = default_shape(p->precision, qg_of(p), p->nx, p->ny);
+  h->shape = default_shape(p->precision, two_step_ok(p), p->nx, p->ny);
   h->ntiles = tiles_of(p->nx, p->ny, shape_def(p->precision, h->shape).ty);
   *out = h;
   return LBM_OK;
@@ -503,11 +508,21 @@ static void launch_step(int precision, int qg, int shape, int grid, hipStream_t 
 #undef LBM_LAUNCH_F64
 }
 
-// n launches of the step kernel, then the clock advance by the steps they span
+// n launches of the step kernel (each followed by the open-top boundary pass where the
+// simulation has one), then the clock advance by the steps they span
 static lbm_status launch_steps(lbm_ctx* h, int n) {
   const int d = shape_def(h->prm.precision, h->shape).depth;
-  for (int k = 0; k < n; ++k)
+  const bool open = h->prm.y_walls && h->prm.open_top;
+  const int ob = (h->prm.nx + 255) / 256;
+  for (int k = 0; k < n; ++k) {
     launch_step(h->prm.precision, qg_of(&h->prm), h->shape, h->ntiles, h->stream, h->d_desc, 1, h->d_clock, k);
+    if (open) {
+      if (h->prm.precision == LBM_FP64)
+        open_top_kernel<double><<<ob, 256, 0, h->stream>>>((const InstDesc<double>*)h->d_desc, h->d_clock, k);
+      else
+        open_top_kernel<float><<<ob, 256, 0, h->stream>>>((const InstDesc<float>*)h->d_desc, h->d_clock, k);
+    }
+  }
   clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n * d);
   HIP_OR_FAIL(h, hipGetLastError());
   return LBM_OK;
@@ -588,15 +603,15 @@ lbm_status lbm_shape_info(int precision, int k, int* tile_x, int* tile_y, int* w
 
 int lbm_shape_fits(const lbm_params* p, int k) {
   if (!p || lbm_validate(p) != LBM_OK || k < 0 || k >= shape_count(p->precision)) return 0;
-  return shape_fits(p->precision, qg_of(p), k, p->nx, p->ny) ? 1 : 0;
+  return shape_fits(p->precision, two_step_ok(p), k, p->nx, p->ny) ? 1 : 0;
 }
 
 lbm_status lbm_set_shape(lbm_ctx* h, int k) {
   if (!h || k < -1 || k >= shape_count(h->prm.precision)) return LBM_E_INVAL;
-  if (k >= 0 && !shape_fits(h->prm.precision, qg_of(&h->prm), k, h->prm.nx, h->prm.ny))
+  if (k >= 0 && !shape_fits(h->prm.precision, two_step_ok(&h->prm), k, h->prm.nx, h->prm.ny))
     return fail(h, LBM_E_INVAL, "two-step tile shape on a grid smaller than its halo region");
   h->shape_req = k;
-  const int s = k < 0 ? default_shape(h->prm.precision, qg_of(&h->prm), h->prm.nx, h->prm.ny) : k;
+  const int s = k < 0 ? default_shape(h->prm.precision, two_step_ok(&h->prm), h->prm.nx, h->prm.ny) : k;
   if (s == h->shape) return LBM_OK;
   h->shape = s;
   h->ntiles = tiles_of(h->prm.nx, h->prm.ny, shape_def(h->prm.precision, s).ty);
@@ -889,7 +904,8 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   const int prec = ctxs[0] ? ctxs[0]->prm.precision : -1;
   const int qg = ctxs[0] ? qg_of(&ctxs[0]->prm) : 0;
   for (int i = 0; i < n; ++i)
-    if (!ctxs[i] || !ctxs[i]->initialised || ctxs[i]->prm.precision != prec || qg_of(&ctxs[i]->prm) != qg)
+    if (!ctxs[i] || !ctxs[i]->initialised || ctxs[i]->prm.precision != prec || qg_of(&ctxs[i]->prm) != qg ||
+        (ctxs[i]->prm.y_walls && ctxs[i]->prm.open_top))
       return LBM_E_INVAL;
   lbm_batch* b = new (std::nothrow) lbm_batch();
   if (!b) return LBM_E_NOMEM;
@@ -905,7 +921,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
     delete b;
     return LBM_E_DEVICE;
   }
-  b->shape = batch_default_shape(prec, qg, b->ctx);
+  b->shape = batch_default_shape(prec, b->ctx);
   b->base = (char*)dev_mem;
   b->bytes = bytes;
   b->d_clock = (long long*)b->base;
@@ -930,8 +946,8 @@ lbm_status lbm_batch_set_shape(lbm_batch* b, int k) {
   if (!b || k < -1 || k >= shape_count(b->precision)) return LBM_E_INVAL;
   if (k >= 0)
     for (lbm_ctx* h : b->ctx)
-      if (!shape_fits(b->precision, b->qg, k, h->prm.nx, h->prm.ny)) return LBM_E_INVAL;
-  if (k < 0) k = batch_default_shape(b->precision, b->qg, b->ctx);
+      if (!shape_fits(b->precision, two_step_ok(&h->prm), k, h->prm.nx, h->prm.ny)) return LBM_E_INVAL;
+  if (k < 0) k = batch_default_shape(b->precision, b->ctx);
   b->shape = k;  // tile counts change; the graph is recaptured at the next upload
   return LBM_OK;
 }

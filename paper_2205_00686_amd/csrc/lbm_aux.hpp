@@ -56,7 +56,10 @@ __device__ real psi_any(const DevParams<real>& p, const real* __restrict__ f, co
   x = wrapi(x, nx, true);
   if (!p.y_walls) y = wrapi(y, ny, true);
   real rho, T;
-  if (y == -1 || y == ny) {
+  if (y == ny && p.open_top) {
+    rho_T(f, g, N, (ny - 1) * nx + x, p.qg, rho, T);  // above an open top: zero gradient
+    T = p.T_ref + T;
+  } else if (y == -1 || y == ny) {
     const int top = y == ny;
     const int y1 = top ? ny - 1 : 0, y2 = top ? ny - 2 : 1;
     real r2, r1p, r1m, tt;

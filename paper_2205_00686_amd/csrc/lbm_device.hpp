@@ -76,6 +76,7 @@ struct DevParams {
   int y_walls, thermal_box;
   unsigned flags;
   int qg;                           // velocities of the thermal lattice: 5 or 9
+  int open_top;                     // with walls: the top is open (outflow boundary)
 };
 
 // One simulation as seen by the step kernel.  The step kernel serves single runs (a one-entry

@@ -243,15 +243,16 @@ __device__ __forceinline__ void node_force_velocity(LDS& L, int ex, int ey, cons
 }
 
 // div u = 3 sum_i w_i c_i . u(x + c_i); a ghost row carries -u of the fluid row next to it
-// (gs_: the node is on the bottom fluid row of a walled domain, gn_: on the top one)
+// (gs_: the node is on the bottom fluid row of a walled domain, gn_: on the top one), or +u
+// above an open top (sn = +1 instead of -1: zero gradient)
 template <typename real, class LDS>
-__device__ __forceinline__ real node_divu(const LDS& L, int ex, int ey, bool gs_, bool gn_) {
+__device__ __forceinline__ real node_divu(const LDS& L, int ex, int ey, bool gs_, bool gn_, real sn = real(-1)) {
   const real uy = L.uy[ey][ex];
   const real uxE = L.ux[ey][ex + 1], uxW = L.ux[ey][ex - 1];
-  const real uyN = gn_ ? -uy : L.uy[ey + 1][ex];
+  const real uyN = gn_ ? sn * uy : L.uy[ey + 1][ex];
   const real uyS = gs_ ? -uy : L.uy[ey - 1][ex];
-  const real uxNE = gn_ ? -uxE : L.ux[ey + 1][ex + 1], uyNE = gn_ ? -L.uy[ey][ex + 1] : L.uy[ey + 1][ex + 1];
-  const real uxNW = gn_ ? -uxW : L.ux[ey + 1][ex - 1], uyNW = gn_ ? -L.uy[ey][ex - 1] : L.uy[ey + 1][ex - 1];
+  const real uxNE = gn_ ? sn * uxE : L.ux[ey + 1][ex + 1], uyNE = gn_ ? sn * L.uy[ey][ex + 1] : L.uy[ey + 1][ex + 1];
+  const real uxNW = gn_ ? sn * uxW : L.ux[ey + 1][ex - 1], uyNW = gn_ ? sn * L.uy[ey][ex - 1] : L.uy[ey + 1][ex - 1];
   const real uxSW = gs_ ? -uxW : L.ux[ey - 1][ex - 1], uySW = gs_ ? -L.uy[ey][ex - 1] : L.uy[ey - 1][ex - 1];
   const real uxSE = gs_ ? -uxE : L.ux[ey - 1][ex + 1], uySE = gs_ ? -L.uy[ey][ex + 1] : L.uy[ey - 1][ex + 1];
   return real(1.0 / 3.0) * ((uxE - uxW) + (uyN - uyS)) +
@@ -374,7 +375,9 @@ __device__ __forceinline__ bool ghost_rows(LDS& L, const DevParams<real>& p, int
     const int top = c >= W;
     const int ex = c - top * W;
     const int ey = top ? eyt : eyb;
-    if ((top ? hast : hasb) && ex >= 1 && ex <= W - 2) {
+    if (top && hast && p.open_top) {
+      L.psi[ey][ex] = L.psi[ey - 1][ex];  // above an open top: zero gradient
+    } else if ((top ? hast : hasb) && ex >= 1 && ex <= W - 2) {
       const int d = top ? -1 : 1;  // towards the fluid
       const real tanv = top ? p.tan_top : p.tan_bot;
       const real rg = L.rho[ey + 2 * d][ex] + tanv * fabs(L.rho[ey + d][ex + 1] - L.rho[ey + d][ex - 1]);
@@ -546,7 +549,8 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
     const real rho = L.rho[ey][ex];
     const real ux = L.ux[ey][ex], uy = L.uy[ey][ex];
     const unsigned o = ob[r];
-    const real divu = node_divu<real>(L, ex, ey, walls && yg == 0, walls && yg == ny - 1);
+    const real divu = node_divu<real>(L, ex, ey, walls && yg == 0, walls && yg == ny - 1,
+                                      walls && p.open_top ? real(1) : real(-1));
     real fs_[9], gs_[QG], Tr;
     node_collide<real, QG>(p, freeze, f[r], g[r], rho, ux, uy, Fx[r], Fy[r], S2[r], dpdT[r], divu, T1[r], T2[r],
                            fs_, gs_, Tr);
@@ -585,9 +589,13 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
       { auto b = dst(fdp(1), 1, 0, off); stb(b, off, fs_[1]); }
       { auto b = dst(fdp(3), -1, 0, off); stb(b, off, fs_[3]); }
       if (wall_n) {
-        stb(fdp(4), o, fs_[2]);
-        stb(fdp(7), o, fs_[5]);
-        stb(fdp(8), o, fs_[6]);
+        // under an open top the upward populations leave and the entering ones come from the
+        // boundary pass after the step
+        if (!p.open_top) {
+          stb(fdp(4), o, fs_[2]);
+          stb(fdp(7), o, fs_[5]);
+          stb(fdp(8), o, fs_[6]);
+        }
       } else {
         { auto b = dst(fdp(2), 0, 1, off); stb(b, off, fs_[2]); }
         { auto b = dst(fdp(5), 1, 1, off); stb(b, off, fs_[5]); }
@@ -948,6 +956,36 @@ __global__ void clock_advance_kernel(long long* clock, long long n) {
 // Step window of a single run, set on its stream before the call's launches: steps
 // [t_base, t_end) of the clock, starting from the B buffers if b_base is 1.  (A kernel takes its
 // arguments at enqueue, so no host buffer has to outlive the call.)
+// Open top boundary, after the step of launch k of a one-step shape: the populations that enter
+// the top row N from outside (c_y = -1) follow the convective outflow condition
+//   f_i(x, N, t+1) = [f_i(x, N, t) + U f_i(x, N-1, t+1)] / (1 + U),
+// U = j_y / rho of the top node at time t clipped to [0, 1].  f(t) is in the step's source
+// buffers, f(t+1) of row N-1 in its destination buffers.  One thread per column of the single
+// simulation in table entry 0.
+template <typename real>
+__global__ void open_top_kernel(const InstDesc<real>* __restrict__ table, const long long* __restrict__ clock, int k) {
+  const InstDesc<real>& D = table[0];
+  const long long t = *clock + k;
+  if (t < D.t_base || t >= D.t_end) return;
+  const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (x >= D.nx) return;
+  const bool odd = ((D.b_base + (t - D.t_base)) & 1) != 0;
+  const real* __restrict__ fs = odd ? D.fB : D.fA;
+  real* __restrict__ fd = odd ? D.fA : D.fB;
+  const size_t N = (size_t)D.nx * (size_t)D.ny;
+  const size_t top = (size_t)(D.ny - 1) * (size_t)D.nx + (size_t)x, below = top - (size_t)D.nx;
+  real f[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = fs[i * N + top];
+  const real rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+  const real jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+  real U = jy / rho;
+  U = U < real(0) ? real(0) : (U > real(1) ? real(1) : U);
+  fd[4 * N + top] = (f[4] + U * fd[4 * N + below]) / (real(1) + U);
+  fd[7 * N + top] = (f[7] + U * fd[7 * N + below]) / (real(1) + U);
+  fd[8 * N + top] = (f[8] + U * fd[8 * N + below]) / (real(1) + U);
+}
+
 template <typename real>
 __global__ void set_window_kernel(InstDesc<real>* d, long long t_base, int b_base, long long t_end) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {

@@ -65,6 +65,12 @@ def test_validate_and_footprint(L):
     L.lbm_params_default(ctypes.byref(q), 64, 64)
     q.y_walls = 1  # walls without wall temperatures
     assert L.lbm_validate(ctypes.byref(q)) == -1
+    q.T_bot = q.T_top = 0.09
+    assert L.lbm_validate(ctypes.byref(q)) == 0
+    q.open_top = 1
+    assert L.lbm_validate(ctypes.byref(q)) == 0
+    q.y_walls = 0  # an open top needs the bottom wall
+    assert L.lbm_validate(ctypes.byref(q)) == -1
 
 
 def test_create_rejects_small_or_misaligned_buffers(L):
@@ -164,6 +170,10 @@ def test_two_step_shapes_need_a_grid_larger_than_their_halo(L):
     for k in two:
         assert not shape_fits(Params(nx=512, ny=512, thermal_q=9), k)
     assert all(shape_fits(Params(nx=512, ny=512, thermal_q=9), k) for k, s in enumerate(shapes(0)) if s[3] == 1)
+    # an open top runs its boundary pass between steps: one-step shapes only
+    op = Params(nx=512, ny=512, y_walls=1, open_top=1, T_bot=0.09, T_top=0.09)
+    assert not any(shape_fits(op, k) for k in two)
+    assert all(shape_fits(op, k) for k, s in enumerate(shapes(0)) if s[3] == 1)
     p = _native.LbmParams()
     L.lbm_params_default(ctypes.byref(p), 2, 64)  # invalid parameters
     assert L.lbm_shape_fits(ctypes.byref(p), 0) == 0
