@@ -15,6 +15,7 @@ the library's stream), and the FP64 CPU oracle timed on a bounded sample of the 
   python bench.py --mode serve [--requests 256 --rate 20]        continuous batching vs FIFO
   python bench.py --mode fritz [--gravities 1e-5,...,6e-5]       bubble departure diameter vs gravity
   python bench.py --mode lattice                                 thermal lattice: D2Q5 MRT / BGK vs D2Q9
+  python bench.py --mode heated                                  droplet evaporation on a heated surface
 """
 from __future__ import annotations
 
@@ -303,10 +304,14 @@ def run_fritz_mode(args):
     Tc = lbm.critical_temperature(base)
     rl, rg, ps = lbm.coexistence(base, 0.86 * Tc)
     gs = [float(x) for x in args.gravities.split(",")]
-    fill = head_limited_fill(rl, rg, ps, max(gs), args.ny)
+    if args.open_top:
+        # the paper's setting: the enclosure full of saturated liquid under an open top
+        fill, extra, box = 1.05, {"open_top": 1}, "open top, full of liquid"
+    else:
+        fill, extra, box = head_limited_fill(rl, rg, ps, max(gs), args.ny), {}, "closed box"
     ws = [boiling(Tc, rl, rg, nx=args.nx, ny=args.ny, gravity=g, dT_rel=args.dT_rel, hot_width=args.hot_width,
-                  fill=fill, noise=0.0, seed=1) for g in gs]
-    print(f"[bench] fritz sweep: {len(gs)} gravities on {args.nx}x{args.ny}, fill {fill:.3f}, "
+                  fill=fill, noise=0.0, seed=1, **extra) for g in gs]
+    print(f"[bench] fritz sweep: {len(gs)} gravities on {args.nx}x{args.ny}, {box}, fill {fill:.3f}, "
           f"hot spot dT {args.dT_rel} Tc (width {args.hot_width})", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     res = fritz.sweep(ws, rl, rg, max_steps=args.steps, check_every=args.check_every,
@@ -317,7 +322,7 @@ def run_fritz_mode(args):
     fit = fritz.fit_power([r.gravity for r in ok], [r.diameter for r in ok]) if len(ok) >= 2 else (None, None, None)
     out = {"metric": "bubble departure diameter vs gravity (Fritz: D_d ~ g^-0.5)", "mode": "fritz",
            "config": {"workload": f"nucleate boiling {args.nx}x{args.ny}, T_sat 0.86 Tc, hot spot dT {args.dT_rel} Tc "
-                                  f"(Gaussian width {args.hot_width}), contact angle 75, lambda 2/3, closed box, "
+                                  f"(Gaussian width {args.hot_width}), contact angle 75, lambda 2/3, {box}, "
                                   f"fill {fill:.3f}", "precision": "fp32", "max_steps": args.steps,
                       "check_every": args.check_every},
            "departures": [{"g": r.gravity, "step": r.step, "area": r.area, "D": round(r.diameter, 3),
@@ -327,12 +332,80 @@ def run_fritz_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def _liquid(rho, rho_mid):
+    """Liquid mass (sum of rho over nodes above the mid density), base half-width on the first
+    fluid row and height of the liquid region on the wall, in lattice units."""
+    import numpy as np
+    liq = rho > rho_mid
+    mass = float(rho[liq].sum())
+    cols = np.nonzero(liq[0])[0]
+    a = 0.5 * len(cols)
+    h = float(liq.any(axis=1).nonzero()[0].max() + 1) if liq.any() else 0.0
+    return mass, a, h
+
+
+def run_heated_mode(args):
+    """Droplet evaporation on a heated surface (Section 4.2): the heated_droplet workload (200 x 100,
+    half disk of R = 35 on the wall, contact angle 90, open top at T_sat, lambda = 0.08).  Stage 1
+    runs without heating (wall at T_sat) until the shape settles; its state is then loaded into a
+    context whose wall is at T_h, and the liquid mass is followed until a fraction of it is left.
+    Contact angle of the settled droplet from its base half-width a and height h (circular cap):
+    cos(theta) = 1 - h / R with R = (a^2 + h^2) / (2 h)."""
+    import math
+
+    import paper_2205_00686_amd as lbm
+    from workloads import Params, heated_droplet
+
+    base = Params()
+    Tc = lbm.critical_temperature(base)
+    rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
+    mid = 0.5 * (rl + rg)
+    cold = heated_droplet(Tc, rl, rg, T_h_rel=0.86)
+    s = lbm.Solver(cold.params).init(cold.rho, cold.ux, cold.uy, cold.T)
+    t0 = time.perf_counter()
+    s.step(args.pre_steps)
+    m_pre, a, h = _liquid(s.fields()[0], mid)
+    R = (a * a + h * h) / (2 * h)
+    theta = math.degrees(math.acos(max(-1.0, min(1.0, 1 - h / R))))
+    raw = s.save_state()
+    s.close()
+    hot = heated_droplet(Tc, rl, rg, T_h_rel=args.T_h)
+    s = lbm.Solver(hot.params).init(cold.rho, cold.ux, cold.uy, cold.T)
+    s.load_state(raw)
+    curve = [(0, 1.0)]
+    m0 = m_pre
+    done = 0
+    while done < args.steps:
+        s.step(args.check_every)
+        done += args.check_every
+        m = _liquid(s.fields()[0], mid)[0]
+        curve.append((done, round(m / m0, 5)))
+        if m / m0 < args.stop_fraction:
+            break
+    wall = time.perf_counter() - t0
+    s.close()
+    half = next((t for t, f in curve if f <= 0.5), None)
+    print(f"[bench] heated droplet: contact angle {theta:.1f} after {args.pre_steps} unheated steps; "
+          f"half the liquid gone at step {half}", file=sys.stderr, flush=True)
+    out = {"metric": "normalised droplet mass against time, droplet on a heated surface", "mode": "heated",
+           "config": {"workload": "heated_droplet 200x100, R 35 on the wall, contact angle 90, open top at T_sat, "
+                                  f"wall at {args.T_h} Tc after {args.pre_steps} unheated steps, lambda 0.08, FP32",
+                      "check_every": args.check_every},
+           "contact_angle_deg": round(theta, 1), "base_half_width": a, "height": h,
+           "half_mass_step": half, "curve": curve[:: max(1, len(curve) // 40)], "wall_s": round(wall, 2)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "fritz", "lattice"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "fritz", "lattice", "heated"], default="plain")
     ap.add_argument("--gravities", default="1e-5,1.5e-5,2e-5,3e-5,4e-5,6e-5")
     ap.add_argument("--dT-rel", type=float, default=0.19)
     ap.add_argument("--hot-width", type=float, default=8.0)
+    ap.add_argument("--open-top", action="store_true", help="fritz: the paper's open-top pool full of liquid")
+    ap.add_argument("--T-h", type=float, default=0.95, help="heated: wall temperature / Tc")
+    ap.add_argument("--pre-steps", type=int, default=20000, help="heated: unheated steps before the wall is heated")
+    ap.add_argument("--stop-fraction", type=float, default=0.1, help="heated: stop when this much liquid is left")
     ap.add_argument("--check-every", type=int, default=250)
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--requests", type=int, default=256)
@@ -363,6 +436,11 @@ def main():
             args.nx, args.ny = 150, 300
         args.steps = args.steps or 200000
         return run_fritz_mode(args)
+    if args.mode == "heated":
+        args.steps = args.steps or 400000
+        if args.check_every == 250:
+            args.check_every = 1000
+        return run_heated_mode(args)
     if args.mode == "lattice":
         args.steps = args.steps or 4000
         return run_lattice_mode(args)

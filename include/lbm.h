@@ -90,8 +90,8 @@ typedef struct {
      its open-top problems, Sections 4.2-4.3, read as the convective outflow condition of the
      populations entering the top row: f_i(x,N,t+1) = [f_i(x,N,t) + U f_i(x,N-1,t+1)]/(1+U),
      U = j_y/rho of the top node at time t clipped to [0,1]; zero-gradient pseudopotential and
-     velocity above it; the temperature stays T_top).  Runs on the one-step tile shapes of a
-     single context (not in a batch); mass leaves and enters through the top. */
+     velocity above it; the temperature stays T_top).  Runs on the one-step tile shapes; mass
+     leaves and enters through the top. */
   int32_t open_top;
 } lbm_params;
 
@@ -205,8 +205,8 @@ const char* lbm_last_error(const lbm_ctx* h);
  */
 size_t lbm_batch_footprint_bytes(int n);
 
-/* Build a batch over ctxs[0..n) (all initialised, same precision and thermal lattice, none with
-   an open top), enqueueing on hip_stream.
+/* Build a batch over ctxs[0..n) (all initialised, same precision and thermal lattice),
+   enqueueing on hip_stream.
    The batch's work is ordered after everything already enqueued on the contexts' own streams
    (their lbm_init, for instance), so a context may be initialised on a stream of its own.
    While the batch exists its members are advanced only through it.  Once lbm_batch_sync has

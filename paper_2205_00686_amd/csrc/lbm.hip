@@ -489,6 +489,15 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
   return LBM_OK;
 }
 
+// The open-top boundary pass after launch k, one workgroup per table entry.
+static void launch_open_top(int precision, int ninst, hipStream_t st, const void* table, const long long* clk,
+                            int k) {
+  if (precision == LBM_FP64)
+    open_top_kernel<double><<<ninst, 256, 0, st>>>((const InstDesc<double>*)table, clk, k);
+  else
+    open_top_kernel<float><<<ninst, 256, 0, st>>>((const InstDesc<float>*)table, clk, k);
+}
+
 static void launch_step(int precision, int qg, int shape, int grid, hipStream_t st, const void* table, int ninst,
                         const long long* clk, int k) {
 #define LBM_LAUNCH_F32(kk, ty, w, d) \
@@ -513,15 +522,9 @@ static void launch_step(int precision, int qg, int shape, int grid, hipStream_t 
 static lbm_status launch_steps(lbm_ctx* h, int n) {
   const int d = shape_def(h->prm.precision, h->shape).depth;
   const bool open = h->prm.y_walls && h->prm.open_top;
-  const int ob = (h->prm.nx + 255) / 256;
   for (int k = 0; k < n; ++k) {
     launch_step(h->prm.precision, qg_of(&h->prm), h->shape, h->ntiles, h->stream, h->d_desc, 1, h->d_clock, k);
-    if (open) {
-      if (h->prm.precision == LBM_FP64)
-        open_top_kernel<double><<<ob, 256, 0, h->stream>>>((const InstDesc<double>*)h->d_desc, h->d_clock, k);
-      else
-        open_top_kernel<float><<<ob, 256, 0, h->stream>>>((const InstDesc<float>*)h->d_desc, h->d_clock, k);
-    }
+    if (open) launch_open_top(h->prm.precision, 1, h->stream, h->d_desc, h->d_clock, k);
   }
   clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n * d);
   HIP_OR_FAIL(h, hipGetLastError());
@@ -904,8 +907,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   const int prec = ctxs[0] ? ctxs[0]->prm.precision : -1;
   const int qg = ctxs[0] ? qg_of(&ctxs[0]->prm) : 0;
   for (int i = 0; i < n; ++i)
-    if (!ctxs[i] || !ctxs[i]->initialised || ctxs[i]->prm.precision != prec || qg_of(&ctxs[i]->prm) != qg ||
-        (ctxs[i]->prm.y_walls && ctxs[i]->prm.open_top))
+    if (!ctxs[i] || !ctxs[i]->initialised || ctxs[i]->prm.precision != prec || qg_of(&ctxs[i]->prm) != qg)
       return LBM_E_INVAL;
   lbm_batch* b = new (std::nothrow) lbm_batch();
   if (!b) return LBM_E_NOMEM;
@@ -1029,8 +1031,12 @@ static lbm_status batch_upload(lbm_batch* b, int64_t todo) {
 static lbm_status batch_launch(lbm_batch* b, int nl) {
   const int n = (int)b->ctx.size();
   const int d = shape_def(b->precision, b->shape).depth;
-  for (int s = 0; s < nl; ++s)
+  bool open = false;
+  for (const lbm_ctx* h : b->ctx) open = open || (h->prm.y_walls && h->prm.open_top);
+  for (int s = 0; s < nl; ++s) {
     launch_step(b->precision, b->qg, b->shape, b->total_tiles, b->stream, b->d_table, n, b->d_clock, s);
+    if (open) launch_open_top(b->precision, n, b->stream, b->d_table, b->d_clock, s);
+  }
   clock_advance_kernel<<<1, 64, 0, b->stream>>>(b->d_clock, (long long)nl * d);
   HIP_OR_FAIL(b->ctx[0], hipGetLastError());
   return LBM_OK;

@@ -960,30 +960,32 @@ __global__ void clock_advance_kernel(long long* clock, long long n) {
 // the top row N from outside (c_y = -1) follow the convective outflow condition
 //   f_i(x, N, t+1) = [f_i(x, N, t) + U f_i(x, N-1, t+1)] / (1 + U),
 // U = j_y / rho of the top node at time t clipped to [0, 1].  f(t) is in the step's source
-// buffers, f(t+1) of row N-1 in its destination buffers.  One thread per column of the single
-// simulation in table entry 0.
+// buffers, f(t+1) of row N-1 in its destination buffers.  Workgroup b serves table entry b
+// (entries without an open top, or outside their window, return at once), its threads stride
+// over the columns.
 template <typename real>
 __global__ void open_top_kernel(const InstDesc<real>* __restrict__ table, const long long* __restrict__ clock, int k) {
-  const InstDesc<real>& D = table[0];
+  const InstDesc<real>& D = table[blockIdx.x];
+  if (!D.p.open_top) return;
   const long long t = *clock + k;
   if (t < D.t_base || t >= D.t_end) return;
-  const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (x >= D.nx) return;
   const bool odd = ((D.b_base + (t - D.t_base)) & 1) != 0;
   const real* __restrict__ fs = odd ? D.fB : D.fA;
   real* __restrict__ fd = odd ? D.fA : D.fB;
   const size_t N = (size_t)D.nx * (size_t)D.ny;
-  const size_t top = (size_t)(D.ny - 1) * (size_t)D.nx + (size_t)x, below = top - (size_t)D.nx;
-  real f[9];
+  for (int x = (int)threadIdx.x; x < D.nx; x += (int)blockDim.x) {
+    const size_t top = (size_t)(D.ny - 1) * (size_t)D.nx + (size_t)x, below = top - (size_t)D.nx;
+    real f[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = fs[i * N + top];
-  const real rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-  const real jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
-  real U = jy / rho;
-  U = U < real(0) ? real(0) : (U > real(1) ? real(1) : U);
-  fd[4 * N + top] = (f[4] + U * fd[4 * N + below]) / (real(1) + U);
-  fd[7 * N + top] = (f[7] + U * fd[7 * N + below]) / (real(1) + U);
-  fd[8 * N + top] = (f[8] + U * fd[8 * N + below]) / (real(1) + U);
+    for (int i = 0; i < 9; ++i) f[i] = fs[i * N + top];
+    const real rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const real jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+    real U = jy / rho;
+    U = U < real(0) ? real(0) : (U > real(1) ? real(1) : U);
+    fd[4 * N + top] = (f[4] + U * fd[4 * N + below]) / (real(1) + U);
+    fd[7 * N + top] = (f[7] + U * fd[7 * N + below]) / (real(1) + U);
+    fd[8 * N + top] = (f[8] + U * fd[8 * N + below]) / (real(1) + U);
+  }
 }
 
 template <typename real>

@@ -136,7 +136,7 @@ def sweep(workloads, rho_l: float, rho_g: float, max_steps: int = 60000, check_e
                 nx, ny = w.params.nx, w.params.ny
                 x0 = int(round(w.params.hot_x0))
                 half = (window or nx // 2) // 2
-                y_surface = int(w.meta["fill"] * ny) - surface_margin
+                y_surface = int(min(w.meta["fill"], 1.0) * ny) - surface_margin
                 rows = s.vapour_rows(rho_mid, x0 - half, x0 + half)
                 res[i].profile_checks += 1
                 if not gap_above_vapour(rows, y_surface):
