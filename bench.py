@@ -34,7 +34,7 @@ BYTES_PER_LU = {"f32": 128, "f64": 256}  # f 9+9, g 5+5, history 2+2 values per 
 # HBM bytes per launch of the step kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # scaled by the same counters read for a plain copy of known size (profiles/); keyed by grid size
 # and tile shape, None where no measurement of the current kernel exists
-TRAFFIC = {(512, 512, 6): 36286873}
+TRAFFIC = {(512, 512, 6): 37693644}
 
 
 def build_workload(nx=512, ny=512, steps=20000):
