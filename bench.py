@@ -34,16 +34,22 @@ BYTES_PER_LU = {"f32": 128, "f64": 256}  # f 9+9, g 5+5, history 2+2 values per 
 # HBM bytes per launch of the step kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # scaled by the same counters read for a plain copy of known size (profiles/); keyed by grid size
 # and tile shape, None where no measurement of the current kernel exists
-TRAFFIC = {(512, 512, 6): 37693644}
+TRAFFIC = {("evaporation", 512, 512, 6): 37693644}
 
 
-def build_workload(nx=512, ny=512, steps=20000):
+def build_workload(nx=512, ny=512, steps=20000, kind="evaporation"):
+    """evaporation: the benchmark workload.  boiling: the nucleate-boiling pool (walls, hot spot of
+    width 32 and dT 0.2 Tc, g = 2e-5, noise from seed 1); its pool is filled to the head limit of
+    the closed box (workloads.head_limited_fill) so that it stays stable over a long timed run."""
     import paper_2205_00686_amd as lbm
-    from workloads import Params, evaporation
+    from workloads import Params, boiling, evaporation, head_limited_fill
 
     base = Params()
     Tc = lbm.critical_temperature(base)
-    rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
+    rl, rg, ps = lbm.coexistence(base, 0.86 * Tc)
+    if kind == "boiling":
+        return boiling(Tc, rl, rg, nx=nx, ny=ny, gravity=2e-5, seed=1, steps=steps,
+                       fill=head_limited_fill(rl, rg, ps, 2e-5, ny))
     return evaporation(Tc, rl, rg, nx=nx, ny=ny, R=64.0 * nx / 512, superheat=1.10, steps=steps)
 
 
@@ -58,7 +64,7 @@ def cpu_baseline(w, steps):
     o.step(steps)
     dt = time.perf_counter() - t0
     return {"value": w.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{w.params.nx}x{w.params.ny} evaporation, FP64, {steps} steps after 2 warm-up steps "
+            "sample": f"{w.params.nx}x{w.params.ny} {w.name}, FP64, {steps} steps after 2 warm-up steps "
                       f"({dt:.1f} s)"}
 
 
@@ -418,6 +424,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20000; 10000 with --mode batch)")
     ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--workload", choices=["evaporation", "boiling"], default="evaporation",
+                    help="plain mode: the benchmark workload (default) or the boiling pool")
     ap.add_argument("--nx", type=int, default=512)
     ap.add_argument("--ny", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=2000)
@@ -456,11 +464,11 @@ def main():
     import paper_2205_00686_amd as lbm
 
     torch.cuda.set_device(0)
-    w = build_workload(args.nx, args.ny, args.steps)
+    w = build_workload(args.nx, args.ny, args.steps, args.workload)
     s = lbm.Solver(w.params, precision=lbm.LBM_FP32).init(w.rho, w.ux, w.uy, w.T)
     stream = s.stream
-    print(f"[bench] {args.nx}x{args.ny} evaporation FP32, warmup {args.warmup}, steps {args.steps}", file=sys.stderr,
-          flush=True)
+    print(f"[bench] {args.nx}x{args.ny} {args.workload} FP32, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
 
     if args.calibration_copy_mib > 0:
         n = args.calibration_copy_mib * (1 << 20) // 4
@@ -519,14 +527,16 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
-        "data": "synthetic (seeded initial fields of the paper's droplet-evaporation problem)",
-        "config": {"workload": f"droplet evaporation in open space, {args.nx}x{args.ny}, FP32 populations, "
-                               f"R={64 * args.nx // 512}, edges at 1.1 T_sat",
+        "data": f"synthetic (seeded initial fields of the paper's {args.workload} problem)",
+        "config": {"workload": (f"droplet evaporation in open space, {args.nx}x{args.ny}, FP32 populations, "
+                                f"R={64 * args.nx // 512}, edges at 1.1 T_sat") if args.workload == "evaporation" else
+                               (f"nucleate boiling on a heated wall, {args.nx}x{args.ny}, FP32 populations, walls, "
+                                f"hot spot width 32 dT 0.2 Tc, g 2e-5, pool fill {w.meta['fill']:.3f} (head limit)"),
                    "nx": args.nx, "ny": args.ny, "precision": "fp32", "kernel": "fused D2Q9+D2Q5 step",
                    "tile_shape": shape_text(lbm, lbm.LBM_FP32, s.shape), "tile_shape_ms_per_step": tune,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((args.nx, args.ny, s.shape)),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((args.workload, args.nx, args.ny, s.shape)),
                      "bytes_per_launch": bytes_per_launch, "steps_per_launch": depth,
                      "kernel_ms_per_launch_timed_region": round(ms_per_launch, 6),
                      "kernel_ms_single_step_call_p50": round(launch_p50, 6)},
