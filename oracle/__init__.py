@@ -43,6 +43,8 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
+    from . import o3d  # the three-dimensional oracle is built alongside
+    o3d.build(force)
     return _LIB
 
 

@@ -222,3 +222,74 @@ def request_stream(n=256, rate=20.0, seed=3, nx_range=(128, 1024), ny_range=(128
         steps = int(rng.integers(steps_range[0], steps_range[1] + 1))
         out.append({"id": k, "arrival": t, "kind": kind, "nx": nx, "ny": ny, "steps": steps, "seed": 5000 + k})
     return out
+
+
+# ----------------------------------------------------------------------------- three dimensions
+@dataclass
+class Params3D:
+    """Parameters of a three-dimensional simulation (D3Q19 flow, D3Q7 temperature; lattice units).
+    Defaults follow the two-dimensional ones; the D3Q7 weight parameter wdot gives chat_s^2 = wdot/3."""
+    nx: int = 32
+    ny: int = 32
+    nz: int = 32
+    a: float = 3.0 / 49.0
+    b: float = 2.0 / 21.0
+    R: float = 1.0
+    acentric: float = 0.344
+    G: float = -1.0
+    nu: float = 0.1
+    s_e: float = 1.0
+    s_eps: float = 1.0
+    sigma: float = 1.25
+    lambda_: float = 1.0 / 3.0
+    cv: float = 5.0
+    wdot: float = 2.0 / 3.0
+    vs3: float = 1.0
+    thermal_box: int = 0
+    T_box: float = 0.0
+    flags: int = 0
+
+    def replace(self, **kw) -> "Params3D":
+        return dataclasses.replace(self, **kw)
+
+
+@dataclass
+class Workload3D:
+    name: str
+    params: Params3D
+    rho: np.ndarray
+    ux: np.ndarray
+    uy: np.ndarray
+    uz: np.ndarray
+    T: np.ndarray
+    steps: int
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nodes(self) -> int:
+        return int(self.params.nx) * int(self.params.ny) * int(self.params.nz)
+
+
+def tanh_sphere(nx, ny, nz, R0, rho_l, rho_g, width=5.0) -> np.ndarray:
+    """Eq. (56) in three dimensions, centred in the box: arrays of shape (nz, ny, nx)."""
+    z, y, x = np.mgrid[0:nz, 0:ny, 0:nx].astype(np.float64)
+    r = np.sqrt((x - nx / 2.0) ** 2 + (y - ny / 2.0) ** 2 + (z - nz / 2.0) ** 2)
+    return 0.5 * (rho_l + rho_g) - 0.5 * (rho_l - rho_g) * np.tanh((r - R0) / (0.5 * width))
+
+
+def droplet3d(Tc, rho_l, rho_g, n=48, R=12.0, T_rel=0.86, steps=2000, **kw) -> Workload3D:
+    """Static droplet in a periodic cube at uniform saturation temperature."""
+    p = Params3D(nx=n, ny=n, nz=n, **kw)
+    rho = tanh_sphere(n, n, n, R, rho_l, rho_g)
+    z = np.zeros_like(rho)
+    return Workload3D("droplet3d", p, rho, z, z.copy(), z.copy(), np.full_like(rho, T_rel * Tc), steps, {"R": R})
+
+
+def evaporation3d(Tc, rho_l, rho_g, n=128, R=16.0, T_rel=0.86, superheat=1.10, steps=20000, **kw) -> Workload3D:
+    """Droplet in saturated vapour in a cube whose faces are held at superheat * T_sat; flow periodic."""
+    T_sat = T_rel * Tc
+    p = Params3D(nx=n, ny=n, nz=n, thermal_box=1, T_box=superheat * T_sat, **kw)
+    rho = tanh_sphere(n, n, n, R, rho_l, rho_g)
+    z = np.zeros_like(rho)
+    return Workload3D("evaporation3d", p, rho, z, z.copy(), z.copy(), np.full_like(rho, T_sat), steps,
+                      {"R": R, "T_sat": T_sat})
