@@ -23,11 +23,26 @@ EXPORTS = (
     "lbm_load_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
     "lbm_last_error", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
     "lbm_batch_remaining", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_sync", "lbm_batch_destroy",
+    "lbm3d_params_default", "lbm3d_validate", "lbm3d_footprint_bytes", "lbm3d_create", "lbm3d_init", "lbm3d_step",
+    "lbm3d_sync", "lbm3d_read_fields", "lbm3d_diagnostics", "lbm3d_steps_done", "lbm3d_destroy",
 )
 
 
 class NativeLibraryMissing(RuntimeError):
     pass
+
+
+class Lbm3dParams(ctypes.Structure):
+    """Mirror of lbm3d_params (include/lbm3d.h)."""
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("R", ctypes.c_double), ("acentric", ctypes.c_double),
+        ("G", ctypes.c_double),
+        ("nu", ctypes.c_double), ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("lambda_", ctypes.c_double), ("cv", ctypes.c_double), ("wdot", ctypes.c_double), ("vs3", ctypes.c_double),
+        ("thermal_box", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("T_box", ctypes.c_double),
+        ("flags", ctypes.c_uint32), ("reserved1", ctypes.c_uint32),
+    ]
 
 
 class LbmParams(ctypes.Structure):
@@ -64,6 +79,7 @@ def lib():
         raise NativeLibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build()")
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER(LbmParams)
+    P3 = ctypes.POINTER(Lbm3dParams)
     vp, d, i32, i64, sz = ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     dp = ctypes.POINTER(ctypes.c_double)
     ip = ctypes.POINTER(ctypes.c_int)
@@ -102,6 +118,17 @@ def lib():
         "lbm_batch_get_shape": ([vp], ctypes.c_int),
         "lbm_batch_sync": ([vp, ctypes.POINTER(ctypes.c_int)], st),
         "lbm_batch_destroy": ([vp], st),
+        "lbm3d_params_default": ([P3, i32, i32, i32], None),
+        "lbm3d_validate": ([P3], st),
+        "lbm3d_footprint_bytes": ([P3], sz),
+        "lbm3d_create": ([P3, vp, sz, vp, ctypes.POINTER(vp)], st),
+        "lbm3d_init": ([vp, dp, dp, dp, dp, dp], st),
+        "lbm3d_step": ([vp, i64], st),
+        "lbm3d_sync": ([vp], st),
+        "lbm3d_read_fields": ([vp, dp, dp, dp, dp, dp], st),
+        "lbm3d_diagnostics": ([vp, dp, dp], st),
+        "lbm3d_steps_done": ([vp], i64),
+        "lbm3d_destroy": ([vp], st),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)

@@ -12,9 +12,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_symbols():
-    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = "".join(open(os.path.join(ROOT, "include", n)).read() for n in ("lbm.h", "lbm3d.h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lbm(?:3d)?_[a-z_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -30,6 +30,27 @@ def test_every_declared_symbol_is_exported(L):
     assert set(syms) == set(_native.EXPORTS)
     for s in syms:
         assert hasattr(L, s), s
+
+
+def test_3d_validate_and_footprint(L):
+    from paper_2205_00686_amd import _native
+    p = _native.Lbm3dParams()
+    L.lbm3d_params_default(ctypes.byref(p), 64, 48, 32)
+    assert L.lbm3d_validate(ctypes.byref(p)) == 0
+    n = 64 * 48 * 32
+    assert 276 * n <= L.lbm3d_footprint_bytes(ctypes.byref(p)) <= 276 * n + 64 * 1024
+    p.precision = 1
+    assert 552 * n <= L.lbm3d_footprint_bytes(ctypes.byref(p)) <= 552 * n + 64 * 1024
+    for field, bad in (("nz", 2), ("nu", 0.0), ("wdot", 1.0), ("precision", 3), ("flags", 8), ("s_e", 2.5)):
+        q = _native.Lbm3dParams()
+        L.lbm3d_params_default(ctypes.byref(q), 16, 16, 16)
+        setattr(q, field, bad)
+        assert L.lbm3d_validate(ctypes.byref(q)) == -1, field
+        assert L.lbm3d_footprint_bytes(ctypes.byref(q)) == 0
+    q = _native.Lbm3dParams()
+    L.lbm3d_params_default(ctypes.byref(q), 16, 16, 16)
+    q.thermal_box = 1  # no box temperature
+    assert L.lbm3d_validate(ctypes.byref(q)) == -1
 
 
 def test_library_carries_gfx950_code_object():
