@@ -408,8 +408,9 @@ def run_3d_mode(args):
     Dirichlet temperature box, FP32, at 128^3 and 256^3.  (A droplet started from the tanh profile
     sends an inward pressure wave that focuses at its centre; from R = 32 on it pushes the density
     past the EOS limit within about 35 steps, in the FP64 oracle as on the GPU.)  Algorithmic bytes per node update:
-    f 19 + 19, g 7 + 7, history 2 + 2 values = 224 B in FP32.  The step runs as three kernels whose
-    per-node fields (15 planes) also pass through HBM."""
+    f 19 + 19, g 7 + 7, history 2 + 2 values = 224 B in FP32.  Both step paths are timed: the fused
+    kernel (one per step) and the per-node kernels (three per step, whose per-node fields, 15
+    planes, also pass through HBM); --z-chunk sets the fused path's planes per workgroup."""
     import torch
 
     import paper_2205_00686_amd as lbm
@@ -420,8 +421,10 @@ def run_3d_mode(args):
     Tc = lbm.critical_temperature(base)
     rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
     rows = []
-    for n, steps in ((128, args.steps), (256, max(20, args.steps // 8))):
+    for n, steps, path in ((128, args.steps, 0), (256, max(20, args.steps // 8), 0),
+                           (128, args.steps, 1), (256, max(20, args.steps // 8), 1)):
         w = evaporation3d(Tc, rl, rg, n=n, R=16.0, superheat=1.1)
+        w.params = w.params.replace(path=path, z_chunk=args.z_chunk if path == 0 else 0)
         s = three_d.Solver3D(w.params).init(w.rho, w.ux, w.uy, w.uz, w.T)
         s.step(10)
         s.sync()
@@ -433,7 +436,8 @@ def run_3d_mode(args):
         s.sync()
         ms = e0.elapsed_time(e1) / steps
         mass, _ = s.diagnostics()
-        rows.append({"grid": f"{n}^3", "steps": steps, "us_per_step": round(ms * 1e3, 2),
+        rows.append({"grid": f"{n}^3", "path": "fused" if path == 0 else "per-node", "steps": steps,
+                     "us_per_step": round(ms * 1e3, 2),
                      "mlups": round(w.nodes / (ms * 1e-3) / 1e6, 1),
                      "roofline_frac": round(w.nodes * 224 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "mass_drift": abs(mass / float(w.rho.sum()) - 1.0)})
@@ -458,6 +462,7 @@ def main():
     ap.add_argument("--pre-steps", type=int, default=20000, help="heated: unheated steps before the wall is heated")
     ap.add_argument("--stop-fraction", type=float, default=0.1, help="heated: stop when this much liquid is left")
     ap.add_argument("--check-every", type=int, default=250)
+    ap.add_argument("--z-chunk", type=int, default=0, help="3d: z planes per workgroup of the fused kernel (0: auto)")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--rate", type=float, default=20.0)

@@ -18,6 +18,11 @@
  * Layout in the caller's device memory: f[19][nz][ny][nx], g[7][nz][ny][nx], the temperature
  * history [2][nz][ny][nx] (x fastest), the populations in two copies, plus per-node fields of
  * the current step (15 planes) and a small control block.
+ *
+ * Two step paths give the same results up to the summation order of div u:
+ *   LBM3D_PATH_FUSED (default): one kernel per step; 64 x 8 column tiles, each workgroup marching
+ *     through a chunk of z planes with psi, u and the streaming-destination values in LDS;
+ *   LBM3D_PATH_PER_NODE: three kernels per step, per-node fields in HBM between them.
  */
 #ifndef LBM3D_H
 #define LBM3D_H
@@ -43,18 +48,21 @@ typedef struct {
      chat_s^2 = wdot/3; heat capacity c_v; vs3 the rate of the three second-order moments */
   double lambda, cv, wdot, vs3;
   int32_t thermal_box;      /* 1: T = T_box on all six faces */
-  int32_t reserved0;
+  int32_t z_chunk;          /* fused path: z planes per workgroup; 0 = about one workgroup per CU */
   double T_box;
   uint32_t flags;           /* LBM_FREEZE_FLOW | LBM_NO_S, tests only */
-  uint32_t reserved1;
+  uint32_t path;            /* LBM3D_PATH_FUSED or LBM3D_PATH_PER_NODE */
 } lbm3d_params;
+
+#define LBM3D_PATH_FUSED 0u
+#define LBM3D_PATH_PER_NODE 1u
 
 /* The paper's values (as in two dimensions) for an nx x ny x nz FP32 grid. */
 void lbm3d_params_default(lbm3d_params* p, int32_t nx, int32_t ny, int32_t nz);
 
 /* LBM_E_INVAL if a size is < 3, a population plane exceeds 2^32 - 1 bytes, a rate is outside
-   (0, 2), wdot outside (0, 1), c_v, nu or lambda <= 0, an unknown flag is set, or the box
-   temperature is not positive and finite. */
+   (0, 2), wdot outside (0, 1), c_v, nu or lambda <= 0, an unknown flag is set, the box
+   temperature is not positive and finite, z_chunk < 0 or the path is unknown. */
 lbm_status lbm3d_validate(const lbm3d_params* p);
 
 /* Exact device bytes a context needs: 276 B per node in FP32 (f 19 and g 7 in two copies, the
@@ -71,8 +79,9 @@ lbm_status lbm3d_create(const lbm3d_params* p, void* dev_mem, size_t bytes, void
 lbm_status lbm3d_init(lbm3d_ctx* h, const double* rho, const double* ux, const double* uy, const double* uz,
                       const double* T);
 
-/* Enqueue n time steps (three kernels per step: per-node fields; forces and velocity;
-   collision and streaming).  Asynchronous.  LBM_E_STATE before init or after a failure. */
+/* Enqueue n time steps (the fused path: one kernel per step; the per-node path: per-node fields,
+   forces and velocity, collision and streaming).  Asynchronous.  LBM_E_STATE before init or after
+   a failure. */
 lbm_status lbm3d_step(lbm3d_ctx* h, int64_t n);
 
 /* Wait for the stream; report a device-side numerical failure (sticky). */

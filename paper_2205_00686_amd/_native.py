@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NUMERIC, LBM_E_STATE = 0, -1, -2, -3, -4, -5
 LBM_FP32, LBM_FP64 = 0, 1
 LBM_FREEZE_FLOW, LBM_NO_S, LBM_BGK = 1, 2, 8
+LBM3D_PATH_FUSED, LBM3D_PATH_PER_NODE = 0, 1
 
 # every symbol include/lbm.h declares
 EXPORTS = (
@@ -40,8 +41,8 @@ class Lbm3dParams(ctypes.Structure):
         ("G", ctypes.c_double),
         ("nu", ctypes.c_double), ("s_e", ctypes.c_double), ("s_eps", ctypes.c_double), ("sigma", ctypes.c_double),
         ("lambda_", ctypes.c_double), ("cv", ctypes.c_double), ("wdot", ctypes.c_double), ("vs3", ctypes.c_double),
-        ("thermal_box", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("T_box", ctypes.c_double),
-        ("flags", ctypes.c_uint32), ("reserved1", ctypes.c_uint32),
+        ("thermal_box", ctypes.c_int32), ("z_chunk", ctypes.c_int32), ("T_box", ctypes.c_double),
+        ("flags", ctypes.c_uint32), ("path", ctypes.c_uint32),
     ]
 
 

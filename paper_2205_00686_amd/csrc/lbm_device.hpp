@@ -109,6 +109,28 @@ __device__ __forceinline__ gptr<T> to_global(T* p) {
   return (gptr<T>)p;
 }
 
+// Global accesses as (uniform base, 32-bit byte offset per lane): the base lives in scalar
+// registers and one vector register carries the offset, so an access costs no vector
+// arithmetic.  A plane holds fewer than 2^32 bytes (checked by lbm_validate).
+// A base computed by uniform arithmetic is passed through readfirstlane (it already is uniform,
+// so this costs two scalar moves), which keeps the compiler from folding the plane offset into a
+// 64-bit per-lane address.
+template <typename T>
+__device__ __forceinline__ gptr<T> sbase(gptr<T> ptr) {
+  const unsigned long long v = (unsigned long long)ptr;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (gptr<T>)(((unsigned long long)hi << 32) | lo);
+}
+template <typename real>
+__device__ __forceinline__ real ldb(gptr<const char> base, unsigned off) {
+  return *(gptr<const real>)(base + off);
+}
+template <typename real>
+__device__ __forceinline__ void stb(gptr<char> base, unsigned off, real v) {
+  *(gptr<real>)(base + off) = v;
+}
+
 // Reciprocal and square root: hardware instructions (1 ulp) in FP32, IEEE-exact in FP64.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }

@@ -136,28 +136,6 @@ __device__ __forceinline__ int row_kind(int y, int ny, int walls) {
   return 3;
 }
 
-// Global accesses as (uniform base, 32-bit byte offset per lane): the base lives in scalar
-// registers and one vector register carries the offset, so an access costs no vector
-// arithmetic.  A plane holds fewer than 2^32 bytes (checked by lbm_validate).
-// A base computed by uniform arithmetic is passed through readfirstlane (it already is uniform,
-// so this costs two scalar moves), which keeps the compiler from folding the plane offset into a
-// 64-bit per-lane address.
-template <typename T>
-__device__ __forceinline__ gptr<T> sbase(gptr<T> ptr) {
-  const unsigned long long v = (unsigned long long)ptr;
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-  return (gptr<T>)(((unsigned long long)hi << 32) | lo);
-}
-template <typename real>
-__device__ __forceinline__ real ldb(gptr<const char> base, unsigned off) {
-  return *(gptr<const real>)(base + off);
-}
-template <typename real>
-__device__ __forceinline__ void stb(gptr<char> base, unsigned off, real v) {
-  *(gptr<real>)(base + off) = v;
-}
-
 // ------------------------------------------------------------------------- per-node arithmetic
 
 // rho, j, T of a node and its LDS entries (Eqs. 11 and 25), psi with error checks; returns

@@ -41,7 +41,8 @@ def test_3d_validate_and_footprint(L):
     assert 276 * n <= L.lbm3d_footprint_bytes(ctypes.byref(p)) <= 276 * n + 64 * 1024
     p.precision = 1
     assert 552 * n <= L.lbm3d_footprint_bytes(ctypes.byref(p)) <= 552 * n + 64 * 1024
-    for field, bad in (("nz", 2), ("nu", 0.0), ("wdot", 1.0), ("precision", 3), ("flags", 8), ("s_e", 2.5)):
+    for field, bad in (("nz", 2), ("nu", 0.0), ("wdot", 1.0), ("precision", 3), ("flags", 8), ("s_e", 2.5),
+                       ("z_chunk", -1), ("path", 2)):
         q = _native.Lbm3dParams()
         L.lbm3d_params_default(ctypes.byref(q), 16, 16, 16)
         setattr(q, field, bad)
@@ -51,6 +52,8 @@ def test_3d_validate_and_footprint(L):
     L.lbm3d_params_default(ctypes.byref(q), 16, 16, 16)
     q.thermal_box = 1  # no box temperature
     assert L.lbm3d_validate(ctypes.byref(q)) == -1
+    q.thermal_box, q.path, q.z_chunk = 0, _native.LBM3D_PATH_PER_NODE, 5
+    assert L.lbm3d_validate(ctypes.byref(q)) == 0
 
 
 def test_library_carries_gfx950_code_object():

@@ -2,7 +2,9 @@
 through the C ABI: a static droplet (periodic cube), an evaporating droplet in a Dirichlet
 temperature box, a ragged random case, the test flags; FP64 to rounding, FP32 after 100 steps
 within the two-dimensional bounds (rho within 2e-4 rho_l, T within 2e-6 relative, u within 1e-5);
-mass conservation of the FP64 diagnostics."""
+mass conservation of the FP64 diagnostics.  Both step paths: the fused kernel (default) on grids
+spanning several column tiles (64 x 8) with ragged edges and several z chunks, its results
+bit-identical for every chunking, and the per-node kernels."""
 import numpy as np
 import pytest
 
@@ -101,3 +103,75 @@ def test_3d_test_flags_fp64(lbm3, o3, orc, flags):
     s, _, _, _, err = _run(lbm3, o3, w, 40, 1, f"flags={flags}")
     assert err["rho"] <= 1e-11 and err["T"] <= 1e-13
     s.close()
+
+
+def _random3d(orc, nx, ny, nz, seed, box):
+    Tc, rl, rg = _sat(orc)
+    rng = np.random.default_rng(seed)
+    shp = (nz, ny, nx)
+    # smooth random density (a sum of a few low modes) so that a few steps stay well defined
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    m = np.zeros(shp)
+    for _ in range(6):
+        k = rng.integers(1, 3, 3)
+        ph = rng.uniform(0, 2 * np.pi, 3)
+        m += np.cos(2 * np.pi * k[0] * x / nx + ph[0]) * np.cos(2 * np.pi * k[1] * y / ny + ph[1]) * \
+            np.cos(2 * np.pi * k[2] * z / nz + ph[2])
+    m = (m - m.min()) / (m.max() - m.min())
+    rho = rg + (rl - rg) * m
+    T = 0.86 * Tc * (1 + 0.01 * rng.uniform(-1, 1, shp))
+    u = [0.01 * rng.standard_normal(shp) for _ in range(3)]
+    from workloads import Workload3D
+    p = Params3D(nx=nx, ny=ny, nz=nz, thermal_box=box, T_box=0.9 * Tc)
+    return Workload3D("random", p, rho, u[0], u[1], u[2], T, 20)
+
+
+@pytest.mark.parametrize("box", [0, 1])
+def test_3d_fused_multi_tile_fp64(lbm3, o3, orc, box):
+    """80 x 19 x 13: two column tiles in x (64 + 16), three in y (8 + 8 + 3), z chunks of 5, 5, 3;
+    periodic and in a Dirichlet box (anti-bounce-back on every face of the tiles at the boundary)."""
+    w = _random3d(orc, 80, 19, 13, 8013 + box, box)
+    w.params = w.params.replace(z_chunk=5)
+    s, _, _, _, err = _run(lbm3, o3, w, 12, 1, f"fused multi-tile box={box}")
+    assert err["rho"] <= 1e-11 and err["T"] <= 1e-13 and max(err["ux"], err["uy"], err["uz"]) <= 1e-12
+    s.close()
+
+
+def test_3d_fused_fp32_multi_tile(lbm3, o3, orc):
+    """FP32 fused kernel on 136 x 24 x 20 (three x tiles, the last 8 wide) against the oracle."""
+    Tc, rl, rg = _sat(orc)
+    w = evaporation3d(Tc, rl, rg, n=24, R=7.0, superheat=1.2)
+    # widen the box in x with vapour: the droplet sits in the first tile, the rest is quiescent
+    from workloads import Workload3D
+    pad = 136 - 24
+    ext = lambda a, v: np.concatenate([a, np.full(a.shape[:2] + (pad,), v)], axis=2)
+    rg_far = float(w.rho[0, 0, 0])
+    T_far = float(w.T[0, 0, 0])
+    p = w.params.replace(nx=136)
+    w2 = Workload3D("evap-wide", p, ext(w.rho, rg_far), ext(w.ux, 0.0), ext(w.uy, 0.0), ext(w.uz, 0.0),
+                    ext(w.T, T_far), 100)
+    s, _, got, exp, err = _run(lbm3, o3, w2, 60, 0, "fused fp32 wide")
+    Tmax = float(np.abs(exp[4]).max())
+    assert err["rho"] <= 2e-4 * 6.5 and err["T"] <= 2e-6 * Tmax
+    assert max(err["ux"], err["uy"], err["uz"]) <= 1e-5
+    s.close()
+
+
+def test_3d_fused_chunking_is_bitwise_and_matches_per_node(lbm3, orc):
+    """The fused kernel's result does not depend on the z chunking (bit for bit, FP32), and the
+    per-node path agrees with it to FP32 rounding (only div u sums its terms in another order)."""
+    w = _random3d(orc, 70, 17, 11, 7011, 1)
+    out = {}
+    for name, kw in (("auto", {}), ("z1", {"z_chunk": 1}), ("z4", {"z_chunk": 4}), ("z11", {"z_chunk": 11}),
+                     ("per_node", {"path": 1})):
+        p = w.params.replace(**kw)
+        print(f"\n[case] 3d chunking {name}", flush=True)
+        s = lbm3.Solver3D(p, precision=0).init(w.rho, w.ux, w.uy, w.uz, w.T)
+        s.step(15)
+        out[name] = s.fields()
+        s.close()
+    for name in ("z1", "z4", "z11"):
+        for a, b in zip(out["auto"], out[name]):
+            assert np.array_equal(a, b), name
+    for a, b in zip(out["auto"], out["per_node"]):
+        assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max())

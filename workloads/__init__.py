@@ -248,6 +248,8 @@ class Params3D:
     thermal_box: int = 0
     T_box: float = 0.0
     flags: int = 0
+    z_chunk: int = 0  # GPU fused path: z planes per workgroup (0: automatic)
+    path: int = 0     # GPU step path: 0 fused, 1 per-node kernels
 
     def replace(self, **kw) -> "Params3D":
         return dataclasses.replace(self, **kw)
