@@ -35,6 +35,9 @@ BYTES_PER_LU = {"f32": 128, "f64": 256}  # f 9+9, g 5+5, history 2+2 values per 
 # HBM bytes per launch of the step kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
 # scaled by the same counters read for a plain copy of known size (profiles/); keyed by grid size
 # and tile shape, None where no measurement of the current kernel exists
+# Measured HBM bytes per launch of the fused 3-D kernel (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a
+# plain copy): (edge, path, z_chunk) -> bytes, for the kernel as profiled
+TRAFFIC3D = {(256, 0, 0): 3986283140}
 TRAFFIC = {("evaporation", 512, 512, 6): 37693644}
 
 
@@ -421,8 +424,15 @@ def run_3d_mode(args):
     Tc = lbm.critical_temperature(base)
     rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
     rows = []
-    for n, steps, path in ((128, args.steps, 0), (256, max(20, args.steps // 8), 0),
-                           (128, args.steps, 1), (256, max(20, args.steps // 8), 1)):
+    if args.calibration_copy_mib > 0:
+        src = torch.ones(args.calibration_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
+    grids = [int(v) for v in args.grids3d.split(",")]
+    paths = [{"fused": 0, "per-node": 1}[v] for v in args.paths3d.split(",")]
+    for path, n in [(pa, g) for pa in paths for g in grids]:
+        steps = args.steps if n <= 128 else max(20, args.steps * 128 ** 3 // n ** 3)
         w = evaporation3d(Tc, rl, rg, n=n, R=16.0, superheat=1.1)
         w.params = w.params.replace(path=path, z_chunk=args.z_chunk if path == 0 else 0)
         s = three_d.Solver3D(w.params).init(w.rho, w.ux, w.uy, w.uz, w.T)
@@ -436,7 +446,9 @@ def run_3d_mode(args):
         s.sync()
         ms = e0.elapsed_time(e1) / steps
         mass, _ = s.diagnostics()
+        traffic = TRAFFIC3D.get((n, path, args.z_chunk))
         rows.append({"grid": f"{n}^3", "path": "fused" if path == 0 else "per-node", "steps": steps,
+                     "traffic_bytes": traffic,
                      "us_per_step": round(ms * 1e3, 2),
                      "mlups": round(w.nodes / (ms * 1e-3) / 1e6, 1),
                      "roofline_frac": round(w.nodes * 224 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -463,6 +475,8 @@ def main():
     ap.add_argument("--stop-fraction", type=float, default=0.1, help="heated: stop when this much liquid is left")
     ap.add_argument("--check-every", type=int, default=250)
     ap.add_argument("--z-chunk", type=int, default=0, help="3d: z planes per workgroup of the fused kernel (0: auto)")
+    ap.add_argument("--grids3d", default="128,256", help="3d: edge lengths of the cubic grids")
+    ap.add_argument("--paths3d", default="fused,per-node", help="3d: step paths to time")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--rate", type=float, default=20.0)
