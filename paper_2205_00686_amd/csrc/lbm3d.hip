@@ -976,19 +976,35 @@ void launch_fields(lbm3d_ctx* h) {
   force3_kernel<real><<<nb, 256, 0, h->stream>>>(p, b, h->N);
 }
 
-// Column tiles of the fused path (64 x FUSED_TY) and planes per workgroup: without a choice of the
-// caller, enough z chunks for about one workgroup per compute unit
+// Column tiles of the fused path (64 x FUSED_TY) and planes per workgroup.  A workgroup fills a
+// compute unit (its registers allow one per CU), so a launch takes ceil(workgroups / 256) rounds of
+// (planes + 4) iterations each (the 4 extra planes are the chunk's halo in z).  Without a choice of
+// the caller the number of z chunks minimises that; ties go to fewer chunks.
 constexpr int FUSED_TY = 8;
 constexpr int NCU3 = 256;
 
 void fused_geometry(const lbm3d_params* p, int& ntx, int& nty, int& lz, int& nwg) {
   ntx = (p->nx + 63) / 64;
   nty = (p->ny + FUSED_TY - 1) / FUSED_TY;
-  const int cols = ntx * nty;
-  int nch = p->z_chunk > 0 ? (p->nz + p->z_chunk - 1) / p->z_chunk : std::max(1, std::min(p->nz, (NCU3 + cols - 1) / cols));
+  const long long cols = (long long)ntx * nty;
+  int nch = 1;
+  if (p->z_chunk > 0) {
+    nch = (p->nz + p->z_chunk - 1) / p->z_chunk;
+  } else {
+    long long best = -1;
+    for (int c = 1; c <= p->nz; ++c) {
+      const int l = (p->nz + c - 1) / c;
+      if ((p->nz + l - 1) / l != c) continue;  // same chunk length as a smaller count
+      const long long cost = (cols * c + NCU3 - 1) / NCU3 * (l + 4);
+      if (best < 0 || cost < best) {
+        best = cost;
+        nch = c;
+      }
+    }
+  }
   lz = (p->nz + nch - 1) / nch;
   nch = (p->nz + lz - 1) / lz;
-  nwg = cols * nch;
+  nwg = (int)(cols * nch);
 }
 
 template <typename real>
