@@ -551,15 +551,26 @@ def main():
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
+    # the K timed steps run as five equal segments (the last takes the remainder) with an event
+    # between them: `value` is the whole run, the segments give the p50 and spread of repeats
+    nseg = 5 if args.steps >= 5 else 1
+    seg_steps = [args.steps // nseg] * (nseg - 1) + [args.steps - (args.steps // nseg) * (nseg - 1)]
+    seg_ev = [torch.cuda.Event(enable_timing=True) for _ in range(nseg - 1)]
     t0 = time.perf_counter()
     ev0.record(stream)
-    s.step(args.steps)
+    for k, n in enumerate(seg_steps):
+        s.step(n)
+        if k < nseg - 1:
+            seg_ev[k].record(stream)
     ev1.record(stream)
     ev1.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s.sync()  # raises if the device flagged a numerical failure
     ev_ms = ev0.elapsed_time(ev1)
+    bounds = [ev0] + seg_ev + [ev1]
+    seg_mlups = sorted(w.nodes * n / (bounds[k].elapsed_time(bounds[k + 1]) * 1e-3) / 1e6
+                       for k, n in enumerate(seg_steps))
     ms_per_step = ev_ms / args.steps
     nodes = w.nodes
     mlups = nodes * args.steps / (ev_ms * 1e-3) / 1e6
@@ -607,6 +618,8 @@ def main():
                      "bytes_per_launch": bytes_per_launch, "steps_per_launch": depth,
                      "kernel_ms_per_launch_timed_region": round(ms_per_launch, 6),
                      "kernel_ms_single_step_call_p50": round(launch_p50, 6)},
+        "repeats": {"segments": nseg, "steps_each": seg_steps[0], "mlups_p50": round(seg_mlups[nseg // 2], 1),
+                    "mlups_min": round(seg_mlups[0], 1), "mlups_max": round(seg_mlups[-1], 1)},
         "wall_s": round(wall, 4),
         "fields_finite": finite,
     }
