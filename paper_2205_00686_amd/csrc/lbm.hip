@@ -112,6 +112,7 @@ struct lbm_ctx {
   bool failed = false;
   int64_t steps = 0;
   int gen = 0;           // 1 if the current state is in the B buffers
+  int hgen = 0;          // 1 if the temperature history is in ThB (it moves only on two-step launches)
   long long clock = 0;   // host mirror of the context's device clock (advanced by its own launches)
   double rho_ave = 0.0;
   double T_ref = 0.0;  // storage offset of g and the history (exact in the working precision)
@@ -127,6 +128,7 @@ struct lbm_batch {
   std::vector<int64_t> remaining;
   std::vector<int64_t> pending;  // steps enqueued since the last sync, per instance
   std::vector<int64_t> pending_launches;  // launches that advanced each instance since the last sync
+  std::vector<int64_t> pending_hmoves;    // of these, launches that moved its temperature history
   hipStream_t stream = nullptr;
   int precision = 0;
   int qg = 5;                    // thermal lattice of every member
@@ -185,6 +187,10 @@ static lbm_status fail(lbm_ctx* h, lbm_status s, const std::string& msg) {
     if (e_ != hipSuccess)                                                                  \
       return fail((h), LBM_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
+
+// Launches of a window of n steps at d steps per launch that move the temperature history to the
+// other copy: those that do two steps (a one-step launch updates it in place)
+static int64_t history_moves(int64_t n, int d) { return d == 2 ? n / 2 : 0; }
 
 template <typename real>
 static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref) {
@@ -264,6 +270,7 @@ static InstDesc<real> make_desc(lbm_ctx* h, int ty) {
   D.nty = (h->prm.ny + ty - 1) / ty;
   D.tile_begin = 0;
   D.b_base = 0;
+  D.h_base = 0;
   D.t_base = 0;
   D.t_end = std::numeric_limits<long long>::max();
   D.p = derive<real>(&h->prm, h->rho_ave, h->T_ref);
@@ -475,6 +482,7 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
   h->steps = 0;
   h->gen = 0;
+  h->hgen = 0;
   h->clock = 0;
   lbm_status s = upload_desc(h);
   if (s != LBM_OK) return s;
@@ -560,9 +568,11 @@ lbm_status lbm_step(lbm_ctx* h, int64_t n) {
   // two-step shape does one step where only one is left
   const int d = shape_def(h->prm.precision, h->shape).depth;
   if (h->prm.precision == LBM_FP64)
-    set_window_kernel<double><<<1, 64, 0, h->stream>>>((InstDesc<double>*)h->d_desc, h->clock, h->gen, h->clock + n);
+    set_window_kernel<double><<<1, 64, 0, h->stream>>>((InstDesc<double>*)h->d_desc, h->clock, h->gen, h->hgen,
+                                                       h->clock + n);
   else
-    set_window_kernel<float><<<1, 64, 0, h->stream>>>((InstDesc<float>*)h->d_desc, h->clock, h->gen, h->clock + n);
+    set_window_kernel<float><<<1, 64, 0, h->stream>>>((InstDesc<float>*)h->d_desc, h->clock, h->gen, h->hgen,
+                                                      h->clock + n);
   HIP_OR_FAIL(h, hipGetLastError());
   const int64_t launches = (n + d - 1) / d;
   const int64_t per_graph = GRAPH_STEPS / d;
@@ -584,6 +594,7 @@ lbm_status lbm_step(lbm_ctx* h, int64_t n) {
   h->clock += (long long)launches * d;
   h->steps += n;
   h->gen ^= (int)(launches & 1);
+  h->hgen ^= (int)(history_moves(n, d) & 1);
   return LBM_OK;
 }
 
@@ -649,7 +660,7 @@ static void current_buffers(lbm_ctx* h, void*& f, void*& g, void*& fo) {
 }
 
 // current temperature history (follows the buffers of f and g)
-static void* current_history(lbm_ctx* h) { return (h->gen & 1) ? h->ThB : h->ThA; }
+static void* current_history(lbm_ctx* h) { return (h->hgen & 1) ? h->ThB : h->ThA; }
 
 lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, double* T) {
   if (!h) return LBM_E_INVAL;
@@ -765,6 +776,7 @@ lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
   if (meta[0] < 0) return fail(h, LBM_E_INVAL, "corrupt state: negative step count");
   h->steps = meta[0];
   h->gen = 0;  // the state goes to the A buffers
+  h->hgen = 0;
   std::memcpy(&h->rho_ave, &meta[1], sizeof(double));
   std::memcpy(&h->T_ref, &meta[2], sizeof(double));
   void *f, *g, *fo;
@@ -915,6 +927,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   b->remaining.assign(n, 0);
   b->pending.assign(n, 0);
   b->pending_launches.assign(n, 0);
+  b->pending_hmoves.assign(n, 0);
   b->stream = (hipStream_t)hip_stream;
   b->precision = prec;
   b->qg = qg;
@@ -978,6 +991,7 @@ static void fill_table(lbm_batch* b, std::vector<InstDesc<real>>& tab, int64_t t
     // buffers as left by the context's own steps and the batched launches not yet synced
     D.t_base = b->clock;
     D.b_base = (h->gen ^ (int)(b->pending_launches[i] & 1)) & 1;
+    D.h_base = (h->hgen ^ (int)(b->pending_hmoves[i] & 1)) & 1;
     if (b->remaining[i] > 0) {
       D.tile_begin = tiles;
       D.t_end = b->clock + std::min<int64_t>(todo, b->remaining[i]);
@@ -1085,6 +1099,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
     const int64_t ran = std::min<int64_t>(todo, b->remaining[i]);
     b->pending[i] += ran;
     b->pending_launches[i] += (ran + d - 1) / d;
+    b->pending_hmoves[i] += history_moves(ran, d);
     b->remaining[i] -= ran;
   }
   return LBM_OK;
@@ -1099,8 +1114,10 @@ lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status) {
     lbm_ctx* h = b->ctx[i];
     h->steps += b->pending[i];
     h->gen ^= (int)(b->pending_launches[i] & 1);
+    h->hgen ^= (int)(b->pending_hmoves[i] & 1);
     b->pending[i] = 0;
     b->pending_launches[i] = 0;
+    b->pending_hmoves[i] = 0;
     unsigned e = 0;
     HIP_OR_FAIL(h, hipMemcpy(&e, h->d_err, sizeof(unsigned), hipMemcpyDeviceToHost));
     if (e) {

@@ -469,10 +469,10 @@ __global__ __launch_bounds__(256) void collide3_kernel(Dev3<real> p, Bufs3<real>
 // The first threads also load the ring nodes (one each).  Per column, f of one plane waits for
 // its collision in LDS (FP32; in registers in FP64, whose LDS is full) and g of two planes in
 // registers; 1/(rho c_v) and g_1..g_4 of the last four planes (the streaming destinations in x
-// and y) are staged in LDS.  In FP32 the loads of the next plane are issued one iteration ahead.  Every population of the chunk is
-// read from HBM once and written once; the ring reloads hit the L2 that neighbouring tiles share
-// (XCD-aware order).  Each node's arithmetic is that of the per-node path (the divergence sums
-// its 18 terms in another order).
+// and y) are staged in LDS.  In FP32 the loads of the next plane are issued one iteration ahead.
+// Every population of the chunk is read from HBM once and written once; the ring reloads hit the
+// L2 that neighbouring tiles share (XCD-aware order).  Each node's arithmetic is that of the
+// per-node path (the divergence sums its 18 terms in another order).
 template <typename real, int TY, bool FST>
 struct Fused3Lds {
   real psi[3][TY + 4][68];  // psi of three consecutive planes over the tile and ring of radius 2

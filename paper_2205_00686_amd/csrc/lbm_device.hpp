@@ -94,6 +94,7 @@ struct InstDesc {
   int ntx, nty;        // tiles along x and y
   int tile_begin;      // first workgroup index of this instance in the launch
   int b_base;          // 1 if the current state is in the B buffers at clock t_base
+  int h_base;          // 1 if the temperature history is in ThB at clock t_base
   long long t_base;    // clock value from which launches advance this instance
   long long t_end;     // clock value at which it stops
   DevParams<real> p;

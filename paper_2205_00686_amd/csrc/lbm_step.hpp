@@ -384,8 +384,8 @@ struct LdsState {
 // perform the same arithmetic on every node.  FROM_LDS: f and g come from `st` (second step of
 // a two-step launch) instead of the global source buffers.
 template <typename real, class S, int V, bool FROM_LDS, int QG = 5>
-__device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real, S::EYW, QG>& L, bool odd, int x0,
-                                          int y0, const LdsState<real, S>& st, unsigned& err) {
+__device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real, S::EYW, QG>& L, bool odd, bool hodd,
+                                          int x0, int y0, const LdsState<real, S>& st, unsigned& err) {
   static_assert(!FROM_LDS || QG == 5, "the two-step state in LDS holds D2Q5 thermal populations");
   constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, RING = S::RING, URING = S::URING, EYW = S::EYW;
   const int nx = D.nx, ny = D.ny;
@@ -395,8 +395,11 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   const gptr<const char> gs = (gptr<const char>)to_global<const real>(odd ? D.gB : D.gA);
   const gptr<char> fd = (gptr<char>)to_global<real>(odd ? D.fA : D.fB);
   const gptr<char> gd = (gptr<char>)to_global<real>(odd ? D.gA : D.gB);
-  const gptr<const char> Ths = (gptr<const char>)to_global<const real>(odd ? D.ThB : D.ThA);
-  const gptr<char> Thd = (gptr<char>)to_global<real>(odd ? D.ThA : D.ThB);
+  // temperature history: a step that reads only its own nodes' history (every step but the second
+  // of a two-step launch, whose first step read the ring's) updates it in place; the second step
+  // of a two-step launch writes the other copy
+  const gptr<const char> Ths = (gptr<const char>)to_global<const real>(hodd ? D.ThB : D.ThA);
+  const gptr<char> Thd = (gptr<char>)to_global<real>((hodd != FROM_LDS) ? D.ThB : D.ThA);
   const DevParams<real> p = D.p;
   constexpr bool INTERIOR = Variant<V>::INTERIOR;
   constexpr int walls = Variant<V>::WALLS ? 1 : 0;
@@ -673,8 +676,8 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
 // and streams into the state arrays over the second step's load region (HXW, HYW).  Pushes that
 // leave that region are dropped; every kept slot is written exactly once.
 template <typename real, class S, int V>
-__device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<real, S>& L, bool odd, int x0, int y0,
-                                           real (&Tn1)[S::RPT], real (&Tn2)[S::RPT], unsigned& err) {
+__device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<real, S>& L, bool odd, bool hodd, int x0,
+                                           int y0, real (&Tn1)[S::RPT], real (&Tn2)[S::RPT], unsigned& err) {
   constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, MX = S::MX, MY = S::MY, MXH = S::MXH, MYH = S::MYH;
   constexpr int MRING = MX * MY - TX * S::TY;
   constexpr int RPN = (MRING + NT - 1) / NT;
@@ -684,7 +687,7 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
   const ptrdiff_t PB = (ptrdiff_t)nx * (ptrdiff_t)ny * SZ;
   const gptr<const char> fs = (gptr<const char>)to_global<const real>(odd ? D.fB : D.fA);
   const gptr<const char> gs = (gptr<const char>)to_global<const real>(odd ? D.gB : D.gA);
-  const gptr<const char> Th = (gptr<const char>)to_global<const real>(odd ? D.ThB : D.ThA);
+  const gptr<const char> Th = (gptr<const char>)to_global<const real>(hodd ? D.ThB : D.ThA);
   const DevParams<real> p = D.p;
   constexpr bool INTERIOR = Variant<V>::INTERIOR;
   constexpr int walls = Variant<V>::WALLS ? 1 : 0;
@@ -880,6 +883,9 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
   const int bx = tile - by * D.ntx;
   const int x0 = bx * TX, y0 = by * S::TY;
   const bool odd = ((D.b_base + (t - D.t_base) / S::DEPTH) & 1) != 0;
+  // the history changes copy once per launch that does two steps (every launch of a two-step
+  // shape in the window but possibly the last, which does one step in place)
+  const bool hodd = ((D.h_base + (S::DEPTH == 2 ? (t - D.t_base) / 2 : 0)) & 1) != 0;
   unsigned err = 0u;
   // interior: the load region lies inside the grid, so no wrap, ghost row, wall or Dirichlet
   // edge is involved
@@ -892,19 +898,19 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
       real Tn1[S::RPT], Tn2[S::RPT];
       const bool interior2 =
           x0 >= S::MXH && x0 + TX + S::MXH <= D.nx && y0 >= S::MYH && y0 + S::TY + S::MYH <= D.ny;
-      if (interior2) first_step<real, S, 0>(D, L2, odd, x0, y0, Tn1, Tn2, err);
-      else with_general_variant(gv, [&](auto v) { first_step<real, S, decltype(v)::value>(D, L2, odd, x0, y0, Tn1, Tn2, err); });
+      if (interior2) first_step<real, S, 0>(D, L2, odd, hodd, x0, y0, Tn1, Tn2, err);
+      else with_general_variant(gv, [&](auto v) { first_step<real, S, decltype(v)::value>(D, L2, odd, hodd, x0, y0, Tn1, Tn2, err); });
       const LdsState<real, S> st{L2.sf, L2.sg, Tn1, Tn2};
-      if (interior) step_body<real, S, 0, true>(D, L2.m2, odd, x0, y0, st, err);
-      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, true>(D, L2.m2, odd, x0, y0, st, err); });
+      if (interior) step_body<real, S, 0, true>(D, L2.m2, odd, hodd, x0, y0, st, err);
+      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, true>(D, L2.m2, odd, hodd, x0, y0, st, err); });
     } else {
-      if (interior) step_body<real, S, 0, false>(D, L2.m2, odd, x0, y0, none, err);
-      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false>(D, L2.m2, odd, x0, y0, none, err); });
+      if (interior) step_body<real, S, 0, false>(D, L2.m2, odd, hodd, x0, y0, none, err);
+      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false>(D, L2.m2, odd, hodd, x0, y0, none, err); });
     }
   } else {
     __shared__ StepLds<real, S::EYW, QG> L;
-    if (interior) step_body<real, S, 0, false, QG>(D, L, odd, x0, y0, none, err);
-    else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false, QG>(D, L, odd, x0, y0, none, err); });
+    if (interior) step_body<real, S, 0, false, QG>(D, L, odd, hodd, x0, y0, none, err);
+    else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false, QG>(D, L, odd, hodd, x0, y0, none, err); });
   }
   // A failing simulation flags every node.  One atomic per thread, or even per wavefront, on one
   // word would serialise the launch, so a wavefront ORs its flags with ballots and sets only the
@@ -967,10 +973,11 @@ __global__ void open_top_kernel(const InstDesc<real>* __restrict__ table, const 
 }
 
 template <typename real>
-__global__ void set_window_kernel(InstDesc<real>* d, long long t_base, int b_base, long long t_end) {
+__global__ void set_window_kernel(InstDesc<real>* d, long long t_base, int b_base, int h_base, long long t_end) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     d->t_base = t_base;
     d->b_base = b_base;
+    d->h_base = h_base;
     d->t_end = t_end;
   }
 }
