@@ -551,14 +551,10 @@ __global__ __launch_bounds__(64 * TY) void fused3_kernel(Dev3<real> p, Bufs3<rea
   unsigned err = 0u;
 
   // f, g of the plane at byte offset zb for the own column and the ring node (lanes without one
-  // keep zeros).  The plane stride is made opaque to the compiler at each use, so the plane bases
-  // are recomputed in scalar registers next to their loads and stores instead of being kept live
-  // (and spilled) across the loop.
-  auto stride = [&]() {
-    size_t n = (size_t)nxy * (size_t)nz;
-    asm volatile("" : "+s"(n));
-    return n;
-  };
+  // keep zeros).  The plane stride is opaque to the compiler at each use (lbm::opaque), so the
+  // plane bases are recomputed in scalar registers next to their loads and stores instead of being
+  // kept live (and spilled) across the loop.
+  auto stride = [&]() { return lbm::opaque((size_t)nxy * (size_t)nz); };
   auto ld = [](const real* base, size_t off, uint32_t byte) -> real {
     return lbm::ldb<real>(lbm::sbase(lbm::to_global((const char*)(base + off))), byte);
   };

@@ -123,6 +123,15 @@ __device__ __forceinline__ gptr<T> sbase(gptr<T> ptr) {
   const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
   return (gptr<T>)(((unsigned long long)hi << 32) | lo);
 }
+// A uniform value the compiler must take as unknown at each use (an empty asm statement that
+// claims to change it).  Plane bases derived from an opaque plane stride are recomputed in
+// scalar registers next to their accesses instead of being hoisted and kept live (and spilled to
+// vector lanes) across the kernel.
+template <typename T>
+__device__ __forceinline__ T opaque(T v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
 template <typename real>
 __device__ __forceinline__ real ldb(gptr<const char> base, unsigned off) {
   return *(gptr<const real>)(base + off);

@@ -414,10 +414,10 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   auto wx = [&](int v) { return INTERIOR ? v : wrapi(v, nx, tiny); };
   auto wy = [&](int v) { return (INTERIOR || walls) ? v : wrapi(v, ny, tiny); };
   auto fluid_row = [&](int y) { return INTERIOR || row_kind(y, ny, walls) == 0; };
-  auto fsp = [&](int i) { return sbase(fs + i * PB); };
-  auto gsp = [&](int i) { return sbase(gs + i * PB); };
-  auto fdp = [&](int i) { return sbase(fd + i * PB); };
-  auto gdp = [&](int i) { return sbase(gd + i * PB); };
+  auto fsp = [&](int i) { return sbase(fs + i * opaque(PB)); };
+  auto gsp = [&](int i) { return sbase(gs + i * opaque(PB)); };
+  auto fdp = [&](int i) { return sbase(fd + i * opaque(PB)); };
+  auto gdp = [&](int i) { return sbase(gd + i * opaque(PB)); };
 
   // ---- phase 1: every global load of the tile is issued first (own nodes with their T
   // history, then the halo ring), so that the workgroup waits for memory once.  Own nodes keep
@@ -448,7 +448,7 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
 #pragma unroll
         for (int i = 0; i < QG; ++i) g[r][i] = ldb<real>(gsp(i), ob[r]);
         T1[r] = ldb<real>(Ths, ob[r]);
-        T2[r] = ldb<real>(sbase(Ths + PB), ob[r]);
+        T2[r] = ldb<real>(sbase(Ths + opaque(PB)), ob[r]);
       }
     } else {
 #pragma unroll
@@ -536,7 +536,7 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
     node_collide<real, QG>(p, freeze, f[r], g[r], rho, ux, uy, Fx[r], Fy[r], S2[r], dpdT[r], divu, T1[r], T2[r],
                            fs_, gs_, Tr);
     stb(Thd, o, Tr);
-    stb(sbase(Thd + PB), o, T1[r]);
+    stb(sbase(Thd + opaque(PB)), o, T1[r]);
 
     // ---- streaming.  Interior tiles: a neighbour's byte offset differs from the node's by a
     // uniform amount, folded into the plane base.  Other tiles: wrapped offsets of the eight
@@ -702,8 +702,8 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
   auto wx = [&](int v) { return INTERIOR ? v : wrapi(v, nx, tiny); };
   auto wy = [&](int v) { return (INTERIOR || walls) ? v : wrapi(v, ny, tiny); };
   auto fluid_row = [&](int y) { return INTERIOR || row_kind(y, ny, walls) == 0; };
-  auto fsp = [&](int i) { return sbase(fs + i * PB); };
-  auto gsp = [&](int i) { return sbase(gs + i * PB); };
+  auto fsp = [&](int i) { return sbase(fs + i * opaque(PB)); };
+  auto gsp = [&](int i) { return sbase(gs + i * opaque(PB)); };
   auto in_c = [](int mx, int my) { return mx >= MXH - HXW - 1 && mx < MX - (MXH - HXW - 1) && my >= MYH - HYW - 1 &&
                                           my < MY - (MYH - HYW - 1); };
   auto in_u = [](int mx, int my) { return mx >= MXH - HXW - 2 && mx < MX - (MXH - HXW - 2) && my >= MYH - HYW - 2 &&
@@ -736,7 +736,7 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
       for (int i = 0; i < 5; ++i) g[n][i] = ldb<real>(gsp(i), o);
       if (in_c(mx_[n], my_[n])) {
         T1[n] = ldb<real>(Th, o);
-        T2[n] = ldb<real>(sbase(Th + PB), o);
+        T2[n] = ldb<real>(sbase(Th + opaque(PB)), o);
       }
     }
   }
