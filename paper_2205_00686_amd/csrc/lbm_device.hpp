@@ -63,7 +63,7 @@ struct DevParams {
   real inv_Tc, inv_G;
   real s_e, s_eps, s_q, s_p;        // D2Q9 MRT rates (Eq. 5)
   real corr_e, corr_eps;            // sigma / (1/s - 1/2) of Li's forcing (Eq. 8)
-  real cv, wdot, w0h, w1h, w2h;     // thermal weights: D2Q5 (Eq. 26; w2h unused) or D2Q9 (rest, axis, diagonal)
+  real cv, wdot, w0h, w1h;          // thermal weights of the rest and axis velocities (Eq. 26)
   real vs1, vs3, vs4, inv_cs2h;     // D2Q5 MRT rates (vs1 = 1/tau_g, also the D2Q9 BGK rate); 1/chat_s^2
   real gx, gy, rho_ave;             // buoyancy
   real T_box, T_top, T_bot, hot_dT, hot_x0, inv_2s2;
@@ -72,10 +72,12 @@ struct DevParams {
   // Derived on the host: without scalar floating-point units, a constant computed in the kernel
   // costs a vector instruction per wavefront, as much as per-node arithmetic.
   real om_e, om_eps, om_q, om_p;    // 1 - s/2 of the forcing term (Eq. 5)
-  real opk, GG, two_w1h, two_w2h;   // 1 + kappa; G^2; 2 w_axis, 2 w_diagonal
+  real opk, GG, two_w1h;            // 1 + kappa; G^2; 2 w_axis
   int y_walls, thermal_box;
   unsigned flags;
   int qg;                           // velocities of the thermal lattice: 5 or 9
+  // (after the fields of the D2Q5 path, whose offsets, and so the kernel's scalar loads, they keep)
+  real w2h, two_w2h;                // D2Q9 thermal lattice: weight of a diagonal velocity, twice it
   int open_top;                     // with walls: the top is open (outflow boundary)
 };
 
