@@ -3,7 +3,7 @@ inputs, element by element, for every boundary kind, ragged grids spanning sever
 smallest grids, and the full-size static-droplet configuration.
 
 FP64 runs must agree to rounding level.  FP32 runs are held to bounds derived from the FP32 unit
-roundoff: see the tolerances next to each case (they are stated again in the design doc).
+roundoff: see the tolerances next to each case.
 """
 import numpy as np
 import pytest
