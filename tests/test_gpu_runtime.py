@@ -75,6 +75,30 @@ def test_checkpoint_resume_is_exact(lbm, sat_gpu, precision):
         assert np.array_equal(x, y)
 
 
+@pytest.mark.parametrize("n1,shape2", [(102, 6), (101, 2), (2, 6), (7, 2)])
+def test_checkpoint_resume_across_history_parities(lbm, sat_gpu, n1, shape2):
+    """The populations change buffers on every launch, the temperature history only on launches
+    that do two steps: checkpoints taken with the history in either copy, after a change between
+    the two-step shape (6) and a one-step shape (2), resume bit for bit."""
+    Tc, rl, rg = sat_gpu
+    w = boiling(Tc, rl, rg, nx=160, ny=96, hot_width=6.0, seed=7)
+    assert lbm.shape_fits(w.params, 6, lbm.LBM_FP32)
+    print(f"\n[case] checkpoint parities n1={n1} shape2={shape2}", flush=True)
+    a = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    a.set_shape(6)
+    a.step(n1)
+    a.set_shape(shape2)
+    a.step(13)
+    blob = a.save_state()
+    a.set_shape(6)
+    a.step(41)
+    b = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    b.load_state(blob)
+    b.set_shape(2)
+    b.step(41)
+    assert np.array_equal(_raw(a), _raw(b))
+
+
 def test_batch_equals_alone_bitwise(lbm, sat_gpu):
     """Instances of different sizes, parameters and step budgets in one batched launch give the
     same bits as each run alone."""
