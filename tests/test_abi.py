@@ -201,3 +201,15 @@ def test_two_step_shapes_need_a_grid_larger_than_their_halo(L):
     p = _native.LbmParams()
     L.lbm_params_default(ctypes.byref(p), 2, 64)  # invalid parameters
     assert L.lbm_shape_fits(ctypes.byref(p), 0) == 0
+
+
+def test_3d_binding_carries_path_and_chunking(L):
+    """three_d.params3_struct copies every field the parameter object names, including the step
+    path and the z chunking of the fused kernel; defaults are the fused path, automatic chunking."""
+    from paper_2205_00686_amd import _native, three_d
+    from workloads import Params3D
+    c = three_d.params3_struct(Params3D(nx=20, ny=12, nz=9))
+    assert c.path == _native.LBM3D_PATH_FUSED and c.z_chunk == 0
+    c = three_d.params3_struct(Params3D(nx=20, ny=12, nz=9, path=1, z_chunk=3), precision=_native.LBM_FP64)
+    assert (c.nx, c.ny, c.nz, c.precision, c.path, c.z_chunk) == (20, 12, 9, 1, 1, 3)
+    assert L.lbm3d_validate(ctypes.byref(c)) == 0
