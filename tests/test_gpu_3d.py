@@ -175,3 +175,23 @@ def test_3d_fused_chunking_is_bitwise_and_matches_per_node(lbm3, orc):
             assert np.array_equal(a, b), name
     for a, b in zip(out["auto"], out["per_node"]):
         assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max())
+
+
+@pytest.mark.parametrize("shape", [(3, 3, 3), (65, 9, 3), (4, 17, 5)])
+@pytest.mark.parametrize("box", [0, 1])
+def test_3d_smallest_grids_fp64(lbm3, o3, orc, shape, box):
+    """Grids at and just above the minimum size, where the radius-2 ring of a tile wraps onto the
+    tile itself (periodic images of the same nodes) and a 64-wide tile is ragged by one column."""
+    Tc, rl, rg = _sat(orc)
+    nx, ny, nz = shape
+    rng = np.random.default_rng(nx * 100 + ny * 10 + nz)
+    shp = (nz, ny, nx)
+    rho = 0.5 * (rl + rg) * (1 + 0.05 * rng.uniform(-1, 1, shp))
+    T = 0.86 * Tc * (1 + 0.01 * rng.uniform(-1, 1, shp))
+    u = [0.005 * rng.standard_normal(shp) for _ in range(3)]
+    from workloads import Workload3D
+    p = Params3D(nx=nx, ny=ny, nz=nz, thermal_box=box, T_box=0.9 * Tc)
+    w = Workload3D("small", p, rho, u[0], u[1], u[2], T, 8)
+    s, _, _, _, err = _run(lbm3, o3, w, 8, 1, f"small box={box}")
+    assert err["rho"] <= 1e-11 and err["T"] <= 1e-13 and max(err["ux"], err["uy"], err["uz"]) <= 1e-12
+    s.close()
