@@ -448,11 +448,12 @@ def run_3d_mode(args):
         ms = e0.elapsed_time(e1) / steps
         mass, _ = s.diagnostics()
         traffic = TRAFFIC3D.get((n, path, args.z_chunk))
+        achieved = w.nodes * 224 / (ms * 1e-3) / 1e9  # algorithmic GB/s (one launch per step on the fused path)
         rows.append({"grid": f"{n}^3", "path": "fused" if path == 0 else "per-node", "steps": steps,
-                     "traffic_bytes": traffic,
                      "us_per_step": round(ms * 1e3, 2),
                      "mlups": round(w.nodes / (ms * 1e-3) / 1e6, 1),
-                     "roofline_frac": round(w.nodes * 224 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
                      "mass_drift": abs(mass / float(w.rho.sum()) - 1.0)})
         print(f"[bench] 3d {rows[-1]}", file=sys.stderr, flush=True)
         s.close()
