@@ -39,7 +39,7 @@ BYTES_PER_LU = {"f32": 128, "f64": 256}  # f 9+9, g 5+5, history 2+2 values per 
 # Measured HBM bytes per launch of the fused 3-D kernel (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a
 # plain copy): (edge, path, z_chunk) -> bytes, for the kernel as profiled
 TRAFFIC3D = {(256, 0, 0): 3986283140}
-TRAFFIC = {("evaporation", 512, 512, 6): 37926069}
+TRAFFIC = {("evaporation", 512, 512, 6): 37947954}
 
 
 def build_workload(nx=512, ny=512, steps=20000, kind="evaporation"):
