@@ -195,3 +195,22 @@ def test_3d_smallest_grids_fp64(lbm3, o3, orc, shape, box):
     s, _, _, _, err = _run(lbm3, o3, w, 8, 1, f"small box={box}")
     assert err["rho"] <= 1e-11 and err["T"] <= 1e-13 and max(err["ux"], err["uy"], err["uz"]) <= 1e-12
     s.close()
+
+
+def test_3d_fused_fp32_long_marches(lbm3, o3, orc):
+    """64^3 evaporating droplet in a Dirichlet box, FP32, z chunks of 16 planes (each workgroup
+    marches 20 iterations through its chunk), 100 steps against the oracle within the FP32 bounds;
+    the result equals that of the default chunking bit for bit."""
+    Tc, rl, rg = _sat(orc)
+    w = evaporation3d(Tc, rl, rg, n=64, R=14.0, superheat=1.2)
+    w.params = w.params.replace(z_chunk=16)
+    s, _, got, exp, err = _run(lbm3, o3, w, 100, 0, "fused fp32 64^3 z_chunk=16")
+    Tmax = float(np.abs(exp[4]).max())
+    assert err["rho"] <= 2e-4 * 6.5 and err["T"] <= 2e-6 * Tmax
+    assert max(err["ux"], err["uy"], err["uz"]) <= 1e-5
+    s.close()
+    s2 = lbm3.Solver3D(w.params.replace(z_chunk=0), precision=0).init(w.rho, w.ux, w.uy, w.uz, w.T)
+    s2.step(100)
+    for a, b in zip(got, s2.fields()):
+        assert np.array_equal(a, b)
+    s2.close()
