@@ -58,19 +58,41 @@ def build_workload(nx=512, ny=512, steps=20000, kind="evaporation"):
     return evaporation(Tc, rl, rg, nx=nx, ny=ny, R=64.0 * nx / 512, superheat=1.10, steps=steps)
 
 
+def _host_cpu() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, steps):
-    """The FP64 oracle on the same workload for a bounded number of steps (host cores)."""
+    """The FP64 oracle on the same workload for a bounded number of steps, on all host cores
+    (OpenMP), then on one core for a sixteenth of the steps."""
     import oracle
 
     oracle.build(force=False)
     o = oracle.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
     o.step(2)  # warm caches
+    cores = oracle.num_threads()
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": w.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+    steps1 = max(1, steps // 16)
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        o.step(steps1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
+    return {"value": w.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{w.params.nx}x{w.params.ny} {w.name}, FP64, {steps} steps after 2 warm-up steps "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s)",
+            "single_core": {"value": w.nodes * steps1 / dt1 / 1e6, "steps": steps1, "seconds": round(dt1, 2)},
+            "host": {"cpu": _host_cpu(), "logical_cpus": os.cpu_count()}}
 
 
 def shape_text(lbm, precision, k):

@@ -108,6 +108,7 @@ def lib():
         L.orc_get_post.argtypes = [vp, dp]; L.orc_get_post.restype = None
         L.orc_steps.argtypes = [vp]; L.orc_steps.restype = ctypes.c_long
         L.orc_num_threads.argtypes = []; L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]; L.orc_set_threads.restype = None
         L.orc_matrices.argtypes = [vp, dp, dp, dp, dp]; L.orc_matrices.restype = None
         L.orc_relaxation.argtypes = [vp, dp, dp]; L.orc_relaxation.restype = None
         _lib = L
@@ -270,6 +271,11 @@ def num_threads() -> int:
     return int(lib().orc_num_threads())
 
 
+def set_threads(n: int) -> None:
+    """Threads for the oracle's following grid loops (for timing it on one core)."""
+    lib().orc_set_threads(int(n))
+
+
 def run(prm, rho, ux, uy, T, steps: int):
     """Convenience: initialise, run ``steps`` steps, return (rho, ux, uy, T)."""
     o = Oracle(prm).init(rho, ux, uy, T)
@@ -277,5 +283,5 @@ def run(prm, rho, ux, uy, T, steps: int):
     return o.fields()
 
 
-__all__ = ["build", "num_threads", "Tc", "eos_p", "eos_dpdT", "psi", "maxwell", "feq", "meq", "force_moments",
+__all__ = ["build", "num_threads", "set_threads", "Tc", "eos_p", "eos_dpdT", "psi", "maxwell", "feq", "meq", "force_moments",
            "Oracle", "OracleError", "run", "FREEZE_FLOW", "NO_S", "BGK"]

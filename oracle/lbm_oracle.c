@@ -771,6 +771,14 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+/* threads for the following grid loops (n >= 1; without OpenMP a no-op) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 long orc_steps(const orc_state* s) { return s->steps; }
 
 /* The matrices in use (for the identity checks of the tests). */
