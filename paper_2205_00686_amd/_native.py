@@ -25,7 +25,8 @@ EXPORTS = (
     "lbm_last_error", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
     "lbm_batch_remaining", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_sync", "lbm_batch_destroy",
     "lbm3d_params_default", "lbm3d_validate", "lbm3d_footprint_bytes", "lbm3d_create", "lbm3d_init", "lbm3d_step",
-    "lbm3d_sync", "lbm3d_read_fields", "lbm3d_diagnostics", "lbm3d_steps_done", "lbm3d_destroy",
+    "lbm3d_sync", "lbm3d_read_fields", "lbm3d_diagnostics", "lbm3d_steps_done", "lbm3d_state_bytes",
+    "lbm3d_save_state", "lbm3d_load_state", "lbm3d_destroy",
 )
 
 
@@ -129,6 +130,9 @@ def lib():
         "lbm3d_read_fields": ([vp, dp, dp, dp, dp, dp], st),
         "lbm3d_diagnostics": ([vp, dp, dp], st),
         "lbm3d_steps_done": ([vp], i64),
+        "lbm3d_state_bytes": ([vp], sz),
+        "lbm3d_save_state": ([vp, vp, sz], st),
+        "lbm3d_load_state": ([vp, vp, sz], st),
         "lbm3d_destroy": ([vp], st),
     }
     for name, (args, res) in sig.items():

@@ -1211,6 +1211,46 @@ lbm_status lbm3d_diagnostics(lbm3d_ctx* h, double* mass, double* energy) {
 
 int64_t lbm3d_steps_done(const lbm3d_ctx* h) { return h ? h->steps : -1; }
 
+size_t lbm3d_state_bytes(const lbm3d_ctx* h) { return h ? 28 * h->N * h->rsz + 2 * sizeof(int64_t) : 0; }
+
+lbm_status lbm3d_save_state(lbm3d_ctx* h, void* host, size_t bytes) {
+  if (!h || !host) return LBM_E_INVAL;
+  if (!h->initialised) return fail3(h, LBM_E_STATE, "lbm3d_save_state before lbm3d_init");
+  if (bytes < lbm3d_state_bytes(h)) return fail3(h, LBM_E_INVAL, "host buffer smaller than lbm3d_state_bytes");
+  char* q = (char*)host;
+  const size_t N = h->N, r = h->rsz;
+  HIP3(h, hipMemcpyAsync(q, h->gen ? h->fB : h->fA, 19 * N * r, hipMemcpyDeviceToHost, h->stream));
+  HIP3(h, hipMemcpyAsync(q + 19 * N * r, h->gen ? h->gB : h->gA, 7 * N * r, hipMemcpyDeviceToHost, h->stream));
+  HIP3(h, hipMemcpyAsync(q + 26 * N * r, h->Th, 2 * N * r, hipMemcpyDeviceToHost, h->stream));
+  HIP3(h, hipStreamSynchronize(h->stream));
+  int64_t meta[2] = {h->steps, 0};
+  std::memcpy(&meta[1], &h->T_ref, sizeof(double));
+  std::memcpy(q + 28 * N * r, meta, sizeof(meta));
+  return check3(h);
+}
+
+lbm_status lbm3d_load_state(lbm3d_ctx* h, const void* host, size_t bytes) {
+  if (!h || !host) return LBM_E_INVAL;
+  if (bytes < lbm3d_state_bytes(h)) return fail3(h, LBM_E_INVAL, "host buffer smaller than lbm3d_state_bytes");
+  const char* q = (const char*)host;
+  const size_t N = h->N, r = h->rsz;
+  int64_t meta[2];
+  std::memcpy(meta, q + 28 * N * r, sizeof(meta));
+  if (meta[0] < 0) return fail3(h, LBM_E_INVAL, "corrupt state: negative step count");
+  h->steps = meta[0];
+  std::memcpy(&h->T_ref, &meta[1], sizeof(double));
+  h->gen = 0;  // the state goes to the A buffers
+  HIP3(h, hipMemcpyAsync(h->fA, q, 19 * N * r, hipMemcpyHostToDevice, h->stream));
+  HIP3(h, hipMemcpyAsync(h->gA, q + 19 * N * r, 7 * N * r, hipMemcpyHostToDevice, h->stream));
+  HIP3(h, hipMemcpyAsync(h->Th, q + 26 * N * r, 2 * N * r, hipMemcpyHostToDevice, h->stream));
+  const unsigned zero = 0;
+  HIP3(h, hipMemcpyAsync(h->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+  HIP3(h, hipStreamSynchronize(h->stream));
+  h->initialised = true;
+  h->failed = false;
+  return LBM_OK;
+}
+
 lbm_status lbm3d_destroy(lbm3d_ctx* h) {
   if (!h) return LBM_E_INVAL;
   delete h;

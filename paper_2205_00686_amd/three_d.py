@@ -82,6 +82,20 @@ class Solver3D:
         self._status(_native.lib().lbm3d_diagnostics(self.handle, ctypes.byref(m), ctypes.byref(e)))
         return m.value, e.value
 
+    def state_bytes(self) -> int:
+        return int(_native.lib().lbm3d_state_bytes(self.handle))
+
+    def save_state(self) -> bytes:
+        """Raw state (f, g, history in the working precision, step count, T_ref) as bytes."""
+        buf = ctypes.create_string_buffer(self.state_bytes())
+        self._status(_native.lib().lbm3d_save_state(self.handle, buf, len(buf)))
+        return buf.raw
+
+    def load_state(self, data: bytes):
+        buf = ctypes.create_string_buffer(data, len(data))
+        self._status(_native.lib().lbm3d_load_state(self.handle, buf, len(data)))
+        return self
+
     def _status(self, s):
         if s != 0:
             L = _native.lib()
