@@ -11,7 +11,9 @@ model on D3Q7; the readings are listed in oracle/lbm3d_oracle.c):
     solution with D = lambda/(rho c_v), lambda = (wdot/3)(tau_g - 1/2);
   * a flat interface across a thin periodic box settles at the Maxwell densities with the sigma
     of the two-dimensional model (the per-component reading of the sigma term);
-  * two spherical droplets give the same surface tension from the Laplace law dp = 2 gamma / R.
+  * two spherical droplets give the same surface tension from the Laplace law dp = 2 gamma / R;
+  * a shear wave decays at nu k^2 with nu = (1/s_nu - 1/2)/3, in each of the three orientations
+    that put it on one of the off-diagonal stress moments (xz, xy, yz), at two viscosities.
 """
 import numpy as np
 import pytest
@@ -160,3 +162,30 @@ def test_laplace_law_two_droplets(o3, sat):
         gam.append((p_in - p_out) * Re / 2)
     assert gam[0] > 0 and gam[1] > 0
     assert gam[0] == pytest.approx(gam[1], rel=0.10)
+
+
+@pytest.mark.parametrize("nu", [0.1, 1.0 / 30.0])
+@pytest.mark.parametrize("comp,axis", [("ux", "z"), ("uy", "x"), ("uz", "y")])
+def test_shear_wave_decays_at_the_viscous_rate(o3, sat, nu, comp, axis):
+    """u_comp = U sin(k axis) in a uniform liquid (psi uniform, so no interaction force; div u = 0,
+    so the temperature stays uniform) decays as exp(-nu k^2 t), nu = (1/s_nu - 1/2)/3: the decay
+    rate between steps 100 and 300 is within 0.5 % of nu k^2 (the finite-k correction is about
+    k^2/12 of it).  A stress moment relaxed at another rate would be off by tens of percent."""
+    T0, rl = sat[1], sat[2]
+    n, U = 32, 1e-3
+    k = 2 * np.pi / n
+    p = Params3D(nx=n if axis == "x" else 4, ny=n if axis == "y" else 4, nz=n if axis == "z" else 4, nu=nu)
+    shp = (p.nz, p.ny, p.nx)
+    z, y, x = np.meshgrid(np.arange(p.nz), np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    mode = np.sin(k * {"x": x, "y": y, "z": z}[axis])
+    u = {"ux": 0 * mode, "uy": 0 * mode, "uz": 0 * mode}
+    u[comp] = U * mode
+    o = o3.Oracle3D(p).init(np.full(shp, rl), u["ux"], u["uy"], u["uz"], np.full(shp, T0))
+    amp = []
+    for _ in range(3):
+        o.step(100)
+        f = o.fields()
+        uc = {"ux": f[1], "uy": f[2], "uz": f[3]}[comp]
+        amp.append(float((uc * mode).sum() / (mode * mode).sum()))
+    rate = -np.log(amp[2] / amp[0]) / 200.0
+    assert rate == pytest.approx(nu * k * k, rel=5e-3)
