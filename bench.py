@@ -529,6 +529,8 @@ def main():
     ap.add_argument("--stop-fraction", type=float, default=0.1, help="heated: stop when this much liquid is left")
     ap.add_argument("--check-every", type=int, default=250)
     ap.add_argument("--z-chunk", type=int, default=0, help="3d: z planes per workgroup of the fused kernel (0: auto)")
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32",
+                    help="plain mode: working precision of the populations (FP64 moves 256 B per node update)")
     ap.add_argument("--grids3d", default="128,256", help="3d: edge lengths of the cubic grids")
     ap.add_argument("--paths3d", default="fused,per-node", help="3d: step paths to time")
     ap.add_argument("--instances", type=int, default=64)
@@ -588,9 +590,11 @@ def main():
 
     torch.cuda.set_device(0)
     w = build_workload(args.nx, args.ny, args.steps, args.workload)
-    s = lbm.Solver(w.params, precision=lbm.LBM_FP32).init(w.rho, w.ux, w.uy, w.T)
+    prec = lbm.LBM_FP64 if args.precision == "fp64" else lbm.LBM_FP32
+    PREC = args.precision.upper()
+    s = lbm.Solver(w.params, precision=prec).init(w.rho, w.ux, w.uy, w.T)
     stream = s.stream
-    print(f"[bench] {args.nx}x{args.ny} {args.workload} FP32, warmup {args.warmup}, steps {args.steps}",
+    print(f"[bench] {args.nx}x{args.ny} {args.workload} {PREC}, warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
 
     if args.calibration_copy_mib > 0:
@@ -641,8 +645,8 @@ def main():
     per_launch_ms = sorted(a.elapsed_time(b) for a, b in evs)
     launch_p50 = per_launch_ms[len(per_launch_ms) // 2]
 
-    dtype = "f32"
-    depth = lbm.shapes(lbm.LBM_FP32)[s.shape][3]  # time steps per launch of the step kernel
+    dtype = "f64" if prec == lbm.LBM_FP64 else "f32"
+    depth = lbm.shapes(prec)[s.shape][3]  # time steps per launch of the step kernel
     bytes_per_launch = BYTES_PER_LU[dtype] * nodes * depth
     ms_per_launch = ms_per_step * depth
     achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
@@ -662,15 +666,16 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": f"synthetic (seeded initial fields of the paper's {args.workload} problem)",
-        "config": {"workload": (f"droplet evaporation in open space, {args.nx}x{args.ny}, FP32 populations, "
+        "config": {"workload": (f"droplet evaporation in open space, {args.nx}x{args.ny}, {PREC} populations, "
                                 f"R={64 * args.nx // 512}, edges at 1.1 T_sat") if args.workload == "evaporation" else
-                               (f"nucleate boiling on a heated wall, {args.nx}x{args.ny}, FP32 populations, walls, "
+                               (f"nucleate boiling on a heated wall, {args.nx}x{args.ny}, {PREC} populations, walls, "
                                 f"hot spot width 32 dT 0.2 Tc, g 2e-5, pool fill {w.meta['fill']:.3f} (head limit)"),
-                   "nx": args.nx, "ny": args.ny, "precision": "fp32", "kernel": "fused D2Q9+D2Q5 step",
-                   "tile_shape": shape_text(lbm, lbm.LBM_FP32, s.shape), "tile_shape_ms_per_step": tune,
+                   "nx": args.nx, "ny": args.ny, "precision": args.precision, "kernel": "fused D2Q9+D2Q5 step",
+                   "tile_shape": shape_text(lbm, prec, s.shape), "tile_shape_ms_per_step": tune,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": TRAFFIC.get((args.workload, args.nx, args.ny, s.shape)),
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": TRAFFIC.get((args.workload, args.nx, args.ny, s.shape)) if dtype == "f32" else None,
                      "bytes_per_launch": bytes_per_launch, "steps_per_launch": depth,
                      "kernel_ms_per_launch_timed_region": round(ms_per_launch, 6),
                      "kernel_ms_single_step_call_p50": round(launch_p50, 6)},
