@@ -237,3 +237,35 @@ def test_3d_checkpoint_resume_is_exact(lbm3, orc, precision, path):
         assert np.array_equal(x, y)
     a.close()
     b.close()
+
+
+def test_3d_fused_shear_wave_at_full_size(lbm3, orc):
+    """At the benchmark's size (256^3, FP32, default z chunking) a property fixed by the model:
+    u_x = U sin(k z) in a uniform liquid decays as exp(-nu k^2 t), nu = (1/s_nu - 1/2)/3; the rate
+    between steps 100 and 500 within 1 % (k = 2 pi / 64)."""
+    Tc, rl, rg = _sat(orc)
+    n, U = 256, 1e-3
+    k = 2 * np.pi / 64
+    p = Params3D(nx=n, ny=n, nz=n)
+    print(f"\n[case] 3d shear wave {n}^3 fp32", flush=True)
+    zz = np.arange(n, dtype=float)
+    mode_z = np.sin(k * zz)
+    shp = (n, n, n)
+    ux = np.broadcast_to((U * mode_z)[:, None, None], shp)
+    zero = np.zeros(shp)
+    s = lbm3.Solver3D(p, precision=0).init(np.full(shp, rl), ux, zero, zero, np.full(shp, 0.86 * Tc))
+
+    def amplitude():
+        f = s.fields()
+        prof = f[1].mean(axis=(1, 2))  # u_x averaged over each z plane
+        return float((prof * mode_z).sum() / (mode_z * mode_z).sum())
+
+    s.step(100)
+    a0 = amplitude()
+    s.step(400)
+    a1 = amplitude()
+    rate = -np.log(a1 / a0) / 400.0
+    nu = p.nu
+    print(f"   rate {rate:.6e} against nu k^2 = {nu * k * k:.6e}", flush=True)
+    assert rate == pytest.approx(nu * k * k, rel=1e-2)
+    s.close()
