@@ -38,8 +38,11 @@
  *   R-DIR  Dirichlet temperature "by halfway bounce-back" is the anti-bounce-back rule
  *         g_i(y,t+1) upstream term = -g*_ibar(y,t) + 2 what_i T_w, blended like any other
  *         upstream population.
- *   R-AVE  rho_ave of the buoyancy force is the mean of the initial density (mass is
- *         conserved on the closed and periodic domains used here), unless given.
+ *   R-AVE  rho_ave of the buoyancy force F_b = (rho - rho_ave) g (Section 4.3) is the mean
+ *         density over the whole domain at the time level of the step: it is recomputed from the
+ *         density field of time t at every step (a fixed-order FP64 sum), so that the buoyancy
+ *         adds no net force to the domain also when mass leaves or enters through an open top.
+ *         A finite rho_ave given in the parameters is used as a constant instead.
  *   R-Q9   The D2Q9 thermal lattice the paper compares against (Sections 1 and 3.1): the BGK
  *         equation of Eq. (21) with the linear equilibrium what_i T of Eq. (22) on the D2Q9
  *         velocities, what_i = the D2Q9 weights (chat_s^2 = 1/3), G_i and S_i of Eqs. (23)-(24)
@@ -74,7 +77,7 @@ typedef struct {
   double a, b, R, acentric, G;  /* Peng-Robinson EOS (Eq. 10) and interaction strength (Eq. 9) */
   double nu, s_e, s_eps, s_q, sigma; /* D2Q9 MRT rates (Eq. 5) and Li's sigma (Eq. 8) */
   double lambda, cv, wdot, vs3, vs4; /* conductivity, c_v, D2Q5 weight parameter, varsigma_3,4 */
-  double gx, gy, rho_ave;       /* body-force acceleration and rho_ave of F_b (NaN: initial mean) */
+  double gx, gy, rho_ave;       /* body-force acceleration and rho_ave of F_b (NaN: current mean, R-AVE) */
   int32_t y_walls;              /* 0: periodic in y; 1: no-slip walls at y=-1/2 and y=ny-1/2 */
   int32_t thermal_box;          /* 1: Dirichlet T = T_box on all four edges (flow periodic) */
   double T_box, T_top, T_bot, hot_dT, hot_x0, hot_sigma;
@@ -449,6 +452,17 @@ static int compute_macro(orc_state* s) {
       s->dpdT[k] = orc_eos_dpdT(p, r, T);
     }
   if (err) return err;
+  /* rho_ave of the buoyancy force: the mean density of the domain at time t (R-AVE), summed
+     row by row in a fixed order */
+  if (isnan(p->rho_ave)) {
+    double total = 0.0;
+    for (int y = 0; y < ny; ++y) {
+      double row = 0.0;
+      for (int x = 0; x < nx; ++x) row += s->rho[idx(s, x, y)];
+      total += row;
+    }
+    s->rho_ave = total / (double)n;
+  }
   if (p->y_walls) {
     /* Eq. (54): rho_ghost(x) = rho(x, 2nd layer) + tan(pi/2 - theta) |rho(x+1, 1st) - rho(x-1, 1st)| */
     double tb = tan(M_PI / 2.0 - p->theta_bot_deg * M_PI / 180.0);

@@ -90,3 +90,31 @@ def test_open_top_dirichlet_temperature_conduction(orc, sat):
     T = o.fields()[3]
     y = np.arange(ny)[:, None]
     assert np.allclose(T, Tb + (Tt - Tb) * (y + 0.5) / ny, rtol=0, atol=1e-12)
+
+
+def test_open_top_buoyancy_follows_the_current_mean_density(orc, sat):
+    """Section 4.3 takes rho_ave of F_b = (rho - rho_ave) g as the mean density of the whole
+    domain.  Under an open top mass leaves, so that mean moves: at every step the oracle's rho_ave
+    must equal the mean of the density field it reads out at that step, and the buoyancy then adds
+    no net force to the domain (sum of (rho - rho_ave) g = 0 to rounding), although the mass has
+    changed by far more than rounding (so a rho_ave frozen at its initial value would leave a net
+    force of (M(t) - M(0)) g, checked below to be large)."""
+    from workloads import boiling
+    Tc, T0, rl, rg, _ = sat
+    w = boiling(Tc, rl, rg, nx=64, ny=48, hot_width=6.0, dT_rel=0.2, gravity=1e-4, seed=4, fill=0.6, open_top=1)
+    o = orc.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
+    g = abs(w.params.gy)
+    m0 = float(w.rho.sum())
+    worst = 0.0
+    for _ in range(40):
+        o.step(10)
+        rho = o.fields()[0]
+        mean = float(rho.sum()) / rho.size
+        assert o.rho_ave == pytest.approx(mean, rel=1e-14)
+        worst = max(worst, abs(float((rho - o.rho_ave).sum())) * g)
+    drained = abs(float(rho.sum()) - m0)
+    print(f"mass change {drained / m0:.2e} (relative); net buoyancy with the current mean {worst:.2e}, "
+          f"with the initial mean {drained * g:.2e}")
+    assert drained > 1e-4 * m0
+    assert worst <= 1e-13 * m0 * g
+    assert drained * g > 1e6 * worst
