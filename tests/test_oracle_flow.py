@@ -6,8 +6,9 @@
   * body-force-driven Poiseuille flow between halfway bounce-back walls is exact (to rounding)
     with the MRT magic combination (1/s_p - 1/2)(1/s_q - 1/2) = 3/16;
   * a flat interface relaxes to the Maxwell coexistence densities with the tuned sigma (Eq. 8);
-  * droplets obey the Laplace law (pressure jump linear in 1/R, no offset);
-  * a droplet in a hot box evaporates following the D^2 law (Eq. 55).
+  * droplets obey the Laplace law (pressure jump linear in 1/R, one surface tension for two radius
+    ranges, a small finite-size offset that shrinks with the radius);
+  * a droplet in vapour at the paper's T_g = 1.0 Tc evaporates following the D^2 law (Eq. 55).
 """
 import numpy as np
 import pytest
@@ -92,16 +93,14 @@ def _equivalent_radius(rho, rl, rg):
     return np.sqrt(np.clip((rho - rg) / (rl - rg), 0, 1).sum() / np.pi)
 
 
-@pytest.mark.slow
-def test_laplace_law(orc, sat):
-    """Isothermal droplets of four radii: p_in - p_out = gamma / R (linear in 1/R, small offset)."""
-    Tc, T0, rl, rg, _ = sat
-    n = 80
+def _laplace_fit(orc, T0, rl, rg, Tc, n, radii, steps):
+    """Isothermal droplets of the given radii on an n x n periodic box: fitted (gamma, intercept, R^2)
+    of p_in - p_out against 1/R, and the pressure jumps."""
     inv_r, dp = [], []
-    for R in (12.0, 15.0, 18.0, 21.0):
+    for R in radii:
         w = droplet(Tc, rl, rg, nx=n, ny=n, R=R, flags=FREEZE_THERMAL)
         o = orc.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
-        o.step(8000)  # the slowest acoustic mode of the largest droplet has decayed by then
+        o.step(steps)  # the slowest acoustic mode of the largest droplet has decayed by then
         rho = o.fields()[0]
         c = n // 2
         p_in = orc.eos_p(w.params, rho[c - 2:c + 3, c - 2:c + 3].mean(), T0)
@@ -112,36 +111,61 @@ def test_laplace_law(orc, sat):
     slope, icpt = np.polyfit(inv_r, dp, 1)
     fit = slope * inv_r + icpt
     r2 = 1 - ((dp - fit) ** 2).sum() / ((dp - dp.mean()) ** 2).sum()
-    assert slope > 0
-    assert r2 >= 0.999
-    assert abs(icpt) <= 0.1 * dp.mean()  # finite interface width leaves a small offset
+    return slope, icpt, r2, dp
+
+
+@pytest.mark.slow
+def test_laplace_law(orc, sat):
+    """Isothermal droplets: p_in - p_out = gamma / R.  Two independent sets, R = 12..21 on an 80^2
+    box and R = 16..28 on a 112^2 box: each is linear in 1/R (R^2 >= 0.999), both give the same
+    surface tension within 0.5 % (measured 0.05 %), and the small offset of the line (a finite-size
+    effect of the diffuse interface, measured -4.2 % and -3.7 % of the jump at the smallest radius
+    of each set) shrinks as the droplets grow.  A wrong force, ghost-free stencil or collision
+    term would change gamma with the radius range or bend the line."""
+    Tc, T0, rl, rg, _ = sat
+    g1, b1, r2a, dp1 = _laplace_fit(orc, T0, rl, rg, Tc, 80, (12.0, 15.0, 18.0, 21.0), 8000)
+    g2, b2, r2b, dp2 = _laplace_fit(orc, T0, rl, rg, Tc, 112, (16.0, 20.0, 24.0, 28.0), 8000)
+    print(f"gamma {g1:.5e} / {g2:.5e}; offsets {b1 / dp1[0]:.4f} / {b2 / dp2[0]:.4f} of the first jump; "
+          f"R^2 {r2a:.6f} / {r2b:.6f}")
+    assert g1 > 0 and g2 > 0
+    assert r2a >= 0.999 and r2b >= 0.999
+    assert g1 == pytest.approx(g2, rel=5e-3)
+    assert abs(b1) <= 0.07 * dp1[0] and abs(b2) <= 0.05 * dp2[0]
+    assert abs(b2) < abs(b1)
 
 
 @pytest.mark.slow
 def test_d2_law_evaporation(orc, sat):
-    """Droplet at T_sat in vapour at 1.4 T_c (box edges held there, lambda = 1): the area
-    fraction (D/D0)^2 of nodes above rho_mid = (rho_l+rho_g)/2 (Section 3.3) falls linearly."""
+    """The D^2-law test of Section 4.1 with the paper's values (saturated droplet at 0.86 Tc in
+    vapour and box edges at T_g = 1.0 Tc, lambda = 1/3, nu = 0.1, c_v = 5), scaled from D_0 = 60 on
+    200^2 to D_0 = 20 on 64^2 (same box-to-droplet ratio; the evaporation time scales with D_0^2):
+    the droplet area, measured as the liquid excess over the far-field vapour
+    sum clip((rho - rho_v)/(rho_l - rho_v), 0, 1) with rho_v the median density, falls linearly in
+    time (Eq. 55, (D/D_0)^2 = 1 - K t / D_0^2) while it goes from 0.9 to 0.2 of its start: R^2 >= 0.995
+    (measured 0.9971)."""
     Tc, T0, rl, rg, _ = sat
     from workloads import evaporation
-    w = evaporation(Tc, rl, rg, nx=96, ny=96, R=14.0, superheat=1.4 / 0.86, lambda_=1.0, hot_vapour=True)
+    w = evaporation(Tc, rl, rg, nx=64, ny=64, R=10.0, superheat=1.0 / 0.86, hot_vapour=True)
     o = orc.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
-    rmid = 0.5 * (rl + rg)
-    A0 = (w.rho > rmid).sum()
+    A0 = np.clip((w.rho - rg) / (rl - rg), 0, 1).sum()
     t, a = [], []
-    while o.steps < 20000:
+    while o.steps < 80000:
         o.step(250)
+        rho = o.fields()[0]
+        rv = float(np.median(rho))
         t.append(o.steps)
-        a.append((o.fields()[0] > rmid).sum() / A0)
+        a.append(np.clip((rho - rv) / (rl - rv), 0, 1).sum() / A0)
         if a[-1] < 0.15:
             break
     t, a = np.array(t), np.array(a)
     sel = (a <= 0.9) & (a >= 0.2)
-    assert sel.sum() >= 10, a
+    assert sel.sum() >= 100, a
     slope, icpt = np.polyfit(t[sel], a[sel], 1)
     fit = slope * t[sel] + icpt
     r2 = 1 - ((a[sel] - fit) ** 2).sum() / ((a[sel] - a[sel].mean()) ** 2).sum()
+    print(f"D^2 law: slope {slope:.4e} per step, R^2 {r2:.5f} over {sel.sum()} points")
     assert slope < 0
-    assert r2 >= 0.99
+    assert r2 >= 0.995
 
 
 @pytest.mark.parametrize("theta", [60.0, 90.0, 120.0])
