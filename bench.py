@@ -1,23 +1,28 @@
 """Benchmark of the fused thermal LBM step on one MI355X.
 
-Workload: droplet evaporation in open space -- 512 x 512 grid, FP32 populations, droplet of
-radius 64 at the Maxwell densities of T_sat = 0.86 Tc in saturated vapour, box edges held at
-1.1 T_sat, initial T uniform at T_sat, periodic flow.  One benchmark step is one time step of the
+Headline workload: the nucleate-boiling pool of the paper's Section 4.3 set-up at 1024 x 2048, FP32
+populations: walls at the bottom (contact angle 75, Gaussian hot spot of width 32 and 0.2 Tc) and
+top (90), gravity 2e-5, saturated liquid at 0.86 Tc with 1e-3 density noise (seed 1).  The pool is
+filled to the head limit of the closed box: at the stated fill 0.5 the vapour column above it is
+compressed past its spinodal within about 1500 steps.  One benchmark step is one time step of the
 whole coupled D2Q9 + D2Q5 update over the grid (fused kernels, one or two steps per launch as the
 autotuned tile shape has it).
 
-Prints one JSON line: MLUPS over the timed steps, the roofline of the step kernel (algorithmic
-128 bytes per node update in FP32 divided by the kernel's average duration from HIP events on
-the library's stream), and the FP64 CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line: MLUPS of exactly K steps in one call, the roofline of the step kernel
+(algorithmic 128 bytes per node update in FP32 over the kernel's average launch duration from HIP
+events on the library's stream), the batched gravity sweep against plain launches, a served request
+stream against FIFO service (p50/p99 latency), and the FP64 CPU oracle timed on a bounded sample of
+the same workload.
 
-  python bench.py [--gpus 1] [--steps 20000] [--warmup 500] [--no-cpu-baseline]
-  python bench.py --mode batch [--instances 64 --steps 2000]     batched gravity sweep vs plain
+  python bench.py [--gpus 1] [--steps 2000] [--warmup 100] [--no-cpu-baseline] [--no-batched] [--no-served]
+  python bench.py --workload evaporation --nx 512 --ny 512       the droplet-evaporation workload instead
+  python bench.py --mode batch [--instances 64 --steps 10000]    batched gravity sweep vs plain
   python bench.py --mode serve [--requests 256 --rate 20]        continuous batching vs FIFO
   python bench.py --mode fritz [--gravities 1e-5,...,6e-5]       bubble departure diameter vs gravity
   python bench.py --mode lattice                                 thermal lattice: D2Q5 MRT / BGK vs D2Q9
   python bench.py --mode heated                                  droplet evaporation on a heated surface
   python bench.py --mode 3d                                      three-dimensional extension (D3Q19 + D3Q7)
-  python bench.py --mode ceiling                                 device copies of 64 MiB to 4 GiB (HBM ceiling)
+  python bench.py --mode ceiling                                 HBM copy ceiling (hand-written copy kernel)
 """
 from __future__ import annotations
 
@@ -33,13 +38,13 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (D2Q9+D2Q5 node updates/s) & % HBM roofline; batched vs plain; p50/p99"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = {"f32": 128, "f64": 256}  # f 9+9, g 5+5, history 2+2 values per node update
-# HBM bytes per launch of the step kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes,
-# scaled by the same counters read for a plain copy of known size (profiles/); keyed by grid size
-# and tile shape, None where no measurement of the current kernel exists
 # Measured HBM bytes per launch of the fused 3-D kernel (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a
 # plain copy): (edge, path, z_chunk) -> bytes, for the kernel as profiled
 TRAFFIC3D = {(256, 0, 0): 3986283140}
-TRAFFIC = {("evaporation", 512, 512, 6): 37947954}
+# HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by the
+# same counters read for a plain copy of known size (profiles/): (workload, nx, ny, shape, dtype) ->
+# bytes and the digest of the kernel sources profiled (reported only while the sources match)
+TRAFFIC = {}
 
 
 def build_workload(nx=512, ny=512, steps=20000, kind="evaporation"):
@@ -448,10 +453,7 @@ def run_3d_mode(args):
     rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
     rows = []
     if args.calibration_copy_mib > 0:
-        src = torch.ones(args.calibration_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
-        torch.empty_like(src).copy_(src)
-        torch.cuda.synchronize()
-        del src
+        calibration_copy(lbm, args.calibration_copy_mib)
     grids = [int(v) for v in args.grids3d.split(",")]
     paths = [{"fused": 0, "per-node": 1}[v] for v in args.paths3d.split(",")]
     for path, n in [(pa, g) for pa in paths for g in grids]:
@@ -487,33 +489,278 @@ def run_3d_mode(args):
 
 
 def run_ceiling_mode(args):
-    """Practical HBM ceiling: device-to-device copies (torch's vectorised copy kernel) of 64 MiB to
-    4 GiB, each counted as bytes read plus bytes written.  The sizes up to 128 MiB fit the 256 MB
-    Infinity Cache with their destination; the larger ones stream from HBM."""
+    """Practical HBM ceiling: device-to-device copies of 64 MiB to 4 GiB with the library's
+    streaming copy kernel (16-byte lanes, lbm_device_copy) and, for comparison, torch's copy, each
+    counted as bytes read plus bytes written.  The sizes up to 128 MiB fit the 256 MB Infinity
+    Cache with their destination; the larger ones stream from HBM."""
     import torch
 
+    import paper_2205_00686_amd as lbm
+
     rows = []
+    stream = torch.cuda.current_stream()
     for mib in (64, 128, 256, 1024, 4096):
         n = mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        reps = max(5, 4096 // mib)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            dst.copy_(src)
-        e1.record()
-        e1.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        rows.append({"copy_mib": mib, "ms": round(ms, 4), "tb_per_s": round(2 * n * 4 / (ms * 1e-3) / 1e12, 3)})
+        row = {"copy_mib": mib}
+        for name, fn in (("hip_copy16", lambda: lbm.device_copy(src, dst, stream)), ("torch_copy", lambda: dst.copy_(src))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            reps = max(5, 4096 // mib)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            row[name] = {"ms": round(ms, 4), "tb_per_s": round(2 * n * 4 / (ms * 1e-3) / 1e12, 3)}
+        assert torch.equal(src, dst)
+        rows.append(row)
         print(f"[bench] ceiling {rows[-1]}", file=sys.stderr, flush=True)
         del src, dst
         torch.cuda.empty_cache()
     print(json.dumps({"mode": "HBM copy ceiling", "unit": "TB/s", "peak_tb_per_s": HBM_PEAK_GBS / 1000, "runs": rows}),
           flush=True)
+
+
+def calibration_copy(lbm, mib):
+    """One copy of `mib` MiB with the library's streaming copy kernel: a kernel of known traffic
+    (mib MiB read, mib MiB written) whose byte counters calibrate those of a profile."""
+    import torch
+    src = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    lbm.device_copy(src, dst)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def _kernel_source_sha() -> str:
+    """Digest of the step kernel's sources: a profile's traffic figure applies to this build only."""
+    import hashlib
+    h = hashlib.sha1()
+    for name in ("lbm_step.hpp", "lbm_device.hpp"):
+        with open(os.path.join(ROOT, "paper_2205_00686_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _timed_steps(s, n):
+    """ms of one s.step(n) call from HIP events on the solver's stream, bracketed by device syncs."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s.stream)
+    s.step(n)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def batched_summary(lbm, instances, steps, warmup):
+    """The batched gravity sweep (64 boiling instances on 256x512 / 384x768 / 512x1024 grids): one
+    batched, graph-replayed launch per step over every instance, against the same instances run one
+    after the other with plain lbm_step calls (each grid size at its own autotuned tile shape).  Same
+    steps for both; the first four instances are compared bit for bit."""
+    import torch
+
+    from paper_2205_00686_amd import autotune
+
+    ws = sweep_workloads(instances, steps, lbm)
+    nodes = sum(w.nodes for w in ws)
+    print(f"[bench] batched: {len(ws)} boiling instances, {nodes} nodes, {steps} steps", file=sys.stderr, flush=True)
+    solvers = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for w in ws]
+    stream = solvers[0].stream
+    plain_shapes = {}
+    for s in solvers:
+        key = f"{s.nx}x{s.ny}"
+        if key not in plain_shapes:
+            plain_shapes[key] = autotune.tune_solver(s, use_cache=False).shape
+        s.set_shape(plain_shapes[key])
+        s.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for s in solvers:
+        s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    for s in solvers:
+        s.sync()
+    plain_ms = e0.elapsed_time(e1)
+    plain_state = [s.save_state() for s in solvers[:4]]
+    for s in solvers:
+        s.close()
+    solvers = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for w in ws]
+    b = lbm.Batch(solvers)
+    for i in range(len(solvers)):
+        b.set_budget(i, warmup)
+    b.step(warmup)
+    b.sync()
+    bt = autotune.tune_batch(b, use_cache=False)
+    for i in range(len(solvers)):
+        b.set_budget(i, steps)
+    torch.cuda.synchronize()
+    e0.record(b.stream)
+    b.step(steps)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    st = b.sync()
+    batch_ms = e0.elapsed_time(e1)
+    same = all(s.save_state() == p for s, p in zip(solvers[:4], plain_state))
+    b.close()
+    for s in solvers:
+        s.close()
+    lu = nodes * steps
+    return {"workload": f"gravity sweep: {len(ws)} boiling instances on 256x512/384x768/512x1024 grids, g log-uniform "
+                        f"[5e-6, 5e-5], hot-spot dT uniform [0.1, 0.3] Tc, pool fill 0.5 or head-limited, FP32",
+            "instances": len(ws), "nodes": nodes, "steps": steps, "warmup": warmup,
+            "batched_mlups": round(lu / (batch_ms * 1e-3) / 1e6, 1),
+            "plain_sequential_mlups": round(lu / (plain_ms * 1e-3) / 1e6, 1),
+            "speedup": round(plain_ms / batch_ms, 3),
+            "batched_roofline_frac": round(lu * BYTES_PER_LU["f32"] / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "batch_tile_shape": shape_text(lbm, lbm.LBM_FP32, bt.shape),
+            "plain_tile_shapes": {k: shape_text(lbm, lbm.LBM_FP32, v) for k, v in plain_shapes.items()},
+            "equal_bits_first4": same, "failed_instances": sum(1 for x in st if x != 0)}
+
+
+def served_summary(lbm, requests, rate, min_steps, max_steps, budget_gb, slots, chunk):
+    """A Poisson stream of mixed droplet / evaporation / boiling requests (grids log-uniform between
+    128x128 and 1024x2048): continuous batching (admission by HBM footprint, state kept on the device,
+    requests joining between chunks) against one-at-a-time FIFO service with plain launches.
+    Latency runs from arrival to fields on the host."""
+    from paper_2205_00686_amd import serve
+    from workloads import Params, boiling, droplet, evaporation, head_limited_fill, request_stream
+
+    base = Params()
+    Tc = lbm.critical_temperature(base)
+    rl, rg, ps = lbm.coexistence(base, 0.86 * Tc)
+
+    def make(spec):
+        nx, ny, seed = spec["nx"], spec["ny"], spec["seed"]
+        if spec["kind"] == "droplet":
+            return lambda: droplet(Tc, rl, rg, nx=nx, ny=ny, R=min(nx, ny) / 4.0)
+        if spec["kind"] == "evaporation":
+            return lambda: evaporation(Tc, rl, rg, nx=nx, ny=ny, R=min(nx, ny) / 8.0)
+        fill = head_limited_fill(rl, rg, ps, 2e-5, ny)
+        return lambda: boiling(Tc, rl, rg, nx=nx, ny=ny, seed=seed, fill=fill)
+
+    specs = request_stream(n=requests, rate=rate, steps_range=(min_steps, max_steps))
+    mk = lambda: [serve.Request(rid=sp["id"], arrival=sp["arrival"], steps=sp["steps"], make=make(sp),  # noqa: E731
+                                meta={"kind": sp["kind"], "nx": sp["nx"], "ny": sp["ny"]}) for sp in specs]
+    print(f"[bench] served: {requests} requests at {rate}/s, budget {budget_gb} GB, {slots} slots",
+          file=sys.stderr, flush=True)
+    server = serve.Server(hbm_budget=int(budget_gb * 2**30), max_slots=slots, chunk=chunk, keep_results=False)
+    _, served = server.run(mk())
+    print(f"[bench] served {json.dumps(served)}", file=sys.stderr, flush=True)
+    _, fifo = serve.fifo(mk(), keep_results=False)
+    print(f"[bench] fifo {json.dumps(fifo)}", file=sys.stderr, flush=True)
+    keep = ("completed", "failed", "latency_p50_s", "latency_p99_s", "makespan_s", "aggregate_mlups")
+    return {"workload": f"Poisson stream of {requests} mixed droplet/evaporation/boiling requests at {rate} req/s, "
+                        f"grids log-uniform 128x128..1024x2048, steps uniform [{min_steps}, {max_steps}], FP32",
+            "hbm_budget_gb": budget_gb, "slots": slots, "chunk": chunk,
+            "served": {k: (round(served[k], 4) if isinstance(served[k], float) else served[k]) for k in keep},
+            "fifo": {k: (round(fifo[k], 4) if isinstance(fifo[k], float) else fifo[k]) for k in keep}}
+
+
+def run_headline(args):
+    """The benchmark line: the nucleate-boiling pool at 1024 x 2048 in FP32 (the largest
+    single-GPU workload; its pool is filled to the head limit of the closed box, see
+    workloads.head_limited_fill), W warm-up steps, tile shape autotuned, then exactly K steps in one
+    lbm_step call timed with HIP events on the library's stream.  Beside it: repeats of the same call,
+    the roofline of the step kernel, the batched sweep against plain launches, the served stream
+    against FIFO, and the FP64 oracle on a bounded sample of the same workload."""
+    import numpy as np
+    import torch
+
+    import paper_2205_00686_amd as lbm
+
+    torch.cuda.set_device(0)
+    w = build_workload(args.nx, args.ny, args.steps, args.workload)
+    prec = lbm.LBM_FP64 if args.precision == "fp64" else lbm.LBM_FP32
+    PREC = args.precision.upper()
+    dtype = "f64" if prec == lbm.LBM_FP64 else "f32"
+    s = lbm.Solver(w.params, precision=prec).init(w.rho, w.ux, w.uy, w.T)
+    print(f"[bench] {args.nx}x{args.ny} {args.workload} {PREC}, warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    if args.calibration_copy_mib > 0:
+        calibration_copy(lbm, args.calibration_copy_mib)
+    tune = choose_shape(s, args.shape)
+    print(f"[bench] tile shape {s.shape}: {tune}", file=sys.stderr, flush=True)
+    s.step(args.warmup)
+    s.sync()
+    # ---- the timed region: exactly K steps in one call
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = _timed_steps(s, args.steps)
+    wall = time.perf_counter() - t0
+    s.sync()  # raises if the device flagged a numerical failure
+    nodes = w.nodes
+    mlups = nodes * args.steps / (ms * 1e-3) / 1e6
+    depth = lbm.shapes(prec)[s.shape][3]  # time steps per launch of the step kernel
+    launches = -(-args.steps // depth)
+    ms_per_launch = ms / launches
+    # ---- repeats: separate calls of K steps, and calls repeated until 0.5 s of GPU time
+    rep = sorted(nodes * args.steps / (_timed_steps(s, args.steps) * 1e-3) / 1e6 for _ in range(args.repeats))
+    sus_ms, sus_steps = 0.0, 0
+    while sus_ms < 500.0:
+        sus_ms += _timed_steps(s, args.steps)
+        sus_steps += args.steps
+    s.sync()
+    bytes_per_launch = BYTES_PER_LU[dtype] * nodes * depth
+    achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
+    prof = TRAFFIC.get((args.workload, args.nx, args.ny, s.shape, dtype))
+    sha = _kernel_source_sha()
+    traffic = prof["bytes"] if prof and prof["kernel_sha"] == sha else None
+    fields = s.fields()
+    finite = all(bool(np.isfinite(f).all()) for f in fields)
+    shape = s.shape
+    s.close()
+    wl = {"evaporation": f"droplet evaporation in open space, {args.nx}x{args.ny}, R={64 * args.nx // 512}, "
+                         f"edges at 1.1 T_sat",
+          "boiling": f"nucleate boiling on a heated wall, {args.nx}x{args.ny}, walls (75/90 deg), hot spot width "
+                     f"32 dT 0.2 Tc, g 2e-5, noise 1e-3 seed 1, pool fill {w.meta['fill']:.3f} (head limit of the "
+                     f"closed box; the stated fill 0.5 collapses the vapour column)"}[args.workload]
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": f"synthetic (seeded initial fields of the paper's {args.workload} problem)",
+        "config": {"workload": f"{wl}, {PREC} populations", "nx": args.nx, "ny": args.ny,
+                   "kernel": "fused D2Q9+D2Q5 step", "tile_shape": shape_text(lbm, prec, shape),
+                   "tile_shape_ms_per_step": tune, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "algorithmic_bytes_per_launch": bytes_per_launch, "steps_per_launch": depth,
+                     "kernel_ms_per_launch": round(ms_per_launch, 6),
+                     "measured_hbm_gbs": round(traffic / (ms_per_launch * 1e-3) / 1e9, 1) if traffic else None,
+                     "kernel_sha": sha},
+        "repeats": {"calls": args.repeats, "steps_each": args.steps, "mlups_p50": round(rep[len(rep) // 2], 1),
+                    "mlups_min": round(rep[0], 1), "mlups_max": round(rep[-1], 1)},
+        "sustained": {"steps": sus_steps, "gpu_s": round(sus_ms * 1e-3, 4),
+                      "mlups": round(nodes * sus_steps / (sus_ms * 1e-3) / 1e6, 1)},
+        "wall_s": round(wall, 4),
+        "fields_finite": finite,
+    }
+    if not args.no_batched:
+        out["batched"] = batched_summary(lbm, args.instances, args.batch_steps, args.batch_warmup)
+    if not args.no_served:
+        out["served"] = served_summary(lbm, args.serve_requests, args.rate, args.min_steps, args.max_steps,
+                                       args.hbm_budget_gb, args.slots, args.chunk)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -542,13 +789,19 @@ def main():
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=512)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 20000; 10000 with --mode batch)")
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--workload", choices=["evaporation", "boiling"], default="evaporation",
-                    help="plain mode: the benchmark workload (default) or the boiling pool")
-    ap.add_argument("--nx", type=int, default=512)
-    ap.add_argument("--ny", type=int, default=512)
-    ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 2000; 10000 with --mode batch)")
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", choices=["evaporation", "boiling"], default="boiling",
+                    help="plain mode: the boiling pool (default) or the evaporation workload")
+    ap.add_argument("--nx", type=int, default=1024)
+    ap.add_argument("--ny", type=int, default=2048)
+    ap.add_argument("--repeats", type=int, default=5, help="plain mode: further timed calls of K steps")
+    ap.add_argument("--batch-steps", type=int, default=10000, help="plain mode: steps of the batched sweep")
+    ap.add_argument("--batch-warmup", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=256, help="plain mode: requests of the served stream")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--shape", default="auto", help="tile shape index, or 'auto' to autotune (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -560,7 +813,7 @@ def main():
               f"(--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
     if args.mode == "fritz":
-        if args.nx == 512 and args.ny == 512:  # the paper's boiling domain unless a grid is given
+        if args.nx == 1024 and args.ny == 2048:  # the paper's boiling domain unless a grid is given
             args.nx, args.ny = 150, 300
         args.steps = args.steps or 200000
         return run_fritz_mode(args)
@@ -578,116 +831,13 @@ def main():
         args.steps = args.steps or 4000
         return run_lattice_mode(args)
     if args.steps is None:
-        args.steps = 10000 if args.mode == "batch" else 20000
+        args.steps = 10000 if args.mode == "batch" else 2000
     if args.mode == "batch":
         return run_batch_mode(args)
     if args.mode == "serve":
         return run_serve_mode(args)
 
-    import torch
-
-    import paper_2205_00686_amd as lbm
-
-    torch.cuda.set_device(0)
-    w = build_workload(args.nx, args.ny, args.steps, args.workload)
-    prec = lbm.LBM_FP64 if args.precision == "fp64" else lbm.LBM_FP32
-    PREC = args.precision.upper()
-    s = lbm.Solver(w.params, precision=prec).init(w.rho, w.ux, w.uy, w.T)
-    stream = s.stream
-    print(f"[bench] {args.nx}x{args.ny} {args.workload} {PREC}, warmup {args.warmup}, steps {args.steps}",
-          file=sys.stderr, flush=True)
-
-    if args.calibration_copy_mib > 0:
-        n = args.calibration_copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    s.step(args.warmup)
-    s.sync()
-    tune = choose_shape(s, args.shape)
-    print(f"[bench] tile shape {s.shape}: {tune}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    # the K timed steps run as five equal segments (the last takes the remainder) with an event
-    # between them: `value` is the whole run, the segments give the p50 and spread of repeats
-    nseg = 5 if args.steps >= 5 else 1
-    seg_steps = [args.steps // nseg] * (nseg - 1) + [args.steps - (args.steps // nseg) * (nseg - 1)]
-    seg_ev = [torch.cuda.Event(enable_timing=True) for _ in range(nseg - 1)]
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for k, n in enumerate(seg_steps):
-        s.step(n)
-        if k < nseg - 1:
-            seg_ev[k].record(stream)
-    ev1.record(stream)
-    ev1.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    s.sync()  # raises if the device flagged a numerical failure
-    ev_ms = ev0.elapsed_time(ev1)
-    bounds = [ev0] + seg_ev + [ev1]
-    seg_mlups = sorted(w.nodes * n / (bounds[k].elapsed_time(bounds[k + 1]) * 1e-3) / 1e6
-                       for k, n in enumerate(seg_steps))
-    ms_per_step = ev_ms / args.steps
-    nodes = w.nodes
-    mlups = nodes * args.steps / (ev_ms * 1e-3) / 1e6
-
-    # latency of a one-step call (one launch, no graph) from event pairs around it
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(200)]
-    for a, b in evs:
-        a.record(stream)
-        s.step(1)
-        b.record(stream)
-    torch.cuda.synchronize()
-    per_launch_ms = sorted(a.elapsed_time(b) for a, b in evs)
-    launch_p50 = per_launch_ms[len(per_launch_ms) // 2]
-
-    dtype = "f64" if prec == lbm.LBM_FP64 else "f32"
-    depth = lbm.shapes(prec)[s.shape][3]  # time steps per launch of the step kernel
-    bytes_per_launch = BYTES_PER_LU[dtype] * nodes * depth
-    ms_per_launch = ms_per_step * depth
-    achieved = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
-    fields = s.fields()
-    finite = all(bool((f == f).all()) for f in fields)
-
-    out = {
-        "metric": METRIC,
-        "value": round(mlups, 1),
-        "unit": "MLUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 6),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": dtype,
-        "data": f"synthetic (seeded initial fields of the paper's {args.workload} problem)",
-        "config": {"workload": (f"droplet evaporation in open space, {args.nx}x{args.ny}, {PREC} populations, "
-                                f"R={64 * args.nx // 512}, edges at 1.1 T_sat") if args.workload == "evaporation" else
-                               (f"nucleate boiling on a heated wall, {args.nx}x{args.ny}, {PREC} populations, walls, "
-                                f"hot spot width 32 dT 0.2 Tc, g 2e-5, pool fill {w.meta['fill']:.3f} (head limit)"),
-                   "nx": args.nx, "ny": args.ny, "precision": args.precision, "kernel": "fused D2Q9+D2Q5 step",
-                   "tile_shape": shape_text(lbm, prec, s.shape), "tile_shape_ms_per_step": tune,
-                   "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": TRAFFIC.get((args.workload, args.nx, args.ny, s.shape)) if dtype == "f32" else None,
-                     "bytes_per_launch": bytes_per_launch, "steps_per_launch": depth,
-                     "kernel_ms_per_launch_timed_region": round(ms_per_launch, 6),
-                     "kernel_ms_single_step_call_p50": round(launch_p50, 6)},
-        "repeats": {"segments": nseg, "steps_each": seg_steps[0], "mlups_p50": round(seg_mlups[nseg // 2], 1),
-                    "mlups_min": round(seg_mlups[0], 1), "mlups_max": round(seg_mlups[-1], 1)},
-        "wall_s": round(wall, 4),
-        "fields_finite": finite,
-    }
-    if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
-    print(json.dumps(out), flush=True)
+    return run_headline(args)
 
 
 if __name__ == "__main__":

@@ -76,8 +76,12 @@ typedef struct {
      1/(lambda/chat_s^2 + 1/2) with chat_s^2 = wdot/2; heat capacity c_v; weight parameter
      wdot in (0,1); relaxation rates varsigma_3, varsigma_4 */
   double lambda, cv, wdot, vs3, vs4;
-  /* buoyancy F_b = (rho - rho_ave) g (Section 4.3); rho_ave = NaN -> FP64 mean of the
-     initial density, computed by lbm_init */
+  /* buoyancy F_b = (rho - rho_ave) g (Section 4.3, rho_ave the mean density of the whole domain).
+     rho_ave = NaN: that mean, in FP64.  On closed and periodic domains mass is conserved and the
+     mean of the initial density is used throughout; with an open top the device tracks the mass
+     that crosses the top in each step (FP64, added by the boundary pass after the step), so
+     rho_ave is the mean density of the current state at every step.  A finite rho_ave is used as
+     a constant. */
   double gx, gy, rho_ave;
   int32_t y_walls;       /* 0: periodic in y; 1: no-slip halfway walls at y=-1/2 and ny-1/2 */
   int32_t thermal_box;   /* 1: Dirichlet T = T_box on all four edges (flow stays periodic) */
@@ -174,14 +178,25 @@ lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy);
    empty, a non-finite threshold or NULL pointers; LBM_E_STATE before lbm_init. */
 lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi, int32_t* counts);
 
-/* Raw state to / from a host buffer of lbm_state_bytes() bytes: f[9][ny][nx], g[Q][ny][nx]
-   (Q = 5 or 9, the thermal lattice), history[2][ny][nx] in the context's precision, then three 8-byte words: the step count
-   (int64), rho_ave and T_ref (FP64).  The temperature populations are stored relative to
-   T_ref (the mean initial temperature): the buffer holds g_i - what_i T_ref and T - T_ref for
-   the history.  Resuming from a saved state reproduces an uninterrupted run bit for bit. */
+/* Raw state to / from a caller-owned host buffer of lbm_state_bytes() bytes: f[9][ny][nx],
+   g[Q][ny][nx] (Q = 5 or 9, the thermal lattice), history[2][ny][nx] in the context's precision,
+   then a 64-byte trailer: magic "LBM2D", format version, precision, nx, ny, Q, the step count
+   (int64), rho_ave, T_ref and the tracked mass (FP64).  The temperature populations are stored
+   relative to T_ref (the mean initial temperature): the buffer holds g_i - what_i T_ref and
+   T - T_ref for the history.  Resuming from a saved state reproduces an uninterrupted run bit for
+   bit.  lbm_save_state: LBM_E_STATE before lbm_init, LBM_E_INVAL for a smaller buffer; synchronises.
+   lbm_load_state: LBM_E_INVAL unless bytes equals lbm_state_bytes() and the trailer names this
+   format, the context's precision, grid and thermal lattice; then the context is initialised from
+   the buffer (it need not have been initialised before); synchronises. */
 size_t lbm_state_bytes(const lbm_ctx* h);
 lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes);
 lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes);
+
+/* The current populations as FP64 host arrays with the storage offset undone (any may be NULL):
+   f[9][ny][nx], g[Q][ny][nx] = the thermal populations g_i of Eq. (22)'s lattice (Q = 5 or 9),
+   hist[2][ny][nx] = T(t-1), T(t-2).  For checks and inspection; synchronises.  LBM_E_STATE before
+   lbm_init, LBM_E_NOMEM if the host staging buffer cannot be allocated. */
+lbm_status lbm_read_state(lbm_ctx* h, double* f, double* g, double* hist);
 
 /* Maxwell equal-area coexistence of the Peng-Robinson EOS at temperature T (host, FP64):
    rho_l, rho_g, p_sat.  LBM_E_INVAL if T is at or above the critical temperature. */
@@ -195,6 +210,14 @@ lbm_status lbm_destroy(lbm_ctx* h);
 
 const char* lbm_strerror(lbm_status s);
 const char* lbm_last_error(const lbm_ctx* h);
+
+/* Device-to-device copy of `bytes` bytes (a multiple of 16; both pointers 16-byte aligned device
+   memory owned by the caller) by a streaming kernel with 16-byte lanes, enqueued on hip_stream
+   (asynchronous).  Not part of the method: it gives the practical HBM ceiling the step kernels are
+   measured against, and a kernel of known traffic (bytes read plus bytes written) that calibrates
+   hardware byte counters in profiles.  LBM_E_INVAL for NULL or misaligned pointers or a size that
+   is not a multiple of 16; LBM_E_DEVICE if the launch fails. */
+lbm_status lbm_device_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
 
 /* ------------------------------------------------------------------------------------
  * Batched execution: many initialised contexts (uneven grids and parameters, same precision and
@@ -232,8 +255,11 @@ int64_t lbm_batch_remaining(const lbm_batch* b, int i);
 lbm_status lbm_batch_set_shape(lbm_batch* b, int k);
 int lbm_batch_get_shape(const lbm_batch* b);
 
-/* Wait for the batch's stream; report per-instance numerical failures in status[n] (may be
-   NULL).  The contexts' step counters are brought up to date. */
+/* Wait for the batch's stream; report per-instance failures in status[n] (may be NULL):
+   LBM_E_NUMERIC for a member whose device error word is set (it is parked; returns LBM_E_NUMERIC),
+   LBM_OK for the others.  The contexts' step counters and buffer parities are brought up to date.
+   If the wait or a read-back fails, every member is marked failed and parked, status[] holds
+   LBM_E_DEVICE for all of them and the call returns LBM_E_DEVICE. */
 lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status);
 
 /* Release the batch.  The caller-owned memory stays in use until the batch's stream has

@@ -96,12 +96,14 @@ lbm_status lbm3d_diagnostics(lbm3d_ctx* h, double* mass, double* energy);
 
 int64_t lbm3d_steps_done(const lbm3d_ctx* h);
 
-/* Raw state to / from a host buffer of lbm3d_state_bytes() bytes: f[19][nz][ny][nx],
-   g[7][nz][ny][nx], history[2][nz][ny][nx] in the context's precision, then two 8-byte words: the
-   step count (int64) and T_ref (FP64; g and the history are stored relative to it).  Loading
-   restores the step count and T_ref and clears a failure; resuming reproduces an uninterrupted
-   run bit for bit.  lbm3d_save_state: LBM_E_STATE before init; both: LBM_E_INVAL for a buffer
-   smaller than lbm3d_state_bytes() (or a negative stored step count on load). */
+/* Raw state to / from a caller-owned host buffer of lbm3d_state_bytes() bytes: f[19][nz][ny][nx],
+   g[7][nz][ny][nx], history[2][nz][ny][nx] in the context's precision, then a 48-byte trailer:
+   magic "LBM3D", format version, precision, nx, ny, nz, the step count (int64) and T_ref (FP64;
+   g and the history are stored relative to it).  Loading restores the step count and T_ref and
+   clears a failure; resuming reproduces an uninterrupted run bit for bit.  lbm3d_save_state:
+   LBM_E_STATE before init, LBM_E_INVAL for a smaller buffer.  lbm3d_load_state: LBM_E_INVAL
+   unless bytes equals lbm3d_state_bytes() and the trailer names this format, the context's
+   precision and grid (or for a negative stored step count).  Both synchronise. */
 size_t lbm3d_state_bytes(const lbm3d_ctx* h);
 lbm_status lbm3d_save_state(lbm3d_ctx* h, void* host, size_t bytes);
 lbm_status lbm3d_load_state(lbm3d_ctx* h, const void* host, size_t bytes);

@@ -19,7 +19,7 @@ from . import _native
 from ._native import LBM_BGK, LBM_FP32, LBM_FP64, LBM_FREEZE_FLOW, LBM_NO_S, NativeLibraryMissing
 
 __all__ = ["Solver", "Batch", "LbmError", "params_struct", "coexistence", "critical_temperature",
-           "footprint_bytes", "shapes", "shape_fits", "LBM_FP32", "LBM_FP64", "LBM_FREEZE_FLOW", "LBM_NO_S", "LBM_BGK",
+           "footprint_bytes", "shapes", "shape_fits", "device_copy", "LBM_FP32", "LBM_FP64", "LBM_FREEZE_FLOW", "LBM_NO_S", "LBM_BGK",
            "NativeLibraryMissing"]
 
 
@@ -91,6 +91,18 @@ def coexistence(prm, T: float):
 def footprint_bytes(prm, precision: int = LBM_FP32) -> int:
     c = params_struct(prm, precision)
     return int(_native.lib().lbm_footprint_bytes(ctypes.byref(c)))
+
+
+def device_copy(src, dst, stream=None):
+    """Copy the bytes of torch tensor src into dst (same byte count, a multiple of 16) with the
+    library's streaming copy kernel, on `stream` (default: the current torch stream)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("source and destination sizes differ")
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    _check(_native.lib().lbm_device_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nbytes,
+                                         ctypes.c_void_p(st.cuda_stream)))
 
 
 def _dptr(a: np.ndarray):
@@ -206,26 +218,25 @@ class Solver:
         _check(_native.lib().lbm_load_state(self.handle, buf, len(data)), self.handle)
 
     def state(self, absolute: bool = True):
-        """(f[9], g[Q], history[2]) host copies (Q = 5 or 9).  The library stores g_i - what_i T_ref
-        and T - T_ref; with absolute=True they are shifted back (FP64), otherwise returned raw in
-        the working precision."""
+        """(f[9], g[Q], history[2]) host copies (Q = 5 or 9).  absolute=True: the populations and
+        T(t-1), T(t-2) in FP64 with the library's storage offset undone (lbm_read_state);
+        absolute=False: the raw planes in the working precision, as stored (g_i - what_i T_ref,
+        T - T_ref)."""
+        n, Q = self.nx * self.ny, self.q
+        if absolute:
+            f = np.empty((9, self.ny, self.nx))
+            g = np.empty((Q, self.ny, self.nx))
+            h = np.empty((2, self.ny, self.nx))
+            _check(_native.lib().lbm_read_state(self.handle, _dptr(f), _dptr(g), _dptr(h)), self.handle)
+            return f, g, h
         raw = self.save_state()
         dt = np.float64 if self.precision == LBM_FP64 else np.float32
-        n, Q = self.nx * self.ny, self.q
         planes = 9 + Q + 2
         a = np.frombuffer(raw, dtype=dt, count=planes * n)
         f = a[:9 * n].reshape(9, self.ny, self.nx)
         g = a[9 * n:(9 + Q) * n].reshape(Q, self.ny, self.nx)
         h = a[(9 + Q) * n:planes * n].reshape(2, self.ny, self.nx)
-        if not absolute:
-            return f, g, h
-        T_ref = float(np.frombuffer(raw, dtype=np.float64, count=1, offset=planes * n * a.itemsize + 16)[0])
-        if Q == 9:
-            w = np.array([4.0 / 9.0] + [1.0 / 9.0] * 4 + [1.0 / 36.0] * 4)[:, None, None]
-        else:
-            wd = float(self.params.wdot)
-            w = np.array([1.0 - wd] + [wd / 4.0] * 4)[:, None, None]
-        return f.astype(np.float64), g.astype(np.float64) + w * T_ref, h.astype(np.float64) + T_ref
+        return f, g, h
 
 
 class Batch:
@@ -270,9 +281,13 @@ class Batch:
         return self
 
     def sync(self):
+        """Wait for the batch; per-member status (0, or -4 for a member parked after a numerical
+        failure).  Raises LbmError if the wait itself failed (every member is then failed)."""
         n = len(self.solvers)
         st = (ctypes.c_int * n)()
-        _native.lib().lbm_batch_sync(self.handle, st)
+        rc = _native.lib().lbm_batch_sync(self.handle, st)
+        if rc not in (_native.LBM_OK, _native.LBM_E_NUMERIC):
+            _check(rc, self.solvers[0].handle)
         return list(st)
 
     def close(self):

@@ -21,8 +21,8 @@ EXPORTS = (
     "lbm_params_default", "lbm_validate", "lbm_footprint_bytes", "lbm_create", "lbm_init", "lbm_step",
     "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_shape_fits", "lbm_set_shape", "lbm_get_shape",
     "lbm_sync", "lbm_read_fields", "lbm_vapour_rows", "lbm_diagnostics", "lbm_state_bytes", "lbm_save_state",
-    "lbm_load_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
-    "lbm_last_error", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
+    "lbm_load_state", "lbm_read_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
+    "lbm_last_error", "lbm_device_copy", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
     "lbm_batch_remaining", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_sync", "lbm_batch_destroy",
     "lbm3d_params_default", "lbm3d_validate", "lbm3d_footprint_bytes", "lbm3d_create", "lbm3d_init", "lbm3d_step",
     "lbm3d_sync", "lbm3d_read_fields", "lbm3d_diagnostics", "lbm3d_steps_done", "lbm3d_state_bytes",
@@ -106,11 +106,13 @@ def lib():
         "lbm_state_bytes": ([vp], sz),
         "lbm_save_state": ([vp, vp, sz], st),
         "lbm_load_state": ([vp, vp, sz], st),
+        "lbm_read_state": ([vp, dp, dp, dp], st),
         "lbm_eos_coexistence": ([P, d, dp, dp, dp], st),
         "lbm_critical_temperature": ([P], d),
         "lbm_destroy": ([vp], st),
         "lbm_strerror": ([st], ctypes.c_char_p),
         "lbm_last_error": ([vp], ctypes.c_char_p),
+        "lbm_device_copy": ([vp, vp, sz, vp], st),
         "lbm_batch_footprint_bytes": ([ctypes.c_int], sz),
         "lbm_batch_create": ([ctypes.POINTER(vp), ctypes.c_int, vp, sz, vp, ctypes.POINTER(vp)], st),
         "lbm_batch_set_budget": ([vp, ctypes.c_int, i64], st),

@@ -30,6 +30,7 @@ constexpr size_t OFF_DESC = 0;        // InstDesc<real> (single-run table)
 constexpr size_t OFF_CLOCK = 4096;    // long long
 constexpr size_t OFF_ERR = 4352;      // unsigned
 constexpr size_t OFF_DIAG = 4608;     // 2 doubles
+constexpr size_t OFF_LIVE = 4864;     // InstLive: FP64 mass and the current rho_ave
 constexpr size_t OFF_PART = 8192;     // partial sums follow the control block
 
 size_t partial_bytes() { return align_up((size_t)MAX_RED_BLOCKS * 2 * sizeof(double)); }
@@ -105,6 +106,7 @@ struct lbm_ctx {
   unsigned* d_err = nullptr;
   double* d_diag = nullptr;
   double* d_part = nullptr;
+  InstLive* d_live = nullptr;
   void* d_desc = nullptr;
   InstDesc<float> desc32{};
   InstDesc<double> desc64{};
@@ -114,11 +116,12 @@ struct lbm_ctx {
   int gen = 0;           // 1 if the current state is in the B buffers
   int hgen = 0;          // 1 if the temperature history is in ThB (it moves only on two-step launches)
   long long clock = 0;   // host mirror of the context's device clock (advanced by its own launches)
-  double rho_ave = 0.0;
+  double rho_ave = 0.0;  // rho_ave of the buoyancy at init (constant unless it follows the mean)
   double T_ref = 0.0;  // storage offset of g and the history (exact in the working precision)
   int shape_req = -1;  // requested tile shape (-1: chosen from the grid size)
   int shape = 0;       // tile shape in use
   int ntiles = 0;
+  InstLive live0{};      // staging of the live values written at init / load (outlives the copy)
   hipGraphExec_t graph = nullptr;
   std::string last_error;
 };
@@ -241,6 +244,8 @@ static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref)
   d.y_walls = p->y_walls ? 1 : 0;
   d.thermal_box = p->thermal_box ? 1 : 0;
   d.open_top = (p->y_walls && p->open_top) ? 1 : 0;
+  // where mass crosses an open top, rho_ave (when not given) follows the domain's mean density
+  d.live_rho_ave = (d.open_top && std::isnan(p->rho_ave)) ? 1 : 0;
   d.flags = p->flags;
   d.T_ref = (real)T_ref;
   d.om_e = (real)(1.0 - 0.5 * p->s_e);
@@ -273,6 +278,7 @@ static InstDesc<real> make_desc(lbm_ctx* h, int ty) {
   D.h_base = 0;
   D.t_base = 0;
   D.t_end = std::numeric_limits<long long>::max();
+  D.live = h->d_live;
   D.p = derive<real>(&h->prm, h->rho_ave, h->T_ref);
   return D;
 }
@@ -303,14 +309,17 @@ static bool set_device(lbm_ctx* h) {
 // Two-step shapes exist for the D2Q5 lattice only (shape_fits keeps the others from here).
 template <typename real, class S>
 static void launch_shape(int qg, int grid, hipStream_t st, const void* table, int ninst, const long long* clk,
-                         int k) {
+                         int k, const LaunchWin& w) {
   const InstDesc<real>* t = (const InstDesc<real>*)table;
   if (qg == 9) {
-    if constexpr (S::DEPTH == 1) step_kernel<real, S, 9><<<grid, S::NT, 0, st>>>(t, ninst, clk, k);
+    if constexpr (S::DEPTH == 1) step_kernel<real, S, 9><<<grid, S::NT, 0, st>>>(t, ninst, clk, k, w);
   } else {
-    step_kernel<real, S, 5><<<grid, S::NT, 0, st>>>(t, ninst, clk, k);
+    step_kernel<real, S, 5><<<grid, S::NT, 0, st>>>(t, ninst, clk, k, w);
   }
 }
+
+// Window of launches that read the device clock and the descriptors (graph replays, batches).
+constexpr LaunchWin FROM_CLOCK{0, 0, 0, 0, 0, 0};
 
 // ------------------------------------------------------------------------------ C ABI
 extern "C" {
@@ -399,6 +408,7 @@ lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hi
   h->d_clock = (long long*)(q + OFF_CLOCK);
   h->d_err = (unsigned*)(q + OFF_ERR);
   h->d_diag = (double*)(q + OFF_DIAG);
+  h->d_live = (InstLive*)(q + OFF_LIVE);
   q += CTRL_BYTES;
   h->d_part = (double*)q;
   q += partial_bytes();
@@ -480,6 +490,8 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
   HIP_OR_FAIL(h, hipGetLastError());
   unsigned zero = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
+  h->live0 = InstLive{sum, sum / (double)N};
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_live, &h->live0, sizeof(InstLive), hipMemcpyHostToDevice, h->stream));
   h->steps = 0;
   h->gen = 0;
   h->hgen = 0;
@@ -499,22 +511,22 @@ lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const doubl
 
 // The open-top boundary pass after launch k, one workgroup per table entry.
 static void launch_open_top(int precision, int ninst, hipStream_t st, const void* table, const long long* clk,
-                            int k) {
+                            int k, const LaunchWin& w) {
   if (precision == LBM_FP64)
-    open_top_kernel<double><<<ninst, 256, 0, st>>>((const InstDesc<double>*)table, clk, k);
+    open_top_kernel<double><<<ninst, OPEN_NT, 0, st>>>((const InstDesc<double>*)table, clk, k, w);
   else
-    open_top_kernel<float><<<ninst, 256, 0, st>>>((const InstDesc<float>*)table, clk, k);
+    open_top_kernel<float><<<ninst, OPEN_NT, 0, st>>>((const InstDesc<float>*)table, clk, k, w);
 }
 
 static void launch_step(int precision, int qg, int shape, int grid, hipStream_t st, const void* table, int ninst,
-                        const long long* clk, int k) {
+                        const long long* clk, int k, const LaunchWin& win) {
 #define LBM_LAUNCH_F32(kk, ty, w, d) \
   case kk:                           \
-    launch_shape<float, Shape<ty, w, d>>(qg, grid, st, table, ninst, clk, k); \
+    launch_shape<float, Shape<ty, w, d>>(qg, grid, st, table, ninst, clk, k, win); \
     break;
 #define LBM_LAUNCH_F64(kk, ty, w, d) \
   case kk:                           \
-    launch_shape<double, Shape<ty, w, d>>(qg, grid, st, table, ninst, clk, k); \
+    launch_shape<double, Shape<ty, w, d>>(qg, grid, st, table, ninst, clk, k, win); \
     break;
   if (precision == LBM_FP64) {
     switch (shape) { LBM_F64_SHAPES(LBM_LAUNCH_F64) default: break; }
@@ -526,15 +538,17 @@ static void launch_step(int precision, int qg, int shape, int grid, hipStream_t 
 }
 
 // n launches of the step kernel (each followed by the open-top boundary pass where the
-// simulation has one), then the clock advance by the steps they span
-static lbm_status launch_steps(lbm_ctx* h, int n) {
+// simulation has one).  With w.use the launches take their step window from w; otherwise they read
+// the device clock and the descriptor, and the clock is advanced by the steps they span (the form
+// captured in a graph).
+static lbm_status launch_steps(lbm_ctx* h, int n, const LaunchWin& w) {
   const int d = shape_def(h->prm.precision, h->shape).depth;
   const bool open = h->prm.y_walls && h->prm.open_top;
   for (int k = 0; k < n; ++k) {
-    launch_step(h->prm.precision, qg_of(&h->prm), h->shape, h->ntiles, h->stream, h->d_desc, 1, h->d_clock, k);
-    if (open) launch_open_top(h->prm.precision, 1, h->stream, h->d_desc, h->d_clock, k);
+    launch_step(h->prm.precision, qg_of(&h->prm), h->shape, h->ntiles, h->stream, h->d_desc, 1, h->d_clock, k, w);
+    if (open) launch_open_top(h->prm.precision, 1, h->stream, h->d_desc, h->d_clock, k, w);
   }
-  clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n * d);
+  if (!w.use) clock_advance_kernel<<<1, 64, 0, h->stream>>>(h->d_clock, (long long)n * d);
   HIP_OR_FAIL(h, hipGetLastError());
   return LBM_OK;
 }
@@ -542,7 +556,7 @@ static lbm_status launch_steps(lbm_ctx* h, int n) {
 static lbm_status build_graph(lbm_ctx* h) {
   hipGraph_t g = nullptr;
   HIP_OR_FAIL(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  lbm_status s = launch_steps(h, GRAPH_STEPS / shape_def(h->prm.precision, h->shape).depth);
+  lbm_status s = launch_steps(h, GRAPH_STEPS / shape_def(h->prm.precision, h->shape).depth, FROM_CLOCK);
   hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (s != LBM_OK) {
     if (g) (void)hipGraphDestroy(g);
@@ -565,30 +579,32 @@ lbm_status lbm_step(lbm_ctx* h, int64_t n) {
   if (n == 0) return LBM_OK;
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
   // this call's window: steps [clock, clock + n) from the current buffers; a launch of a
-  // two-step shape does one step where only one is left
+  // two-step shape does one step where only one is left.  Whole groups of GRAPH_STEPS steps are
+  // graph replays, which read the window and the clock from device memory (set by one small kernel
+  // per call); the remaining launches take the window as an argument.
   const int d = shape_def(h->prm.precision, h->shape).depth;
-  if (h->prm.precision == LBM_FP64)
-    set_window_kernel<double><<<1, 64, 0, h->stream>>>((InstDesc<double>*)h->d_desc, h->clock, h->gen, h->hgen,
-                                                       h->clock + n);
-  else
-    set_window_kernel<float><<<1, 64, 0, h->stream>>>((InstDesc<float>*)h->d_desc, h->clock, h->gen, h->hgen,
-                                                      h->clock + n);
-  HIP_OR_FAIL(h, hipGetLastError());
   const int64_t launches = (n + d - 1) / d;
   const int64_t per_graph = GRAPH_STEPS / d;
-  int64_t left = launches;
-  if (left >= per_graph && h->stream != nullptr) {  // the legacy null stream cannot be captured
+  // the legacy null stream cannot be captured
+  const int64_t replays = h->stream != nullptr ? launches / per_graph : 0;
+  if (replays > 0) {
     if (!h->graph) {
       lbm_status s = build_graph(h);
       if (s != LBM_OK) return s;
     }
-    while (left >= per_graph) {
-      HIP_OR_FAIL(h, hipGraphLaunch(h->graph, h->stream));
-      left -= per_graph;
-    }
+    if (h->prm.precision == LBM_FP64)
+      set_window_kernel<double><<<1, 64, 0, h->stream>>>((InstDesc<double>*)h->d_desc, h->d_clock, h->clock, h->gen,
+                                                         h->hgen, h->clock + n);
+    else
+      set_window_kernel<float><<<1, 64, 0, h->stream>>>((InstDesc<float>*)h->d_desc, h->d_clock, h->clock, h->gen,
+                                                        h->hgen, h->clock + n);
+    HIP_OR_FAIL(h, hipGetLastError());
+    for (int64_t r = 0; r < replays; ++r) HIP_OR_FAIL(h, hipGraphLaunch(h->graph, h->stream));
   }
+  const int64_t left = launches - replays * per_graph;
   if (left > 0) {
-    lbm_status s = launch_steps(h, (int)left);
+    const LaunchWin w{h->clock + replays * per_graph * d, h->clock, h->clock + n, h->gen, h->hgen, 1};
+    lbm_status s = launch_steps(h, (int)left, w);
     if (s != LBM_OK) return s;
   }
   h->clock += (long long)launches * d;
@@ -674,11 +690,11 @@ lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, doub
   const size_t N = h->N;
   const int nb = (int)((N + 255) / 256);
   if (h->prm.precision == LBM_FP64)
-    fields_kernel<double><<<nb, 256, 0, h->stream>>>(h->desc64.p, (const double*)f, (const double*)g, h->prm.nx,
-                                                      h->prm.ny, stage, h->d_err);
+    fields_kernel<double><<<nb, 256, 0, h->stream>>>(h->desc64.p, h->d_live, (const double*)f, (const double*)g,
+                                                      h->prm.nx, h->prm.ny, stage, h->d_err);
   else
-    fields_kernel<float><<<nb, 256, 0, h->stream>>>(h->desc32.p, (const float*)f, (const float*)g, h->prm.nx,
-                                                     h->prm.ny, stage, h->d_err);
+    fields_kernel<float><<<nb, 256, 0, h->stream>>>(h->desc32.p, h->d_live, (const float*)f, (const float*)g,
+                                                     h->prm.nx, h->prm.ny, stage, h->d_err);
   HIP_OR_FAIL(h, hipGetLastError());
   double* outs[4] = {rho, ux, uy, T};
   for (int c = 0; c < 4; ++c)
@@ -741,7 +757,27 @@ lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi,
 // planes of the raw state: f (9), g (5 or 9), history (2)
 static size_t state_planes(const lbm_ctx* h) { return 9 + (size_t)qg_of(&h->prm) + 2; }
 
-size_t lbm_state_bytes(const lbm_ctx* h) { return h ? state_planes(h) * h->N * h->rsz + 3 * sizeof(int64_t) : 0; }
+// Trailer of a saved state (after the planes): what the state belongs to, checked on load, and the
+// scalars that go with the populations.
+struct StateTrailer {
+  char magic[8];      // "LBM2D\0\0\0"
+  int32_t version;    // STATE_VERSION
+  int32_t precision;  // LBM_FP32 / LBM_FP64
+  int32_t nx, ny;
+  int32_t qg;         // thermal lattice: 5 or 9
+  int32_t reserved;
+  int64_t steps;
+  double rho_ave;     // rho_ave of the buoyancy at init (or as given)
+  double T_ref;       // storage offset of g and the history
+  double mass;        // FP64 mass the device tracks (it changes through an open top)
+};
+static_assert(sizeof(StateTrailer) == 64, "state trailer layout");
+constexpr int32_t STATE_VERSION = 2;
+static const char STATE_MAGIC[8] = {'L', 'B', 'M', '2', 'D', 0, 0, 0};
+
+static size_t planes_bytes(const lbm_ctx* h) { return state_planes(h) * h->N * h->rsz; }
+
+size_t lbm_state_bytes(const lbm_ctx* h) { return h ? planes_bytes(h) + sizeof(StateTrailer) : 0; }
 
 lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
   if (!h || !host) return LBM_E_INVAL;
@@ -753,32 +789,48 @@ lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
   char* q = (char*)host;
   const size_t N = h->N, r = h->rsz;
   const size_t Q = (size_t)qg_of(&h->prm);
+  InstLive live{};
   HIP_OR_FAIL(h, hipMemcpyAsync(q, f, 9 * N * r, hipMemcpyDeviceToHost, h->stream));
   HIP_OR_FAIL(h, hipMemcpyAsync(q + 9 * N * r, g, Q * N * r, hipMemcpyDeviceToHost, h->stream));
   HIP_OR_FAIL(h, hipMemcpyAsync(q + (9 + Q) * N * r, current_history(h), 2 * N * r, hipMemcpyDeviceToHost,
                                 h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(&live, h->d_live, sizeof(live), hipMemcpyDeviceToHost, h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
-  int64_t meta[3] = {h->steps, 0, 0};
-  std::memcpy(&meta[1], &h->rho_ave, sizeof(double));
-  std::memcpy(&meta[2], &h->T_ref, sizeof(double));
-  std::memcpy(q + state_planes(h) * N * r, meta, sizeof(meta));
+  StateTrailer t{};
+  std::memcpy(t.magic, STATE_MAGIC, sizeof(t.magic));
+  t.version = STATE_VERSION;
+  t.precision = h->prm.precision;
+  t.nx = h->prm.nx;
+  t.ny = h->prm.ny;
+  t.qg = qg_of(&h->prm);
+  t.steps = h->steps;
+  t.rho_ave = h->rho_ave;
+  t.T_ref = h->T_ref;
+  t.mass = live.mass;
+  std::memcpy(q + planes_bytes(h), &t, sizeof(t));
   return check_device_error(h);
 }
 
 lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
   if (!h || !host) return LBM_E_INVAL;
-  if (bytes < lbm_state_bytes(h)) return fail(h, LBM_E_INVAL, "host buffer smaller than lbm_state_bytes");
-  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  if (bytes != lbm_state_bytes(h)) return fail(h, LBM_E_INVAL, "buffer size differs from lbm_state_bytes");
   const char* q = (const char*)host;
+  StateTrailer t;
+  std::memcpy(&t, q + planes_bytes(h), sizeof(t));
+  if (std::memcmp(t.magic, STATE_MAGIC, sizeof(t.magic)) != 0 || t.version != STATE_VERSION)
+    return fail(h, LBM_E_INVAL, "not a saved state of this library version");
+  if (t.precision != h->prm.precision || t.nx != h->prm.nx || t.ny != h->prm.ny || t.qg != qg_of(&h->prm))
+    return fail(h, LBM_E_INVAL, "saved state of another precision, grid or thermal lattice");
+  if (t.steps < 0 || !std::isfinite(t.rho_ave) || !std::isfinite(t.T_ref) || !std::isfinite(t.mass))
+    return fail(h, LBM_E_INVAL, "corrupt state trailer");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
   const size_t N = h->N, r = h->rsz;
-  int64_t meta[3];
-  std::memcpy(meta, q + state_planes(h) * N * r, sizeof(meta));
-  if (meta[0] < 0) return fail(h, LBM_E_INVAL, "corrupt state: negative step count");
-  h->steps = meta[0];
+  h->steps = t.steps;
   h->gen = 0;  // the state goes to the A buffers
   h->hgen = 0;
-  std::memcpy(&h->rho_ave, &meta[1], sizeof(double));
-  std::memcpy(&h->T_ref, &meta[2], sizeof(double));
+  h->rho_ave = t.rho_ave;
+  h->T_ref = t.T_ref;
+  h->live0 = InstLive{t.mass, t.mass / (double)N};
   void *f, *g, *fo;
   current_buffers(h, f, g, fo);
   const size_t Q = (size_t)qg_of(&h->prm);
@@ -786,6 +838,7 @@ lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
   HIP_OR_FAIL(h, hipMemcpyAsync(g, q + 9 * N * r, Q * N * r, hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(h, hipMemcpyAsync(current_history(h), q + (9 + Q) * N * r, 2 * N * r, hipMemcpyHostToDevice,
                                 h->stream));
+  HIP_OR_FAIL(h, hipMemcpyAsync(h->d_live, &h->live0, sizeof(InstLive), hipMemcpyHostToDevice, h->stream));
   unsigned zero = 0;
   HIP_OR_FAIL(h, hipMemcpyAsync(h->d_err, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream));
   lbm_status s = upload_desc(h);
@@ -794,6 +847,39 @@ lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
   if (s != LBM_OK) return s;
   h->initialised = true;
   h->failed = false;
+  return LBM_OK;
+}
+
+lbm_status lbm_read_state(lbm_ctx* h, double* f, double* g, double* hist) {
+  if (!h) return LBM_E_INVAL;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_read_state before lbm_init");
+  std::vector<char> raw;
+  try {
+    raw.resize(lbm_state_bytes(h));
+  } catch (const std::bad_alloc&) {
+    return fail(h, LBM_E_NOMEM, "host buffer for the state");
+  }
+  lbm_status s = lbm_save_state(h, raw.data(), raw.size());
+  if (s != LBM_OK) return s;
+  const size_t N = h->N;
+  const int qg = qg_of(&h->prm);
+  // weights of the thermal lattice (Eq. 26; the D2Q9 weights for qg = 9): g is stored as
+  // g_i - what_i T_ref, the history as T - T_ref
+  const double w0 = qg == 9 ? 4.0 / 9.0 : 1.0 - h->prm.wdot;
+  const double w1 = qg == 9 ? 1.0 / 9.0 : h->prm.wdot / 4.0;
+  const double w2 = qg == 9 ? 1.0 / 36.0 : 0.0;
+  auto value = [&](size_t plane, size_t k) -> double {
+    if (h->prm.precision == LBM_FP64) return ((const double*)raw.data())[plane * N + k];
+    return (double)((const float*)raw.data())[plane * N + k];
+  };
+  for (size_t k = 0; k < N; ++k) {
+    if (f)
+      for (size_t i = 0; i < 9; ++i) f[i * N + k] = value(i, k);
+    if (g)
+      for (int i = 0; i < qg; ++i) g[i * N + k] = value(9 + i, k) + (i == 0 ? w0 : i < 5 ? w1 : w2) * h->T_ref;
+    if (hist)
+      for (size_t j = 0; j < 2; ++j) hist[j * N + k] = value(9 + qg + j, k) + h->T_ref;
+  }
   return LBM_OK;
 }
 
@@ -1048,8 +1134,8 @@ static lbm_status batch_launch(lbm_batch* b, int nl) {
   bool open = false;
   for (const lbm_ctx* h : b->ctx) open = open || (h->prm.y_walls && h->prm.open_top);
   for (int s = 0; s < nl; ++s) {
-    launch_step(b->precision, b->qg, b->shape, b->total_tiles, b->stream, b->d_table, n, b->d_clock, s);
-    if (open) launch_open_top(b->precision, n, b->stream, b->d_table, b->d_clock, s);
+    launch_step(b->precision, b->qg, b->shape, b->total_tiles, b->stream, b->d_table, n, b->d_clock, s, FROM_CLOCK);
+    if (open) launch_open_top(b->precision, n, b->stream, b->d_table, b->d_clock, s, FROM_CLOCK);
   }
   clock_advance_kernel<<<1, 64, 0, b->stream>>>(b->d_clock, (long long)nl * d);
   HIP_OR_FAIL(b->ctx[0], hipGetLastError());
@@ -1107,10 +1193,10 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
 
 lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status) {
   if (!b) return LBM_E_INVAL;
-  lbm_ctx* h0 = b->ctx[0];
-  HIP_OR_FAIL(h0, hipStreamSynchronize(b->stream));
-  lbm_status worst = LBM_OK;
-  for (size_t i = 0; i < b->ctx.size(); ++i) {
+  const size_t n = b->ctx.size();
+  // The launches already enqueued have advanced the members (their buffer parities and step
+  // counts follow them whatever the outcome of the wait).
+  for (size_t i = 0; i < n; ++i) {
     lbm_ctx* h = b->ctx[i];
     h->steps += b->pending[i];
     h->gen ^= (int)(b->pending_launches[i] & 1);
@@ -1118,17 +1204,38 @@ lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status) {
     b->pending[i] = 0;
     b->pending_launches[i] = 0;
     b->pending_hmoves[i] = 0;
-    unsigned e = 0;
-    HIP_OR_FAIL(h, hipMemcpy(&e, h->d_err, sizeof(unsigned), hipMemcpyDeviceToHost));
-    if (e) {
+  }
+  // A device error leaves every member's state unknown: each is marked failed (LBM_E_DEVICE in
+  // status[]) and parked.
+  auto device_failure = [&](lbm_ctx* h, const char* call, hipError_t e) {
+    const std::string msg = std::string(call) + ": " + hipGetErrorString(e);
+    for (size_t i = 0; i < n; ++i) {
+      b->ctx[i]->failed = true;
+      b->ctx[i]->last_error = "batched run: " + msg;
+      b->remaining[i] = 0;
+      if (status) status[i] = LBM_E_DEVICE;
+    }
+    return fail(h, LBM_E_DEVICE, msg);
+  };
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return device_failure(b->ctx[0], "hipStreamSynchronize", e);
+  lbm_status worst = LBM_OK;
+  for (size_t i = 0; i < n; ++i) {
+    lbm_ctx* h = b->ctx[i];
+    unsigned err = 0;
+    e = hipMemcpy(&err, h->d_err, sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_failure(h, "hipMemcpy", e);
+    if (err && !h->failed) {
       h->failed = true;
       h->last_error = "numerical failure on the device (batched run)";
+    }
+    if (h->failed) {
       b->remaining[i] = 0;
       worst = LBM_E_NUMERIC;
     }
   }
   if (status)
-    for (size_t i = 0; i < b->ctx.size(); ++i) status[i] = b->ctx[i]->failed ? LBM_E_NUMERIC : LBM_OK;
+    for (size_t i = 0; i < n; ++i) status[i] = b->ctx[i]->failed ? LBM_E_NUMERIC : LBM_OK;
   return worst;
 }
 

@@ -1211,7 +1211,28 @@ lbm_status lbm3d_diagnostics(lbm3d_ctx* h, double* mass, double* energy) {
 
 int64_t lbm3d_steps_done(const lbm3d_ctx* h) { return h ? h->steps : -1; }
 
-size_t lbm3d_state_bytes(const lbm3d_ctx* h) { return h ? 28 * h->N * h->rsz + 2 * sizeof(int64_t) : 0; }
+}  // extern "C"
+
+namespace {
+// Trailer of a saved three-dimensional state (after the planes), checked on load.
+struct State3Trailer {
+  char magic[8];      // "LBM3D"
+  int32_t version;    // STATE3_VERSION
+  int32_t precision;
+  int32_t nx, ny, nz;
+  int32_t reserved;
+  int64_t steps;
+  double T_ref;       // storage offset of g and the history
+};
+static_assert(sizeof(State3Trailer) == 48, "state trailer layout");
+constexpr int32_t STATE3_VERSION = 2;
+constexpr char STATE3_MAGIC[8] = {'L', 'B', 'M', '3', 'D', 0, 0, 0};
+size_t planes3_bytes(const lbm3d_ctx* h) { return 28 * h->N * h->rsz; }
+}  // namespace
+
+extern "C" {
+
+size_t lbm3d_state_bytes(const lbm3d_ctx* h) { return h ? planes3_bytes(h) + sizeof(State3Trailer) : 0; }
 
 lbm_status lbm3d_save_state(lbm3d_ctx* h, void* host, size_t bytes) {
   if (!h || !host) return LBM_E_INVAL;
@@ -1223,22 +1244,33 @@ lbm_status lbm3d_save_state(lbm3d_ctx* h, void* host, size_t bytes) {
   HIP3(h, hipMemcpyAsync(q + 19 * N * r, h->gen ? h->gB : h->gA, 7 * N * r, hipMemcpyDeviceToHost, h->stream));
   HIP3(h, hipMemcpyAsync(q + 26 * N * r, h->Th, 2 * N * r, hipMemcpyDeviceToHost, h->stream));
   HIP3(h, hipStreamSynchronize(h->stream));
-  int64_t meta[2] = {h->steps, 0};
-  std::memcpy(&meta[1], &h->T_ref, sizeof(double));
-  std::memcpy(q + 28 * N * r, meta, sizeof(meta));
+  State3Trailer t{};
+  std::memcpy(t.magic, STATE3_MAGIC, sizeof(t.magic));
+  t.version = STATE3_VERSION;
+  t.precision = h->prm.precision;
+  t.nx = h->prm.nx;
+  t.ny = h->prm.ny;
+  t.nz = h->prm.nz;
+  t.steps = h->steps;
+  t.T_ref = h->T_ref;
+  std::memcpy(q + planes3_bytes(h), &t, sizeof(t));
   return check3(h);
 }
 
 lbm_status lbm3d_load_state(lbm3d_ctx* h, const void* host, size_t bytes) {
   if (!h || !host) return LBM_E_INVAL;
-  if (bytes < lbm3d_state_bytes(h)) return fail3(h, LBM_E_INVAL, "host buffer smaller than lbm3d_state_bytes");
+  if (bytes != lbm3d_state_bytes(h)) return fail3(h, LBM_E_INVAL, "buffer size differs from lbm3d_state_bytes");
   const char* q = (const char*)host;
+  State3Trailer t;
+  std::memcpy(&t, q + planes3_bytes(h), sizeof(t));
+  if (std::memcmp(t.magic, STATE3_MAGIC, sizeof(t.magic)) != 0 || t.version != STATE3_VERSION)
+    return fail3(h, LBM_E_INVAL, "not a saved three-dimensional state of this library version");
+  if (t.precision != h->prm.precision || t.nx != h->prm.nx || t.ny != h->prm.ny || t.nz != h->prm.nz)
+    return fail3(h, LBM_E_INVAL, "saved state of another precision or grid");
+  if (t.steps < 0 || !std::isfinite(t.T_ref)) return fail3(h, LBM_E_INVAL, "corrupt state trailer");
   const size_t N = h->N, r = h->rsz;
-  int64_t meta[2];
-  std::memcpy(meta, q + 28 * N * r, sizeof(meta));
-  if (meta[0] < 0) return fail3(h, LBM_E_INVAL, "corrupt state: negative step count");
-  h->steps = meta[0];
-  std::memcpy(&h->T_ref, &meta[1], sizeof(double));
+  h->steps = t.steps;
+  h->T_ref = t.T_ref;
   h->gen = 0;  // the state goes to the A buffers
   HIP3(h, hipMemcpyAsync(h->fA, q, 19 * N * r, hipMemcpyHostToDevice, h->stream));
   HIP3(h, hipMemcpyAsync(h->gA, q + 19 * N * r, 7 * N * r, hipMemcpyHostToDevice, h->stream));

@@ -75,12 +75,15 @@ __device__ real psi_any(const DevParams<real>& p, const real* __restrict__ f, co
   return pseudo(p, rho, T, err);
 }
 
-// rho, u (with half the force of the current state, Eq. 11) and T to FP64 staging:
+// rho, u (with half the force of the current state, Eq. 11; the buoyancy with the current rho_ave)
+// and T to FP64 staging:
 // out[0..N) rho, [N..2N) ux, [2N..3N) uy, [3N..4N) T.
 template <typename real>
-__global__ void fields_kernel(DevParams<real> p, const real* __restrict__ f, const real* __restrict__ g, int nx, int ny,
-                              double* __restrict__ out, unsigned* __restrict__ errw) {
+__global__ void fields_kernel(DevParams<real> p, const InstLive* __restrict__ live, const real* __restrict__ f,
+                              const real* __restrict__ g, int nx, int ny, double* __restrict__ out,
+                              unsigned* __restrict__ errw) {
   const size_t N = (size_t)nx * ny;
+  if (p.live_rho_ave) p.rho_ave = (real)live->rho_ave;  // the current mean density (open top)
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= N) return;
   const int x = (int)(k % nx), y = (int)(k / nx);

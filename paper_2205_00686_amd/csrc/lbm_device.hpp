@@ -79,6 +79,18 @@ struct DevParams {
   // (after the fields of the D2Q5 path, whose offsets, and so the kernel's scalar loads, they keep)
   real w2h, two_w2h;                // D2Q9 thermal lattice: weight of a diagonal velocity, twice it
   int open_top;                     // with walls: the top is open (outflow boundary)
+  // rho_ave of the buoyancy is the current mean density of the domain, read from InstLive at each
+  // launch (an open top, where mass leaves and enters); 0: the constant rho_ave above
+  int live_rho_ave;
+};
+
+// Quantities of one simulation that the device updates as it runs (in its control block).  The
+// mass changes only where populations cross an open top; the boundary pass after each step adds
+// that flux, so rho_ave follows the mean density of the domain (Section 4.3) without a reduction
+// over the grid.
+struct InstLive {
+  double mass;     // total mass sum(rho), FP64
+  double rho_ave;  // mass / (nx ny)
 };
 
 // One simulation as seen by the step kernel.  The step kernel serves single runs (a one-entry
@@ -99,7 +111,17 @@ struct InstDesc {
   int h_base;          // 1 if the temperature history is in ThB at clock t_base
   long long t_base;    // clock value from which launches advance this instance
   long long t_end;     // clock value at which it stops
+  InstLive* live;      // mass and current rho_ave (the instance's control block)
   DevParams<real> p;
+};
+
+// Step window of a single run passed to a launch by value (use = 1) instead of through the device
+// clock and the descriptor: launch k of the call does step t + k DEPTH of the window
+// [t_base, t_end), whose first step starts from the B buffers if b_base is 1 (h_base: the
+// temperature history).  Graph replays and batches pass use = 0 and read both from memory.
+struct LaunchWin {
+  long long t, t_base, t_end;
+  int b_base, h_base, use;
 };
 
 // Pointers into device memory.  The step kernel takes its buffers from a descriptor table in

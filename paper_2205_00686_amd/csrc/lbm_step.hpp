@@ -400,7 +400,9 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   // of a two-step launch writes the other copy
   const gptr<const char> Ths = (gptr<const char>)to_global<const real>(hodd ? D.ThB : D.ThA);
   const gptr<char> Thd = (gptr<char>)to_global<real>((hodd != FROM_LDS) ? D.ThB : D.ThA);
-  const DevParams<real> p = D.p;
+  DevParams<real> p = D.p;
+  // rho_ave of the buoyancy: the current mean density where mass crosses an open top
+  if (p.live_rho_ave) p.rho_ave = (real)D.live->rho_ave;
   constexpr bool INTERIOR = Variant<V>::INTERIOR;
   constexpr int walls = Variant<V>::WALLS ? 1 : 0;
   constexpr bool tb = Variant<V>::TB;
@@ -570,13 +572,12 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
       { auto b = dst(fdp(1), 1, 0, off); stb(b, off, fs_[1]); }
       { auto b = dst(fdp(3), -1, 0, off); stb(b, off, fs_[3]); }
       if (wall_n) {
-        // under an open top the upward populations leave and the entering ones come from the
-        // boundary pass after the step
-        if (!p.open_top) {
-          stb(fdp(4), o, fs_[2]);
-          stb(fdp(7), o, fs_[5]);
-          stb(fdp(8), o, fs_[6]);
-        }
+        // bounce-back.  Under an open top the upward populations leave instead: the boundary pass
+        // after the step reads them from these slots as the outflow of the top row, then
+        // replaces them by the populations that enter from outside
+        stb(fdp(4), o, fs_[2]);
+        stb(fdp(7), o, fs_[5]);
+        stb(fdp(8), o, fs_[6]);
       } else {
         { auto b = dst(fdp(2), 0, 1, off); stb(b, off, fs_[2]); }
         { auto b = dst(fdp(5), 1, 1, off); stb(b, off, fs_[5]); }
@@ -858,7 +859,7 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
 // B exactly when b_base plus the number of launches since t_base is odd.
 template <typename real, class S, int QG>
 __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __restrict__ table, int ninst,
-                                                     const long long* __restrict__ clock, int k) {
+                                                     const long long* __restrict__ clock, int k, LaunchWin w) {
   static_assert(QG == 5 || (QG == 9 && S::DEPTH == 1), "D2Q9 thermal populations: one step per launch");
   // ---- which simulation and which tile (uniform per workgroup).  Workgroups are dispatched to
   // the 8 XCDs round-robin; remap so that each XCD takes a contiguous range of tiles: neighbouring
@@ -875,17 +876,21 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
     else hi = mid - 1;
   }
   const InstDesc<real>& D = table[lo];
-  const long long t = *clock + (long long)k * S::DEPTH;
-  if (t < D.t_base || t >= D.t_end) return;
+  // step window: from the arguments (single runs launched directly) or from the device clock and
+  // the descriptor (graph replays, batches)
+  const long long t = (w.use ? w.t : *clock) + (long long)k * S::DEPTH;
+  const long long t_base = w.use ? w.t_base : D.t_base, t_end = w.use ? w.t_end : D.t_end;
+  const int b_base = w.use ? w.b_base : D.b_base, h_base = w.use ? w.h_base : D.h_base;
+  if (t < t_base || t >= t_end) return;
   const int tile = bid - D.tile_begin;
   if (tile < 0 || tile >= D.ntx * D.nty) return;
   const int by = tile / D.ntx;
   const int bx = tile - by * D.ntx;
   const int x0 = bx * TX, y0 = by * S::TY;
-  const bool odd = ((D.b_base + (t - D.t_base) / S::DEPTH) & 1) != 0;
+  const bool odd = ((b_base + (t - t_base) / S::DEPTH) & 1) != 0;
   // the history changes copy once per launch that does two steps (every launch of a two-step
   // shape in the window but possibly the last, which does one step in place)
-  const bool hodd = ((D.h_base + (S::DEPTH == 2 ? (t - D.t_base) / 2 : 0)) & 1) != 0;
+  const bool hodd = ((h_base + (S::DEPTH == 2 ? (t - t_base) / 2 : 0)) & 1) != 0;
   unsigned err = 0u;
   // interior: the load region lies inside the grid, so no wrap, ghost row, wall or Dirichlet
   // edge is involved
@@ -894,7 +899,7 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
   const LdsState<real, S> none{};
   if constexpr (S::DEPTH == 2) {
     __shared__ Step2Lds<real, S> L2;
-    if (D.t_end - t >= 2) {
+    if (t_end - t >= 2) {
       real Tn1[S::RPT], Tn2[S::RPT];
       const bool interior2 =
           x0 >= S::MXH && x0 + TX + S::MXH <= D.nx && y0 >= S::MYH && y0 + S::TY + S::MYH <= D.ny;
@@ -937,27 +942,50 @@ __global__ void clock_advance_kernel(long long* clock, long long n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) clock[0] = clock[0] + n;
 }
 
-// Step window of a single run, set on its stream before the call's launches: steps
-// [t_base, t_end) of the clock, starting from the B buffers if b_base is 1.  (A kernel takes its
-// arguments at enqueue, so no host buffer has to outlive the call.)
+// Step window and device clock of a single run, set on its stream before the graph replays of an
+// lbm_step call: steps [t_base, t_end) of the clock, starting from the B buffers if b_base is 1.
+// (A kernel takes its arguments at enqueue, so no host buffer has to outlive the call.)
+template <typename real>
+__global__ void set_window_kernel(InstDesc<real>* d, long long* clock, long long t_base, int b_base, int h_base,
+                                  long long t_end) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    d->t_base = t_base;
+    d->b_base = b_base;
+    d->h_base = h_base;
+    d->t_end = t_end;
+    clock[0] = t_base;
+  }
+}
+
 // Open top boundary, after the step of launch k of a one-step shape: the populations that enter
 // the top row N from outside (c_y = -1) follow the convective outflow condition
 //   f_i(x, N, t+1) = [f_i(x, N, t) + U f_i(x, N-1, t+1)] / (1 + U),
 // U = j_y / rho of the top node at time t clipped to [0, 1].  f(t) is in the step's source
-// buffers, f(t+1) of row N-1 in its destination buffers.  Workgroup b serves table entry b
-// (entries without an open top, or outside their window, return at once), its threads stride
-// over the columns.
+// buffers, f(t+1) of row N-1 in its destination buffers.  The step kernel has left the outgoing
+// populations of the top row (c_y = +1) in the slots of the entering ones; their sum, subtracted
+// from that of the entering values, is the mass the domain gains through the top in this step,
+// added to the instance's FP64 mass in a fixed order (per-thread column sums, then the lanes and
+// wavefronts in a fixed tree), so rho_ave follows the mean density.  Workgroup b serves table
+// entry b (entries without an open top, or outside their window, return at once); its threads
+// stride over the columns.
+constexpr int OPEN_NT = 256;
+
 template <typename real>
-__global__ void open_top_kernel(const InstDesc<real>* __restrict__ table, const long long* __restrict__ clock, int k) {
+__global__ __launch_bounds__(OPEN_NT) void open_top_kernel(const InstDesc<real>* __restrict__ table,
+                                                           const long long* __restrict__ clock, int k, LaunchWin w) {
+  __shared__ double part[OPEN_NT / 64];
   const InstDesc<real>& D = table[blockIdx.x];
   if (!D.p.open_top) return;
-  const long long t = *clock + k;
-  if (t < D.t_base || t >= D.t_end) return;
-  const bool odd = ((D.b_base + (t - D.t_base)) & 1) != 0;
+  const long long t = (w.use ? w.t : *clock) + k;
+  const long long t_base = w.use ? w.t_base : D.t_base, t_end = w.use ? w.t_end : D.t_end;
+  const int b_base = w.use ? w.b_base : D.b_base;
+  if (t < t_base || t >= t_end) return;
+  const bool odd = ((b_base + (t - t_base)) & 1) != 0;
   const real* __restrict__ fs = odd ? D.fB : D.fA;
   real* __restrict__ fd = odd ? D.fA : D.fB;
   const size_t N = (size_t)D.nx * (size_t)D.ny;
-  for (int x = (int)threadIdx.x; x < D.nx; x += (int)blockDim.x) {
+  double gain = 0.0;
+  for (int x = (int)threadIdx.x; x < D.nx; x += OPEN_NT) {
     const size_t top = (size_t)(D.ny - 1) * (size_t)D.nx + (size_t)x, below = top - (size_t)D.nx;
     real f[9];
 #pragma unroll
@@ -966,19 +994,24 @@ __global__ void open_top_kernel(const InstDesc<real>* __restrict__ table, const 
     const real jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
     real U = jy / rho;
     U = U < real(0) ? real(0) : (U > real(1) ? real(1) : U);
-    fd[4 * N + top] = (f[4] + U * fd[4 * N + below]) / (real(1) + U);
-    fd[7 * N + top] = (f[7] + U * fd[7 * N + below]) / (real(1) + U);
-    fd[8 * N + top] = (f[8] + U * fd[8 * N + below]) / (real(1) + U);
+    const real out = (fd[4 * N + top] + fd[7 * N + top]) + fd[8 * N + top];
+    const real n4 = (f[4] + U * fd[4 * N + below]) / (real(1) + U);
+    const real n7 = (f[7] + U * fd[7 * N + below]) / (real(1) + U);
+    const real n8 = (f[8] + U * fd[8 * N + below]) / (real(1) + U);
+    fd[4 * N + top] = n4;
+    fd[7 * N + top] = n7;
+    fd[8 * N + top] = n8;
+    gain += ((double)n4 + (double)n7 + (double)n8) - (double)out;
   }
-}
-
-template <typename real>
-__global__ void set_window_kernel(InstDesc<real>* d, long long t_base, int b_base, int h_base, long long t_end) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    d->t_base = t_base;
-    d->b_base = b_base;
-    d->h_base = h_base;
-    d->t_end = t_end;
+  for (int s = 32; s > 0; s >>= 1) gain += __shfl_xor(gain, s, 64);
+  if ((threadIdx.x & 63u) == 0u) part[threadIdx.x >> 6] = gain;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double total = 0.0;
+    for (int v = 0; v < OPEN_NT / 64; ++v) total += part[v];
+    const double m = D.live->mass + total;
+    D.live->mass = m;
+    D.live->rho_ave = m / (double)N;
   }
 }
 

@@ -107,7 +107,12 @@ def test_fp64_test_flags(lbm, orc, flags):
 
 def test_static_droplet_full_config_fp64(lbm, orc):
     """Static droplet: periodic 64x64, R = 16, Maxwell densities at 0.86 Tc, FP64, 2000 steps.
-    Bounds: max|drho| <= 1e-9 and max|dT| <= 1e-12."""
+    Bounds: max|drho| <= 1e-9 and max|dT| <= 1e-12.  Mass and energy against the initial mass and the
+    oracle's energy at 1e-12 relative: the collision adds M^-1 dm, whose nine components sum to zero
+    exactly, and each of the nine additions rounds by at most half an ulp of its population, so a
+    node's mass moves by at most about 4.5 unit roundoffs (1.1e-16) per step; over 2000 steps the
+    worst case is 4.5 * 1.1e-16 * 2000 = 1.0e-12 (measured 1.0e-13, so the roundings are partly
+    systematic; the oracle's own 300-step pin at 1e-13 sits inside the same bound)."""
     Tc, rl, rg = _fixtures(orc)
     w = droplet(Tc, rl, rg, nx=64, ny=64, R=16.0, steps=2000)
     s, ref, got, exp, err = _case("static droplet (full)", w, 2000, lbm.LBM_FP64, lbm, orc)
