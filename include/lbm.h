@@ -166,8 +166,25 @@ lbm_status lbm_sync(lbm_ctx* h);
 lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, double* T);
 
 /* Mass sum(rho) and thermal energy sum(rho c_v T) of the current state, accumulated in FP64
-   in a fixed order (deterministic).  Synchronises. */
+   in a fixed order (deterministic; the reduction of lbm_set_diagnostics_interval).  Synchronises. */
 lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy);
+
+/* Diagnostics every k steps, off the step kernel: with k > 0 every later lbm_step enqueues, after
+   each step whose count since lbm_init is a multiple of k, the FP64 reduction of lbm_diagnostics
+   (a thread's nodes, then the 64 lanes of a wavefront by cross-lane shuffles, then the wavefronts,
+   then the per-workgroup partials, each in a fixed order, so the values are deterministic and
+   equal to lbm_diagnostics at that step) as its own kernels on the context's stream; the record
+   (step count, mass, energy) goes to a ring of LBM_DIAG_RING records in the context's device
+   memory, where the oldest are overwritten.  k = 0 stops it.  Either value of k clears the log.
+   LBM_E_INVAL for k < 0. */
+#define LBM_DIAG_RING 256
+lbm_status lbm_set_diagnostics_interval(lbm_ctx* h, int64_t k);
+
+/* The records enqueued since the last call (at most the last LBM_DIAG_RING of them), oldest first,
+   up to max of them, into caller-owned host arrays steps[max], mass[max], energy[max]; *count
+   receives how many.  Synchronises (a numerical failure is reported as by lbm_sync).  LBM_E_INVAL
+   for NULL outputs or max < 0, LBM_E_STATE before lbm_init. */
+lbm_status lbm_read_diagnostics_log(lbm_ctx* h, int64_t* steps, double* mass, double* energy, int max, int* count);
 
 /* Vapour profile of the current state, for the bubble-departure readout of Section 4.3
    (departure diameter against gravity): counts[y] = number of columns x in [x_lo, x_hi)
@@ -255,11 +272,23 @@ int64_t lbm_batch_remaining(const lbm_batch* b, int i);
 lbm_status lbm_batch_set_shape(lbm_batch* b, int k);
 int lbm_batch_get_shape(const lbm_batch* b);
 
+/* Persistent launches (on = 1): each group of launches of the batch (up to the steps captured in one
+   graph replay) becomes one kernel whose workgroups, as many as are resident on the device at once,
+   loop over the tiles of every active instance launch after launch, with a grid barrier between
+   launches (and around the open-top pass of members that have one).  Results are bit-identical to
+   the launch-per-step form (on = 0, the default).  The barrier's wait is bounded by spin_limit
+   polls with a short sleep in between (0: 2^24): a workgroup that waits longer, which can happen
+   when other work keeps part of the grid from being resident, flags the batch and every workgroup
+   leaves the kernel; lbm_batch_sync then marks every member failed with LBM_E_DEVICE.
+   LBM_E_INVAL for on other than 0 or 1. */
+lbm_status lbm_batch_set_persistent(lbm_batch* b, int on, uint32_t spin_limit);
+
 /* Wait for the batch's stream; report per-instance failures in status[n] (may be NULL):
    LBM_E_NUMERIC for a member whose device error word is set (it is parked; returns LBM_E_NUMERIC),
    LBM_OK for the others.  The contexts' step counters and buffer parities are brought up to date.
-   If the wait or a read-back fails, every member is marked failed and parked, status[] holds
-   LBM_E_DEVICE for all of them and the call returns LBM_E_DEVICE. */
+   If the wait or a read-back fails, or a persistent launch's barrier wait timed out, every member
+   is marked failed and parked, status[] holds LBM_E_DEVICE for all of them and the call returns
+   LBM_E_DEVICE. */
 lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status);
 
 /* Release the batch.  The caller-owned memory stays in use until the batch's stream has

@@ -205,6 +205,21 @@ class Solver:
         _check(_native.lib().lbm_diagnostics(self.handle, ctypes.byref(m), ctypes.byref(e)), self.handle)
         return m.value, e.value
 
+    def set_diagnostics_interval(self, k: int):
+        """Record mass and energy every k steps during later step() calls (0: stop); clears the log."""
+        _check(_native.lib().lbm_set_diagnostics_interval(self.handle, int(k)), self.handle)
+        return self
+
+    def diagnostics_log(self, max_records: int = 256):
+        """[(step, mass, energy), ...] recorded since the last call, oldest first."""
+        n = int(max_records)
+        st = (ctypes.c_int64 * n)()
+        m, e = np.empty(n), np.empty(n)
+        c = ctypes.c_int()
+        _check(_native.lib().lbm_read_diagnostics_log(self.handle, st, _dptr(m), _dptr(e), n, ctypes.byref(c)),
+               self.handle)
+        return [(int(st[i]), float(m[i]), float(e[i])) for i in range(c.value)]
+
     def state_bytes(self) -> int:
         return int(_native.lib().lbm_state_bytes(self.handle))
 
@@ -249,15 +264,14 @@ class Batch:
         L = _native.lib()
         self.solvers = list(solvers)
         n = len(self.solvers)
-        nbytes = int(L.lbm_batch_footprint_bytes(n))
-        dev = self.solvers[0].mem.device
-        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.stream = stream if stream is not None else self.solvers[0].stream
-        self.mem.record_stream(self.stream)
         for s in self.solvers:  # the members' memory is also used on the batch's stream
             s.mem.record_stream(self.stream)
         arr = (ctypes.c_void_p * n)(*[s.handle.value for s in self.solvers])
         h = ctypes.c_void_p()
+        nbytes = int(L.lbm_batch_footprint_bytes(n))
+        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.solvers[0].mem.device)
+        self.mem.record_stream(self.stream)
         _check(L.lbm_batch_create(arr, n, ctypes.c_void_p(self.mem.data_ptr()), nbytes,
                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.handle = h
@@ -280,9 +294,16 @@ class Batch:
         _check(_native.lib().lbm_batch_set_shape(self.handle, int(k)))
         return self
 
+    def set_persistent(self, on: bool = True, spin_limit: int = 0):
+        """Launch each group of steps as one persistent kernel with grid barriers (same results);
+        spin_limit bounds each barrier wait (0: the library's default)."""
+        _check(_native.lib().lbm_batch_set_persistent(self.handle, 1 if on else 0, int(spin_limit)))
+        return self
+
     def sync(self):
         """Wait for the batch; per-member status (0, or -4 for a member parked after a numerical
-        failure).  Raises LbmError if the wait itself failed (every member is then failed)."""
+        failure).  Raises LbmError if the wait itself failed or a persistent launch's barrier timed
+        out (every member is then failed)."""
         n = len(self.solvers)
         st = (ctypes.c_int * n)()
         rc = _native.lib().lbm_batch_sync(self.handle, st)
@@ -293,8 +314,9 @@ class Batch:
     def close(self):
         if getattr(self, "handle", None):
             self.stream.synchronize()
-            _native.lib().lbm_batch_destroy(self.handle)
+            rc = _native.lib().lbm_batch_destroy(self.handle)
             self.handle = None
+            _check(rc)
 
     def __del__(self):
         try:

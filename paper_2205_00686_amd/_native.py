@@ -20,10 +20,12 @@ LBM3D_PATH_FUSED, LBM3D_PATH_PER_NODE = 0, 1
 EXPORTS = (
     "lbm_params_default", "lbm_validate", "lbm_footprint_bytes", "lbm_create", "lbm_init", "lbm_step",
     "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_shape_fits", "lbm_set_shape", "lbm_get_shape",
-    "lbm_sync", "lbm_read_fields", "lbm_vapour_rows", "lbm_diagnostics", "lbm_state_bytes", "lbm_save_state",
+    "lbm_sync", "lbm_read_fields", "lbm_vapour_rows", "lbm_diagnostics", "lbm_set_diagnostics_interval",
+    "lbm_read_diagnostics_log", "lbm_state_bytes", "lbm_save_state",
     "lbm_load_state", "lbm_read_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
     "lbm_last_error", "lbm_device_copy", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
     "lbm_batch_remaining", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_sync", "lbm_batch_destroy",
+    "lbm_batch_set_persistent",
     "lbm3d_params_default", "lbm3d_validate", "lbm3d_footprint_bytes", "lbm3d_create", "lbm3d_init", "lbm3d_step",
     "lbm3d_sync", "lbm3d_read_fields", "lbm3d_diagnostics", "lbm3d_steps_done", "lbm3d_state_bytes",
     "lbm3d_save_state", "lbm3d_load_state", "lbm3d_destroy",
@@ -103,6 +105,8 @@ def lib():
         "lbm_read_fields": ([vp, dp, dp, dp, dp], st),
         "lbm_vapour_rows": ([vp, d, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)], st),
         "lbm_diagnostics": ([vp, dp, dp], st),
+        "lbm_set_diagnostics_interval": ([vp, i64], st),
+        "lbm_read_diagnostics_log": ([vp, ctypes.POINTER(ctypes.c_int64), dp, dp, ctypes.c_int, ip], st),
         "lbm_state_bytes": ([vp], sz),
         "lbm_save_state": ([vp, vp, sz], st),
         "lbm_load_state": ([vp, vp, sz], st),
@@ -122,6 +126,7 @@ def lib():
         "lbm_batch_get_shape": ([vp], ctypes.c_int),
         "lbm_batch_sync": ([vp, ctypes.POINTER(ctypes.c_int)], st),
         "lbm_batch_destroy": ([vp], st),
+        "lbm_batch_set_persistent": ([vp, ctypes.c_int, ctypes.c_uint32], st),
         "lbm3d_params_default": ([P3, i32, i32, i32], None),
         "lbm3d_validate": ([P3], st),
         "lbm3d_footprint_bytes": ([P3], sz),

@@ -31,7 +31,10 @@ constexpr size_t OFF_CLOCK = 4096;    // long long
 constexpr size_t OFF_ERR = 4352;      // unsigned
 constexpr size_t OFF_DIAG = 4608;     // 2 doubles
 constexpr size_t OFF_LIVE = 4864;     // InstLive: FP64 mass and the current rho_ave
-constexpr size_t OFF_PART = 8192;     // partial sums follow the control block
+constexpr size_t OFF_RING = 8192;     // ring of DIAG_RING diagnostics records (every-k diagnostics)
+constexpr int DIAG_RING = 256;
+static_assert(OFF_RING + DIAG_RING * sizeof(DiagRecord) <= CTRL_BYTES, "control block layout");
+// the reduction partials follow the control block
 
 size_t partial_bytes() { return align_up((size_t)MAX_RED_BLOCKS * 2 * sizeof(double)); }
 
@@ -122,6 +125,10 @@ struct lbm_ctx {
   int shape = 0;       // tile shape in use
   int ntiles = 0;
   InstLive live0{};      // staging of the live values written at init / load (outlives the copy)
+  DiagRecord* d_ring = nullptr;  // every-k diagnostics records (control block)
+  int64_t diag_every = 0;        // 0: no periodic diagnostics
+  int64_t diag_enqueued = 0;     // records enqueued since lbm_set_diagnostics_interval
+  int64_t diag_read = 0;         // records returned by lbm_read_diagnostics_log
   hipGraphExec_t graph = nullptr;
   std::string last_error;
 };
@@ -145,6 +152,11 @@ struct lbm_batch {
   hipGraphExec_t graph = nullptr;
   std::vector<lbm_ctx*> graph_layout;  // active instances (in table order) the graph was captured for
   int graph_shape = -1;                // tile shape the graph was captured with
+  GridBar* d_bar = nullptr;            // grid barrier of the persistent launches (batch memory)
+  bool persistent = false;             // launches as one persistent kernel per group of steps
+  bool persistent_used = false;        // a persistent launch has been enqueued since the last sync
+  unsigned spin_limit = 1u << 24;      // bounded wait of the persistent kernel's grid barrier
+  int pgrid = 0, pgrid_shape = -1;     // resident workgroups of the persistent kernel (for shape)
 };
 
 // Orders the batch stream after every member's stream: one event recorded on each distinct
@@ -321,6 +333,43 @@ static void launch_shape(int qg, int grid, hipStream_t st, const void* table, in
 // Window of launches that read the device clock and the descriptors (graph replays, batches).
 constexpr LaunchWin FROM_CLOCK{0, 0, 0, 0, 0, 0};
 
+// Persistent kernel of shape S: one launch of nl launch steps, or (grid = 0) the number of its
+// workgroups that fit on one compute unit at once.
+template <typename real, class S>
+static int persist_shape(int qg, int grid, hipStream_t st, const void* table, int ninst, const long long* clk,
+                         int total_tiles, int nl, int open, GridBar* bar, unsigned spin) {
+  const InstDesc<real>* t = (const InstDesc<real>*)table;
+  int nb = 0;
+  if (qg == 9) {
+    if constexpr (S::DEPTH == 1) {
+      if (grid == 0) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel<real, S, 9>, S::NT, 0);
+      else persist_kernel<real, S, 9><<<grid, S::NT, 0, st>>>(t, ninst, clk, total_tiles, nl, open, bar, spin);
+    }
+  } else {
+    if (grid == 0) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persist_kernel<real, S, 5>, S::NT, 0);
+    else persist_kernel<real, S, 5><<<grid, S::NT, 0, st>>>(t, ninst, clk, total_tiles, nl, open, bar, spin);
+  }
+  return nb;
+}
+
+static int persist_step(int precision, int qg, int shape, int grid, hipStream_t st, const void* table, int ninst,
+                        const long long* clk, int total_tiles, int nl, int open, GridBar* bar, unsigned spin) {
+#define LBM_PERSIST_F32(kk, ty, w, d) \
+  case kk:                            \
+    return persist_shape<float, Shape<ty, w, d>>(qg, grid, st, table, ninst, clk, total_tiles, nl, open, bar, spin);
+#define LBM_PERSIST_F64(kk, ty, w, d) \
+  case kk:                            \
+    return persist_shape<double, Shape<ty, w, d>>(qg, grid, st, table, ninst, clk, total_tiles, nl, open, bar, spin);
+  if (precision == LBM_FP64) {
+    switch (shape) { LBM_F64_SHAPES(LBM_PERSIST_F64) default: break; }
+  } else {
+    switch (shape) { LBM_F32_SHAPES(LBM_PERSIST_F32) default: break; }
+  }
+#undef LBM_PERSIST_F32
+#undef LBM_PERSIST_F64
+  return 0;
+}
+
 // ------------------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -409,6 +458,7 @@ lbm_status lbm_create(const lbm_params* p, void* dev_mem, size_t bytes, void* hi
   h->d_err = (unsigned*)(q + OFF_ERR);
   h->d_diag = (double*)(q + OFF_DIAG);
   h->d_live = (InstLive*)(q + OFF_LIVE);
+  h->d_ring = (DiagRecord*)(q + OFF_RING);
   q += CTRL_BYTES;
   h->d_part = (double*)q;
   q += partial_bytes();
@@ -572,16 +622,11 @@ static lbm_status build_graph(lbm_ctx* h) {
   return LBM_OK;
 }
 
-lbm_status lbm_step(lbm_ctx* h, int64_t n) {
-  if (!h || n < 0) return LBM_E_INVAL;
-  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_step before lbm_init");
-  if (h->failed) return fail(h, LBM_E_STATE, "context has failed: " + h->last_error);
-  if (n == 0) return LBM_OK;
-  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
-  // this call's window: steps [clock, clock + n) from the current buffers; a launch of a
-  // two-step shape does one step where only one is left.  Whole groups of GRAPH_STEPS steps are
-  // graph replays, which read the window and the clock from device memory (set by one small kernel
-  // per call); the remaining launches take the window as an argument.
+// n steps from the current state as one step window: steps [clock, clock + n) from the current
+// buffers; a launch of a two-step shape does one step where only one is left.  Whole groups of
+// GRAPH_STEPS steps are graph replays, which read the window and the clock from device memory (set
+// by one small kernel per window); the remaining launches take the window as an argument.
+static lbm_status step_window(lbm_ctx* h, int64_t n) {
   const int d = shape_def(h->prm.precision, h->shape).depth;
   const int64_t launches = (n + d - 1) / d;
   const int64_t per_graph = GRAPH_STEPS / d;
@@ -611,6 +656,32 @@ lbm_status lbm_step(lbm_ctx* h, int64_t n) {
   h->steps += n;
   h->gen ^= (int)(launches & 1);
   h->hgen ^= (int)(history_moves(n, d) & 1);
+  return LBM_OK;
+}
+
+static lbm_status enqueue_diagnostics(lbm_ctx* h, DiagRecord* rec);
+
+lbm_status lbm_step(lbm_ctx* h, int64_t n) {
+  if (!h || n < 0) return LBM_E_INVAL;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_step before lbm_init");
+  if (h->failed) return fail(h, LBM_E_STATE, "context has failed: " + h->last_error);
+  if (n == 0) return LBM_OK;
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  if (h->diag_every <= 0) return step_window(h, n);
+  // every-k diagnostics: windows that end at the multiples of k, each followed by the reduction
+  // into the next slot of the ring
+  while (n > 0) {
+    const int64_t to_mark = h->diag_every - h->steps % h->diag_every;
+    const int64_t m = std::min(n, to_mark);
+    lbm_status s = step_window(h, m);
+    if (s != LBM_OK) return s;
+    n -= m;
+    if (h->steps % h->diag_every == 0) {
+      s = enqueue_diagnostics(h, h->d_ring + h->diag_enqueued % DIAG_RING);
+      if (s != LBM_OK) return s;
+      ++h->diag_enqueued;
+    }
+  }
   return LBM_OK;
 }
 
@@ -704,10 +775,9 @@ lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, doub
   return check_device_error(h);
 }
 
-lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy) {
-  if (!h) return LBM_E_INVAL;
-  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_diagnostics before lbm_init");
-  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+// The FP64 mass and energy reduction of the current state on the context's stream: result in
+// d_diag and, if rec is not null, as a record of the current step count at *rec.
+static lbm_status enqueue_diagnostics(lbm_ctx* h, DiagRecord* rec) {
   void *f, *g, *fo;
   current_buffers(h, f, g, fo);
   const size_t N = h->N;
@@ -720,13 +790,52 @@ lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy) {
   else
     diag_partial_kernel<float><<<nparts, RED_NT, 0, h->stream>>>(
         (const float*)f, (const float*)g, N, qg_of(&h->prm), h->prm.cv, h->T_ref, per, h->d_part);
-  diag_final_kernel<<<1, RED_NT, 0, h->stream>>>(h->d_part, nparts, h->d_diag);
+  diag_final_kernel<<<1, RED_NT, 0, h->stream>>>(h->d_part, nparts, h->d_diag, rec, (long long)h->steps);
   HIP_OR_FAIL(h, hipGetLastError());
+  return LBM_OK;
+}
+
+lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy) {
+  if (!h) return LBM_E_INVAL;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_diagnostics before lbm_init");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  lbm_status st = enqueue_diagnostics(h, nullptr);
+  if (st != LBM_OK) return st;
   double out[2];
   HIP_OR_FAIL(h, hipMemcpyAsync(out, h->d_diag, sizeof(out), hipMemcpyDeviceToHost, h->stream));
   HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
   if (mass) *mass = out[0];
   if (energy) *energy = out[1];
+  return check_device_error(h);
+}
+
+lbm_status lbm_set_diagnostics_interval(lbm_ctx* h, int64_t k) {
+  if (!h || k < 0) return LBM_E_INVAL;
+  h->diag_every = k;
+  h->diag_enqueued = 0;
+  h->diag_read = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_read_diagnostics_log(lbm_ctx* h, int64_t* steps, double* mass, double* energy, int max, int* count) {
+  if (!h || !count || max < 0 || (max > 0 && (!steps || !mass || !energy))) return LBM_E_INVAL;
+  *count = 0;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_read_diagnostics_log before lbm_init");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  DiagRecord ring[DIAG_RING];
+  HIP_OR_FAIL(h, hipMemcpyAsync(ring, h->d_ring, sizeof(ring), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  // records still in the ring: the last DIAG_RING enqueued; older unread ones were overwritten
+  int64_t first = std::max(h->diag_read, h->diag_enqueued - DIAG_RING);
+  int c = 0;
+  for (int64_t r = first; r < h->diag_enqueued && c < max; ++r, ++c) {
+    const DiagRecord& d = ring[r % DIAG_RING];
+    steps[c] = d.step;
+    mass[c] = d.mass;
+    energy[c] = d.energy;
+  }
+  h->diag_read = first + c;
+  *count = c;
   return check_device_error(h);
 }
 
@@ -1026,6 +1135,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   b->base = (char*)dev_mem;
   b->bytes = bytes;
   b->d_clock = (long long*)b->base;
+  b->d_bar = (GridBar*)(b->base + 64);
   b->d_table = b->base + ALIGN;
   *out = b;
   return LBM_OK;
@@ -1054,6 +1164,17 @@ lbm_status lbm_batch_set_shape(lbm_batch* b, int k) {
 }
 
 int lbm_batch_get_shape(const lbm_batch* b) { return b ? b->shape : -1; }
+
+lbm_status lbm_batch_set_persistent(lbm_batch* b, int on, uint32_t spin_limit) {
+  if (!b || (on != 0 && on != 1)) return LBM_E_INVAL;
+  b->persistent = on != 0;
+  b->spin_limit = spin_limit ? spin_limit : (1u << 24);
+  if (b->graph) {  // the captured launches change form
+    (void)hipGraphExecDestroy(b->graph);
+    b->graph = nullptr;
+  }
+  return LBM_OK;
+}
 
 }  // extern "C"
 
@@ -1127,12 +1248,40 @@ static lbm_status batch_upload(lbm_batch* b, int64_t todo) {
   return LBM_OK;
 }
 
-// nl launches of the batch's step kernel, then the clock advance by the steps they span
+// Workgroups of the batch's persistent kernel: as many as are resident at once on the device
+// (a multiple of the 8 XCDs), and no more than the tiles need.
+static lbm_status persistent_grid(lbm_batch* b, int* grid) {
+  if (b->pgrid_shape != b->shape) {
+    int cus = 0;
+    HIP_OR_FAIL(b->ctx[0], hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->ctx[0]->device));
+    const int per_cu = persist_step(b->precision, b->qg, b->shape, 0, nullptr, nullptr, 0, nullptr, 0, 0, 0, nullptr, 0);
+    b->pgrid = per_cu * cus / NXCD * NXCD;
+    b->pgrid_shape = b->shape;
+    if (b->pgrid < NXCD) return fail(b->ctx[0], LBM_E_DEVICE, "persistent kernel: no resident workgroups");
+  }
+  *grid = std::min(b->pgrid, (b->total_tiles + NXCD - 1) / NXCD * NXCD);
+  return LBM_OK;
+}
+
+// nl launches of the batch's step kernel (or one persistent kernel doing them), then the clock
+// advance by the steps they span
 static lbm_status batch_launch(lbm_batch* b, int nl) {
   const int n = (int)b->ctx.size();
   const int d = shape_def(b->precision, b->shape).depth;
   bool open = false;
   for (const lbm_ctx* h : b->ctx) open = open || (h->prm.y_walls && h->prm.open_top);
+  if (b->persistent) {
+    int grid = 0;
+    lbm_status st = persistent_grid(b, &grid);
+    if (st != LBM_OK) return st;
+    grid_bar_reset_kernel<<<1, 64, 0, b->stream>>>(b->d_bar);
+    persist_step(b->precision, b->qg, b->shape, grid, b->stream, b->d_table, n, b->d_clock, b->total_tiles, nl,
+                 open ? 1 : 0, b->d_bar, b->spin_limit);
+    clock_advance_kernel<<<1, 64, 0, b->stream>>>(b->d_clock, (long long)nl * d);
+    HIP_OR_FAIL(b->ctx[0], hipGetLastError());
+    b->persistent_used = true;
+    return LBM_OK;
+  }
   for (int s = 0; s < nl; ++s) {
     launch_step(b->precision, b->qg, b->shape, b->total_tiles, b->stream, b->d_table, n, b->d_clock, s, FROM_CLOCK);
     if (open) launch_open_top(b->precision, n, b->stream, b->d_table, b->d_clock, s, FROM_CLOCK);
@@ -1219,6 +1368,21 @@ lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status) {
   };
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return device_failure(b->ctx[0], "hipStreamSynchronize", e);
+  if (b->persistent_used) {
+    GridBar bar{};
+    e = hipMemcpy(&bar, b->d_bar, sizeof(bar), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_failure(b->ctx[0], "hipMemcpy", e);
+    b->persistent_used = false;
+    if (bar.abort) {
+      for (size_t i = 0; i < n; ++i) {
+        b->ctx[i]->failed = true;
+        b->ctx[i]->last_error = "batched run: a grid barrier wait of the persistent kernel timed out";
+        b->remaining[i] = 0;
+        if (status) status[i] = LBM_E_DEVICE;
+      }
+      return fail(b->ctx[0], LBM_E_DEVICE, "persistent kernel: a grid barrier wait timed out");
+    }
+  }
   lbm_status worst = LBM_OK;
   for (size_t i = 0; i < n; ++i) {
     lbm_ctx* h = b->ctx[i];

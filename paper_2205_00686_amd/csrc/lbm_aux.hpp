@@ -142,16 +142,46 @@ __global__ __launch_bounds__(VAP_NT) void vapour_rows_kernel(const real* __restr
   }
 }
 
-// Deterministic FP64 sums of rho and rho c_v T: each workgroup reduces a fixed contiguous
-// range in a fixed tree order into partials[2*block], a second single-workgroup pass adds the
-// partials in a fixed tree order.
+// Deterministic FP64 sums of rho and rho c_v T (mass and thermal energy).  Three levels, each in a
+// fixed order: a thread adds its nodes of the workgroup's contiguous range; a wavefront adds its
+// 64 lanes by a butterfly of cross-lane shuffles (every lane ends with the same sum, the two
+// operands of each addition being the same values in either order); the workgroup's wavefronts
+// are added in index order from LDS.  A second single-workgroup pass adds the per-workgroup
+// partials the same way.  The result depends only on N and the range split, not on scheduling.
 constexpr int RED_NT = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int s = 32; s > 0; s >>= 1) v += __shfl_xor(v, s, 64);
+  return v;
+}
+
+// Sum over the workgroup of (m, e); the result is valid in thread 0.
+__device__ __forceinline__ void block_sum2(double& m, double& e) {
+  __shared__ double wm[RED_NT / 64], we[RED_NT / 64];
+  m = wave_sum(m);
+  e = wave_sum(e);
+  const int w = (int)threadIdx.x >> 6;
+  if ((threadIdx.x & 63u) == 0u) {
+    wm[w] = m;
+    we[w] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = wm[0];
+    e = we[0];
+#pragma unroll
+    for (int k = 1; k < RED_NT / 64; ++k) {
+      m += wm[k];
+      e += we[k];
+    }
+  }
+}
 
 template <typename real>
 __global__ __launch_bounds__(RED_NT) void diag_partial_kernel(const real* __restrict__ f, const real* __restrict__ g,
                                                               size_t N, int qg, double cv, double T_ref,
                                                               size_t per_block, double* __restrict__ partials) {
-  __shared__ double sm[RED_NT], se[RED_NT];
   const size_t begin = (size_t)blockIdx.x * per_block;
   const size_t end = begin + per_block < N ? begin + per_block : N;
   double m = 0.0, e = 0.0;
@@ -161,43 +191,35 @@ __global__ __launch_bounds__(RED_NT) void diag_partial_kernel(const real* __rest
     m += (double)rho;
     e += (double)rho * cv * (T_ref + (double)Tr);
   }
-  sm[threadIdx.x] = m;
-  se[threadIdx.x] = e;
-  __syncthreads();
-  for (int s = RED_NT / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      sm[threadIdx.x] += sm[threadIdx.x + s];
-      se[threadIdx.x] += se[threadIdx.x + s];
-    }
-    __syncthreads();
-  }
+  block_sum2(m, e);
   if (threadIdx.x == 0) {
-    partials[2 * blockIdx.x] = sm[0];
-    partials[2 * blockIdx.x + 1] = se[0];
+    partials[2 * blockIdx.x] = m;
+    partials[2 * blockIdx.x + 1] = e;
   }
 }
 
+// One diagnostics record: the step count it belongs to, mass and energy.
+struct DiagRecord {
+  long long step;
+  double mass;
+  double energy;
+};
+
+// Adds the partials; writes mass and energy to out[0], out[1] and, if rec is not null, the record
+// (step, mass, energy) to *rec.
 __global__ __launch_bounds__(RED_NT) void diag_final_kernel(const double* __restrict__ partials, int nparts,
-                                                            double* __restrict__ out) {
-  __shared__ double sm[RED_NT], se[RED_NT];
+                                                            double* __restrict__ out, DiagRecord* __restrict__ rec,
+                                                            long long step) {
   double m = 0.0, e = 0.0;
   for (int k = threadIdx.x; k < nparts; k += RED_NT) {
     m += partials[2 * k];
     e += partials[2 * k + 1];
   }
-  sm[threadIdx.x] = m;
-  se[threadIdx.x] = e;
-  __syncthreads();
-  for (int s = RED_NT / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      sm[threadIdx.x] += sm[threadIdx.x + s];
-      se[threadIdx.x] += se[threadIdx.x + s];
-    }
-    __syncthreads();
-  }
+  block_sum2(m, e);
   if (threadIdx.x == 0) {
-    out[0] = sm[0];
-    out[1] = se[0];
+    out[0] = m;
+    out[1] = e;
+    if (rec) *rec = DiagRecord{step, m, e};
   }
 }
 

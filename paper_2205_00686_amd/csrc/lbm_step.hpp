@@ -851,24 +851,20 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
   __syncthreads();  // state complete; the fields of the first step are dead (m2 aliases them)
 }
 
-// ------------------------------------------------------------------------- kernel
+// ------------------------------------------------------------------------- kernels
 
-// One workgroup per tile.  A launch of shape S advances every active instance by S::DEPTH steps
-// (one step if only one is left in its budget).  The device clock counts steps; the launch's
-// step is t = clock + k DEPTH.  Each launch swaps the A/B buffers once, so the source buffer is
-// B exactly when b_base plus the number of launches since t_base is odd.
+// LDS of one workgroup of shape S: the two-step state, or the one-step fields
 template <typename real, class S, int QG>
-__global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __restrict__ table, int ninst,
-                                                     const long long* __restrict__ clock, int k, LaunchWin w) {
-  static_assert(QG == 5 || (QG == 9 && S::DEPTH == 1), "D2Q9 thermal populations: one step per launch");
-  // ---- which simulation and which tile (uniform per workgroup).  Workgroups are dispatched to
-  // the 8 XCDs round-robin; remap so that each XCD takes a contiguous range of tiles: neighbouring
-  // tiles then share one L2, where their halo reads hit and where the partial cache lines of the
-  // shifted (pushed) stores of two neighbours are merged before they are written back.
-  const int nwg = gridDim.x;
-  const int xcd = blockIdx.x % NXCD;
-  const int per = nwg / NXCD, rem = nwg % NXCD;
-  const int bid = xcd * per + (xcd < rem ? xcd : rem) + blockIdx.x / NXCD;
+using TileLds = typename std::conditional<S::DEPTH == 2, Step2Lds<real, S>, StepLds<real, S::EYW, QG>>::type;
+
+// One tile of one launch: tile bid of the launch's tile range at step t (the launch does S::DEPTH
+// steps, one where only one is left in the instance's window).  Each launch swaps the A/B buffers
+// once, so the source buffer is B exactly when b_base plus the number of launches since t_base is
+// odd.  Returns at once for a tile outside every active instance or outside its window (uniform per
+// workgroup).
+template <typename real, class S, int QG>
+__device__ __forceinline__ void step_tile(const InstDesc<real>* __restrict__ table, int ninst, long long t,
+                                          const LaunchWin& w, int bid, TileLds<real, S, QG>& lds) {
   int lo = 0, hi = ninst - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -876,9 +872,7 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
     else hi = mid - 1;
   }
   const InstDesc<real>& D = table[lo];
-  // step window: from the arguments (single runs launched directly) or from the device clock and
-  // the descriptor (graph replays, batches)
-  const long long t = (w.use ? w.t : *clock) + (long long)k * S::DEPTH;
+  // step window: from the arguments (single runs launched directly) or from the descriptor
   const long long t_base = w.use ? w.t_base : D.t_base, t_end = w.use ? w.t_end : D.t_end;
   const int b_base = w.use ? w.b_base : D.b_base, h_base = w.use ? w.h_base : D.h_base;
   if (t < t_base || t >= t_end) return;
@@ -898,7 +892,7 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
   const int gv = general_variant(D.p.thermal_box, D.p.y_walls);
   const LdsState<real, S> none{};
   if constexpr (S::DEPTH == 2) {
-    __shared__ Step2Lds<real, S> L2;
+    Step2Lds<real, S>& L2 = lds;
     if (t_end - t >= 2) {
       real Tn1[S::RPT], Tn2[S::RPT];
       const bool interior2 =
@@ -913,7 +907,7 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
       else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false>(D, L2.m2, odd, hodd, x0, y0, none, err); });
     }
   } else {
-    __shared__ StepLds<real, S::EYW, QG> L;
+    StepLds<real, S::EYW, QG>& L = lds;
     if (interior) step_body<real, S, 0, false, QG>(D, L, odd, hodd, x0, y0, none, err);
     else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false, QG>(D, L, odd, hodd, x0, y0, none, err); });
   }
@@ -927,6 +921,26 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
     const unsigned held = __hip_atomic_load(D.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if ((held & bits) != bits) atomicOr(D.err, bits);
   }
+}
+
+// One workgroup per tile.  A launch of shape S advances every active instance by S::DEPTH steps
+// (one step if only one is left in its budget).  The device clock counts steps; launch k of a group
+// does step t = clock + k DEPTH (or w.t + k DEPTH with the window in the arguments).
+template <typename real, class S, int QG>
+__global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __restrict__ table, int ninst,
+                                                     const long long* __restrict__ clock, int k, LaunchWin w) {
+  static_assert(QG == 5 || (QG == 9 && S::DEPTH == 1), "D2Q9 thermal populations: one step per launch");
+  // ---- which tile (uniform per workgroup).  Workgroups are dispatched to the 8 XCDs round-robin;
+  // remap so that each XCD takes a contiguous range of tiles: neighbouring tiles then share one L2,
+  // where their halo reads hit and where the partial cache lines of the shifted (pushed) stores of
+  // two neighbours are merged before they are written back.
+  const int nwg = gridDim.x;
+  const int xcd = blockIdx.x % NXCD;
+  const int per = nwg / NXCD, rem = nwg % NXCD;
+  const int bid = xcd * per + (xcd < rem ? xcd : rem) + blockIdx.x / NXCD;
+  const long long t = (w.use ? w.t : *clock) + (long long)k * S::DEPTH;
+  __shared__ TileLds<real, S, QG> lds;
+  step_tile<real, S, QG>(table, ninst, t, w, bid, lds);
 }
 
 // Tile shapes compiled into the library, per precision: (tile height, wavefronts, steps per
@@ -970,13 +984,13 @@ __global__ void set_window_kernel(InstDesc<real>* d, long long* clock, long long
 // stride over the columns.
 constexpr int OPEN_NT = 256;
 
+// The open-top pass for one table entry D after the step at t, by the first OPEN_NT threads of the
+// workgroup (the others wait at its barriers), so that the order of its sums does not depend on
+// the workgroup size.  part: OPEN_NT / 64 doubles of LDS.
 template <typename real>
-__global__ __launch_bounds__(OPEN_NT) void open_top_kernel(const InstDesc<real>* __restrict__ table,
-                                                           const long long* __restrict__ clock, int k, LaunchWin w) {
-  __shared__ double part[OPEN_NT / 64];
-  const InstDesc<real>& D = table[blockIdx.x];
+__device__ __forceinline__ void open_top_body(const InstDesc<real>& D, long long t, const LaunchWin& w,
+                                              double* part) {
   if (!D.p.open_top) return;
-  const long long t = (w.use ? w.t : *clock) + k;
   const long long t_base = w.use ? w.t_base : D.t_base, t_end = w.use ? w.t_end : D.t_end;
   const int b_base = w.use ? w.b_base : D.b_base;
   if (t < t_base || t >= t_end) return;
@@ -984,8 +998,9 @@ __global__ __launch_bounds__(OPEN_NT) void open_top_kernel(const InstDesc<real>*
   const real* __restrict__ fs = odd ? D.fB : D.fA;
   real* __restrict__ fd = odd ? D.fA : D.fB;
   const size_t N = (size_t)D.nx * (size_t)D.ny;
+  const bool active = threadIdx.x < (unsigned)OPEN_NT;
   double gain = 0.0;
-  for (int x = (int)threadIdx.x; x < D.nx; x += OPEN_NT) {
+  for (int x = (int)threadIdx.x; active && x < D.nx; x += OPEN_NT) {
     const size_t top = (size_t)(D.ny - 1) * (size_t)D.nx + (size_t)x, below = top - (size_t)D.nx;
     real f[9];
 #pragma unroll
@@ -1004,7 +1019,7 @@ __global__ __launch_bounds__(OPEN_NT) void open_top_kernel(const InstDesc<real>*
     gain += ((double)n4 + (double)n7 + (double)n8) - (double)out;
   }
   for (int s = 32; s > 0; s >>= 1) gain += __shfl_xor(gain, s, 64);
-  if ((threadIdx.x & 63u) == 0u) part[threadIdx.x >> 6] = gain;
+  if (active && (threadIdx.x & 63u) == 0u) part[threadIdx.x >> 6] = gain;
   __syncthreads();
   if (threadIdx.x == 0) {
     double total = 0.0;
@@ -1012,6 +1027,101 @@ __global__ __launch_bounds__(OPEN_NT) void open_top_kernel(const InstDesc<real>*
     const double m = D.live->mass + total;
     D.live->mass = m;
     D.live->rho_ave = m / (double)N;
+  }
+  __syncthreads();
+}
+
+// Open top boundary, after the step of launch k of a one-step shape: the populations that enter
+// the top row N from outside (c_y = -1) follow the convective outflow condition
+//   f_i(x, N, t+1) = [f_i(x, N, t) + U f_i(x, N-1, t+1)] / (1 + U),
+// U = j_y / rho of the top node at time t clipped to [0, 1].  f(t) is in the step's source
+// buffers, f(t+1) of row N-1 in its destination buffers.  The step kernel has left the outgoing
+// populations of the top row (c_y = +1) in the slots of the entering ones; their sum, subtracted
+// from that of the entering values, is the mass the domain gains through the top in this step,
+// added to the instance's FP64 mass in a fixed order (per-thread column sums, then the lanes and
+// wavefronts in a fixed tree), so rho_ave follows the mean density.  Workgroup b serves table
+// entry b (entries without an open top, or outside their window, return at once); its threads
+// stride over the columns.
+template <typename real>
+__global__ __launch_bounds__(OPEN_NT) void open_top_kernel(const InstDesc<real>* __restrict__ table,
+                                                           const long long* __restrict__ clock, int k, LaunchWin w) {
+  __shared__ double part[OPEN_NT / 64];
+  const long long t = (w.use ? w.t : *clock) + k;
+  open_top_body<real>(table[blockIdx.x], t, w, part);
+}
+
+// ------------------------------------------------------------------------- persistent batches
+
+// Grid barrier of a persistent launch.  count grows by one per workgroup and barrier and is
+// cleared before each launch, so barrier j is complete when it reaches G (j + 1).  The wait is
+// bounded: a workgroup that has spun spin_limit times (or sees another one give up) sets abort and
+// returns false, and every workgroup then leaves the kernel, so a launch whose workgroups are not
+// all resident at once ends with abort set instead of hanging.
+struct GridBar {
+  unsigned count;
+  unsigned abort;
+};
+
+__device__ __forceinline__ bool grid_barrier(GridBar* bar, unsigned target, unsigned spin_limit) {
+  __shared__ unsigned ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();  // release: this workgroup's stores are visible before its arrival
+    __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned spins = 0u, good = 1u;
+    while (__hip_atomic_load(&bar->count, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins >= spin_limit) {
+        __hip_atomic_store(&bar->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        good = 0u;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __threadfence();  // acquire: the other workgroups' stores are visible to this one's loads
+    ok = good;
+  }
+  __syncthreads();
+  return ok != 0u;
+}
+
+// Clears the barrier before a persistent launch (a kernel, so that it can live in a graph).
+__global__ void grid_bar_reset_kernel(GridBar* bar) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    bar->count = 0u;
+    bar->abort = 0u;
+  }
+}
+
+// nlaunch launches of shape S in one kernel: the workgroups (all resident, gridDim.x a multiple of
+// the 8 XCDs) loop over the tiles of every active instance for one launch's steps, meet at a grid
+// barrier, run the open-top pass of the entries that have one (then meet again), and go on with the
+// next launch.  Each XCD's workgroups take a contiguous band of tiles, as the remap of step_kernel
+// does.  Every node's arithmetic is that of step_kernel, so results are bit-identical to nlaunch
+// launches of it.
+template <typename real, class S, int QG>
+__global__ __launch_bounds__(S::NT) void persist_kernel(const InstDesc<real>* __restrict__ table, int ninst,
+                                                        const long long* __restrict__ clock, int total_tiles,
+                                                        int nlaunch, int open, GridBar* bar, unsigned spin_limit) {
+  __shared__ TileLds<real, S, QG> lds;
+  __shared__ double part[OPEN_NT / 64];
+  const long long c0 = *clock;
+  const int G = gridDim.x;
+  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD, gx = G / NXCD;
+  const int band = (total_tiles + NXCD - 1) / NXCD;
+  const int b0 = xcd * band, b1 = min(total_tiles, b0 + band);
+  const LaunchWin w{0, 0, 0, 0, 0, 0};
+  unsigned nbar = 0u;
+  for (int L = 0; L < nlaunch; ++L) {
+    const long long t = c0 + (long long)L * S::DEPTH;
+    for (int bid = b0 + slot; bid < b1; bid += gx) {
+      step_tile<real, S, QG>(table, ninst, t, w, bid, lds);
+      __syncthreads();  // the next tile reuses the LDS
+    }
+    if (!grid_barrier(bar, (unsigned)G * ++nbar, spin_limit)) return;
+    if (open) {
+      for (int i = blockIdx.x; i < ninst; i += G) open_top_body<real>(table[i], t, w, part);
+      if (!grid_barrier(bar, (unsigned)G * ++nbar, spin_limit)) return;
+    }
   }
 }
 
