@@ -292,8 +292,25 @@ lbm_status lbm_batch_set_persistent(lbm_batch* b, int on, uint32_t spin_limit);
 lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status);
 
 /* Release the batch.  The caller-owned memory stays in use until the batch's stream has
-   drained.  The members are not touched, so they may be destroyed before the batch. */
+   drained.  The members are not touched, so they may be destroyed before the batch.  A batch made
+   by lbm_batch_create_noalloc first waits for its stream (LBM_E_DEVICE if that wait fails), then
+   frees its device's static area for the next such batch. */
 lbm_status lbm_batch_destroy(lbm_batch* b);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+   loops, harnesses that forbid allocation): lbm_batch_create without the caller's table memory.
+   The batch's instance table and clock live in a static device array of the library instead, one
+   per device, sized for LBM_BATCH_NOALLOC_MAX instances (about 120 KiB, held by each device the
+   library runs on until the process ends).  Everything else is as lbm_batch_create, and the batch
+   gives the same results.  The members must be on the current device.  One such batch may exist
+   per device at a time: LBM_E_STATE while another one does (lbm_batch_destroy releases it).  The
+   area keeps the last batch's table; every lbm_batch_step rewrites it before its launches, so
+   nothing has to be cleared, but work on one device that reaches the area by other means while a
+   batch uses it races.  LBM_E_INVAL for n outside [1, LBM_BATCH_NOALLOC_MAX], a NULL or
+   foreign-device member; LBM_E_DEVICE if the area's device address cannot be obtained.  Allocates
+   no device memory (host metadata only, as lbm_batch_create). */
+#define LBM_BATCH_NOALLOC_MAX 256
+lbm_status lbm_batch_create_noalloc(lbm_ctx* const* ctxs, int n, void* hip_stream, lbm_batch** out);
 
 #ifdef __cplusplus
 }

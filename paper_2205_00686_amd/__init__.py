@@ -256,9 +256,11 @@ class Solver:
 
 class Batch:
     """Many initialised Solvers (same precision) advanced together: one kernel launch per step
-    covers the tiles of every instance with budget left."""
+    covers the tiles of every instance with budget left.  noalloc=True: the batch's table lives in
+    the library's static per-device area (lbm_batch_create_noalloc) instead of a torch allocation;
+    one such batch per device at a time."""
 
-    def __init__(self, solvers, stream=None):
+    def __init__(self, solvers, stream=None, noalloc: bool = False):
         import torch
 
         L = _native.lib()
@@ -269,11 +271,15 @@ class Batch:
             s.mem.record_stream(self.stream)
         arr = (ctypes.c_void_p * n)(*[s.handle.value for s in self.solvers])
         h = ctypes.c_void_p()
-        nbytes = int(L.lbm_batch_footprint_bytes(n))
-        self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.solvers[0].mem.device)
-        self.mem.record_stream(self.stream)
-        _check(L.lbm_batch_create(arr, n, ctypes.c_void_p(self.mem.data_ptr()), nbytes,
-                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        if noalloc:
+            self.mem = None
+            _check(L.lbm_batch_create_noalloc(arr, n, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        else:
+            nbytes = int(L.lbm_batch_footprint_bytes(n))
+            self.mem = torch.empty(nbytes, dtype=torch.uint8, device=self.solvers[0].mem.device)
+            self.mem.record_stream(self.stream)
+            _check(L.lbm_batch_create(arr, n, ctypes.c_void_p(self.mem.data_ptr()), nbytes,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self.handle = h
 
     def set_budget(self, i: int, steps: int):

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -152,6 +153,7 @@ struct lbm_batch {
   hipGraphExec_t graph = nullptr;
   std::vector<lbm_ctx*> graph_layout;  // active instances (in table order) the graph was captured for
   int graph_shape = -1;                // tile shape the graph was captured with
+  int noalloc_device = -1;             // device whose static batch area the table uses (-1: caller memory)
   GridBar* d_bar = nullptr;            // grid barrier of the persistent launches (batch memory)
   bool persistent = false;             // launches as one persistent kernel per group of steps
   bool persistent_used = false;        // a persistent launch has been enqueued since the last sync
@@ -368,6 +370,42 @@ static int persist_step(int precision, int qg, int shape, int grid, hipStream_t 
 #undef LBM_PERSIST_F32
 #undef LBM_PERSIST_F64
   return 0;
+}
+
+// ------------------------------------------------------------------------------ static batch area
+// For callers that cannot allocate device memory, a batch's instance table and clock (the memory
+// lbm_batch_create takes from the caller) can live in this static array instead: one area per
+// device, holding up to LBM_BATCH_NOALLOC_MAX instances, kept until the process ends.  Host code
+// never uses the array's name as an address: its device address is taken once per device with
+// hipGetSymbolAddress (with that device current) and kept in g_area_ptr.  One batch uses a
+// device's area at a time (g_area_busy); its table and clock are rewritten by every
+// lbm_batch_step before any launch reads them, so nothing in it has to start at zero.
+constexpr int MAX_DEVICES = 64;
+constexpr size_t STATIC_AREA_BYTES =
+    (ALIGN + (size_t)LBM_BATCH_NOALLOC_MAX * sizeof(InstDesc<double>) + ALIGN - 1) / ALIGN * ALIGN;
+__device__ __align__(256) char scratch[STATIC_AREA_BYTES];
+
+static std::mutex g_area_mu;
+static void* g_area_ptr[MAX_DEVICES] = {};
+static bool g_area_busy[MAX_DEVICES] = {};
+
+// Device address of device dev's area (dev current); called with g_area_mu held.
+static lbm_status static_area(int dev, void** out) {
+  if (!g_area_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_E_DEVICE;
+    g_area_ptr[dev] = ptr;
+  }
+  *out = g_area_ptr[dev];
+  return LBM_OK;
+}
+
+// Frees the area of batch b for the next one once b's launches have finished.
+static lbm_status release_static_area(lbm_batch* b) {
+  const hipError_t e = hipStreamSynchronize(b->stream);
+  std::lock_guard<std::mutex> lock(g_area_mu);
+  g_area_busy[b->noalloc_device] = false;
+  return e == hipSuccess ? LBM_OK : LBM_E_DEVICE;
 }
 
 // ------------------------------------------------------------------------------ C ABI
@@ -1407,7 +1445,28 @@ lbm_status lbm_batch_destroy(lbm_batch* b) {
   if (!b) return LBM_E_INVAL;
   // the members are not touched: they may already be destroyed
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  lbm_status s = LBM_OK;
+  if (b->noalloc_device >= 0) s = release_static_area(b);
   delete b;
+  return s;
+}
+
+lbm_status lbm_batch_create_noalloc(lbm_ctx* const* ctxs, int n, void* hip_stream, lbm_batch** out) {
+  if (!out || !ctxs || n <= 0 || n > LBM_BATCH_NOALLOC_MAX) return LBM_E_INVAL;
+  *out = nullptr;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return LBM_E_DEVICE;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i] || ctxs[i]->device != dev) return LBM_E_INVAL;
+  std::lock_guard<std::mutex> lock(g_area_mu);
+  if (g_area_busy[dev]) return LBM_E_STATE;
+  void* area = nullptr;
+  const lbm_status a = static_area(dev, &area);
+  if (a != LBM_OK) return a;
+  const lbm_status s = lbm_batch_create(ctxs, n, area, STATIC_AREA_BYTES, hip_stream, out);
+  if (s != LBM_OK) return s;
+  (*out)->noalloc_device = dev;
+  g_area_busy[dev] = true;
   return LBM_OK;
 }
 
