@@ -157,6 +157,16 @@ lbm_status lbm_set_shape(lbm_ctx* h, int k);
 /* The shape in use (never -1); -1 for a NULL context. */
 int lbm_get_shape(const lbm_ctx* h);
 
+/* Order in which a launch's workgroups take the tiles of the context (results do not depend on it):
+   order = 0, the default: strips of 8 tile columns, each walked from the bottom tile row to the
+   top, where the context's state exceeds the 256 MB Infinity Cache (the halo rows a tile reads are
+   then still in the L2 of its XCD), whole tile rows in order otherwise; 1: whole rows; k >= 2:
+   strips of k tile columns.  Applies to later steps, also in batches.  Waits for the stream.
+   LBM_E_INVAL for order < 0.  lbm_get_tile_order: the strip width in use, in tiles (the number of
+   tile columns for whole rows); -1 for a NULL context. */
+lbm_status lbm_set_tile_order(lbm_ctx* h, int order);
+int lbm_get_tile_order(const lbm_ctx* h);
+
 /* Wait for the stream and report any device-side numerical failure. */
 lbm_status lbm_sync(lbm_ctx* h);
 

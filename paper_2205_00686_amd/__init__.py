@@ -186,6 +186,18 @@ class Solver:
         _check(_native.lib().lbm_set_shape(self.handle, int(k)), self.handle)
         return self
 
+    @property
+    def tile_order(self) -> int:
+        """Tile columns per strip of the order in which workgroups take the tiles (see
+        lbm_set_tile_order)."""
+        return int(_native.lib().lbm_get_tile_order(self.handle))
+
+    def set_tile_order(self, order: int):
+        """0: the library's choice; 1: whole tile rows; k >= 2: strips of k tile columns.  Results do
+        not change."""
+        _check(_native.lib().lbm_set_tile_order(self.handle, int(order)), self.handle)
+        return self
+
     def fields(self):
         out = [np.empty((self.ny, self.nx)) for _ in range(4)]
         _check(_native.lib().lbm_read_fields(self.handle, *(_dptr(a) for a in out)), self.handle)

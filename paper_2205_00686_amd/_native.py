@@ -20,6 +20,7 @@ LBM3D_PATH_FUSED, LBM3D_PATH_PER_NODE = 0, 1
 EXPORTS = (
     "lbm_params_default", "lbm_validate", "lbm_footprint_bytes", "lbm_create", "lbm_init", "lbm_step",
     "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_shape_fits", "lbm_set_shape", "lbm_get_shape",
+    "lbm_set_tile_order", "lbm_get_tile_order",
     "lbm_sync", "lbm_read_fields", "lbm_vapour_rows", "lbm_diagnostics", "lbm_set_diagnostics_interval",
     "lbm_read_diagnostics_log", "lbm_state_bytes", "lbm_save_state",
     "lbm_load_state", "lbm_read_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
@@ -101,6 +102,8 @@ def lib():
         "lbm_shape_fits": ([P, ctypes.c_int], ctypes.c_int),
         "lbm_set_shape": ([vp, ctypes.c_int], st),
         "lbm_get_shape": ([vp], ctypes.c_int),
+        "lbm_set_tile_order": ([vp, ctypes.c_int], st),
+        "lbm_get_tile_order": ([vp], ctypes.c_int),
         "lbm_sync": ([vp], st),
         "lbm_read_fields": ([vp, dp, dp, dp, dp], st),
         "lbm_vapour_rows": ([vp, d, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)], st),

@@ -123,6 +123,7 @@ struct lbm_ctx {
   double rho_ave = 0.0;  // rho_ave of the buoyancy at init (constant unless it follows the mean)
   double T_ref = 0.0;  // storage offset of g and the history (exact in the working precision)
   int shape_req = -1;  // requested tile shape (-1: chosen from the grid size)
+  int order_req = 0;   // requested tile order (0: chosen from the grid size, 1: whole rows, k: strips of k)
   int shape = 0;       // tile shape in use
   int ntiles = 0;
   InstLive live0{};      // staging of the live values written at init / load (outlives the copy)
@@ -273,8 +274,28 @@ static DevParams<real> derive(const lbm_params* p, double rho_ave, double T_ref)
   return d;
 }
 
+static int resident_per_cu(int precision, int qg, int shape);
+
+// Tile columns per strip of the tile order (see tile_position): as requested, or by default strips
+// of 8 tiles where a row of tiles is at least half as wide as the number of workgroups an XCD runs
+// at once (its compute units times the kernel's resident workgroups per unit): with whole rows, the
+// rows of tiles above and below a tile, whose halo it reads, are then too far apart in time for the
+// XCD's L2 to still hold them.  Measured on 64 x 16 two-step tiles (one workgroup per compute unit):
+// 4096^2 -10 %, 2048^2 -6 %, 1024 x 2048 -3 % per step; on 64 x 8 one-step tiles (three per unit):
+// 4096^2 -10 %, but 2048^2 and 1024 x 2048, whose rows fit, +4 to +6 %.
+constexpr int DEFAULT_STRIP = 8;
+static int tile_strip(const lbm_ctx* h, int ntx, int shape) {
+  if (h->order_req == 1) return ntx;
+  if (h->order_req >= 2) return std::min(h->order_req, ntx);
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+  const int per_xcd = resident_per_cu(h->prm.precision, qg_of(&h->prm), shape) * cus / NXCD;
+  return 2 * ntx >= per_xcd ? std::min(DEFAULT_STRIP, ntx) : ntx;
+}
+
 template <typename real>
-static InstDesc<real> make_desc(lbm_ctx* h, int ty) {
+static InstDesc<real> make_desc(lbm_ctx* h, int shape) {
+  const int ty = shape_def(h->prm.precision, shape).ty;
   InstDesc<real> D{};
   D.fA = (real*)h->fA;
   D.gA = (real*)h->gA;
@@ -287,6 +308,7 @@ static InstDesc<real> make_desc(lbm_ctx* h, int ty) {
   D.ny = h->prm.ny;
   D.ntx = (h->prm.nx + TX - 1) / TX;
   D.nty = (h->prm.ny + ty - 1) / ty;
+  D.strip = tile_strip(h, D.ntx, shape);
   D.tile_begin = 0;
   D.b_base = 0;
   D.h_base = 0;
@@ -352,6 +374,42 @@ static int persist_shape(int qg, int grid, hipStream_t st, const void* table, in
     else persist_kernel<real, S, 5><<<grid, S::NT, 0, st>>>(t, ninst, clk, total_tiles, nl, open, bar, spin);
   }
   return nb;
+}
+
+// Workgroups of the step kernel of a shape that fit on one compute unit at once (from the kernel's
+// occupancy; 1 if it cannot be queried), cached per precision, thermal lattice and shape.
+template <typename real, class S>
+static int step_occupancy(int qg) {
+  int nb = 0;
+  if (qg == 9) {
+    if constexpr (S::DEPTH == 1) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<real, S, 9>, S::NT, 0);
+  } else {
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<real, S, 5>, S::NT, 0);
+  }
+  return nb > 0 ? nb : 1;
+}
+
+static int resident_per_cu(int precision, int qg, int shape) {
+  static int cache[2][2][16] = {};
+  int& c = cache[precision == LBM_FP64 ? 1 : 0][qg == 9 ? 1 : 0][shape & 15];
+  if (c == 0) {
+#define LBM_OCC_F32(kk, ty, w, d) \
+  case kk:                        \
+    c = step_occupancy<float, Shape<ty, w, d>>(qg); \
+    break;
+#define LBM_OCC_F64(kk, ty, w, d) \
+  case kk:                        \
+    c = step_occupancy<double, Shape<ty, w, d>>(qg); \
+    break;
+    if (precision == LBM_FP64) {
+      switch (shape) { LBM_F64_SHAPES(LBM_OCC_F64) default: c = 1; break; }
+    } else {
+      switch (shape) { LBM_F32_SHAPES(LBM_OCC_F32) default: c = 1; break; }
+    }
+#undef LBM_OCC_F32
+#undef LBM_OCC_F64
+  }
+  return c;
 }
 
 static int persist_step(int precision, int qg, int shape, int grid, hipStream_t st, const void* table, int ninst,
@@ -523,10 +581,10 @@ lbm_status lbm_destroy(lbm_ctx* h) {
 
 static lbm_status upload_desc(lbm_ctx* h) {
   if (h->prm.precision == LBM_FP64) {
-    h->desc64 = make_desc<double>(h, shape_def(LBM_FP64, h->shape).ty);
+    h->desc64 = make_desc<double>(h, h->shape);
     HIP_OR_FAIL(h, hipMemcpyAsync(h->d_desc, &h->desc64, sizeof(h->desc64), hipMemcpyHostToDevice, h->stream));
   } else {
-    h->desc32 = make_desc<float>(h, shape_def(LBM_FP32, h->shape).ty);
+    h->desc32 = make_desc<float>(h, h->shape);
     HIP_OR_FAIL(h, hipMemcpyAsync(h->d_desc, &h->desc32, sizeof(h->desc32), hipMemcpyHostToDevice, h->stream));
   }
   return LBM_OK;
@@ -768,6 +826,24 @@ lbm_status lbm_set_shape(lbm_ctx* h, int k) {
 }
 
 int lbm_get_shape(const lbm_ctx* h) { return h ? h->shape : -1; }
+
+lbm_status lbm_set_tile_order(lbm_ctx* h, int order) {
+  if (!h || order < 0) return LBM_E_INVAL;
+  h->order_req = order;
+  if (h->initialised) {
+    if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+    lbm_status st = upload_desc(h);  // ordered on the stream after the launches already enqueued
+    if (st != LBM_OK) return st;
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_get_tile_order(const lbm_ctx* h) {
+  if (!h) return -1;
+  const int ntx = (h->prm.nx + TX - 1) / TX;
+  return tile_strip(h, ntx, h->shape);
+}
 
 lbm_status lbm_sync(lbm_ctx* h) {
   if (!h) return LBM_E_INVAL;
@@ -1232,7 +1308,7 @@ static void fill_table(lbm_batch* b, std::vector<InstDesc<real>>& tab, int64_t t
   for (int j = 0; j < n; ++j) {
     const int i = order[j];
     lbm_ctx* h = b->ctx[i];
-    InstDesc<real> D = make_desc<real>(h, shape_def(b->precision, b->shape).ty);
+    InstDesc<real> D = make_desc<real>(h, b->shape);
     // buffers as left by the context's own steps and the batched launches not yet synced
     D.t_base = b->clock;
     D.b_base = (h->gen ^ (int)(b->pending_launches[i] & 1)) & 1;

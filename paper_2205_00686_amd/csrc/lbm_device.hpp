@@ -106,6 +106,7 @@ struct InstDesc {
   unsigned* err;
   int nx, ny;
   int ntx, nty;        // tiles along x and y
+  int strip;           // tile order: strips of this many tile columns (>= ntx: whole rows)
   int tile_begin;      // first workgroup index of this instance in the launch
   int b_base;          // 1 if the current state is in the B buffers at clock t_base
   int h_base;          // 1 if the temperature history is in ThB at clock t_base

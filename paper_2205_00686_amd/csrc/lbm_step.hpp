@@ -853,6 +853,22 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
 
 // ------------------------------------------------------------------------- kernels
 
+// Position (bx, by) of tile number `tile` of an instance with ntx x nty tiles.  Tiles are numbered
+// in strips of `strip` tile columns, each strip from the bottom row to the top, row by row within it
+// (strip >= ntx: whole grid rows in order).  Workgroups take the tiles in this order, each XCD a
+// contiguous range of it.  With strips narrower than the grid, the tiles below and above a tile,
+// whose rows it reads as halo, are processed shortly before and after it on the same XCD, and its
+// halo reads hit that XCD's L2; with whole rows in order they are a grid row of tiles away, which on
+// grids beyond the Infinity Cache is too far for the L2 to keep them.
+__device__ __forceinline__ void tile_position(int tile, int ntx, int nty, int strip, int& bx, int& by) {
+  const int per_strip = strip * nty;
+  const int s = tile / per_strip;
+  const int local = tile - s * per_strip;
+  const int w = min(strip, ntx - s * strip);  // the last strip may be narrower
+  by = local / w;
+  bx = s * strip + (local - by * w);
+}
+
 // LDS of one workgroup of shape S: the two-step state, or the one-step fields
 template <typename real, class S, int QG>
 using TileLds = typename std::conditional<S::DEPTH == 2, Step2Lds<real, S>, StepLds<real, S::EYW, QG>>::type;
@@ -878,8 +894,8 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>* __restrict__ tab
   if (t < t_base || t >= t_end) return;
   const int tile = bid - D.tile_begin;
   if (tile < 0 || tile >= D.ntx * D.nty) return;
-  const int by = tile / D.ntx;
-  const int bx = tile - by * D.ntx;
+  int bx, by;
+  tile_position(tile, D.ntx, D.nty, D.strip, bx, by);
   const int x0 = bx * TX, y0 = by * S::TY;
   const bool odd = ((b_base + (t - t_base) / S::DEPTH) & 1) != 0;
   // the history changes copy once per launch that does two steps (every launch of a two-step

@@ -185,3 +185,33 @@ def test_autotune_batch_leaves_members_untouched(lbm, sat, tmp_path, monkeypatch
         assert s.save_state() == ref.save_state()
         ref.close()
         s.close()
+
+
+def test_tile_orders_give_identical_bits(lbm, sat):
+    """The order in which workgroups take the tiles (whole rows, strips of k tile columns, changed in
+    mid-run, in a batch) does not change a bit: every node's arithmetic is the same."""
+    Tc, rl, rg = sat
+    w = boiling(Tc, rl, rg, nx=600, ny=260, hot_width=10.0, gravity=3e-5)  # 10 tile columns, ragged
+    ref = None
+    for shape in (6, 2):
+        for order in (1, 2, 3, 8, 0):
+            print(f"\n[case] tile order {order} shape {shape}", flush=True)
+            s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T).set_shape(shape).set_tile_order(order)
+            assert s.tile_order == (10 if order == 1 else order if order else s.tile_order)
+            s.step(37)
+            s.set_tile_order(3 if order != 3 else 1)
+            s.step(40)
+            out = s.save_state()
+            s.close()
+            ref = ref or out
+            assert out == ref, (shape, order)
+    sols = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T).set_tile_order(o) for o in (2, 1)]
+    b = lbm.Batch(sols)
+    for i in range(2):
+        b.set_budget(i, 77)
+    b.step(77)
+    assert b.sync() == [0, 0]
+    b.close()
+    for s in sols:
+        assert s.save_state() == ref
+        s.close()
