@@ -44,7 +44,9 @@ TRAFFIC3D = {(256, 0, 0): 3986283140}
 # HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by the
 # same counters read for a plain copy of known size (profiles/): (workload, nx, ny, shape, dtype) ->
 # bytes and the digest of the kernel sources profiled (reported only while the sources match)
-TRAFFIC = {}
+TRAFFIC = {("boiling", 1024, 2048, 2, "f32"): {"bytes": 272039872, "kernel_sha": "ecce28044270a8a8"},
+           ("evaporation", 4096, 4096, 6, "f32"): {"bytes": 2300824416, "kernel_sha": "ecce28044270a8a8"},
+           ("evaporation", 4096, 4096, 2, "f32"): {"bytes": 2323528384, "kernel_sha": "ecce28044270a8a8"}}
 
 
 def build_workload(nx=512, ny=512, steps=20000, kind="evaporation"):
