@@ -205,6 +205,34 @@ lbm_status lbm_read_diagnostics_log(lbm_ctx* h, int64_t* steps, double* mass, do
    empty, a non-finite threshold or NULL pointers; LBM_E_STATE before lbm_init. */
 lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi, int32_t* counts);
 
+/* One vapour component of lbm_vapour_components: a connected set of vapour nodes (8-connected,
+   periodic in x).  root is the smallest node index y*nx + x of the component, area its number of
+   nodes, [y_min, y_max] and [x_min, x_max] the rows and columns it occupies (column indices as
+   stored, so a component that wraps around x spans from near 0 to near nx - 1), and y_sum the sum
+   of its nodes' rows (centroid row = y_sum / area). */
+typedef struct lbm_component {
+  int32_t root, area, y_min, y_max, x_min, x_max;
+  int64_t y_sum;
+} lbm_component;
+
+#define LBM_MAX_COMPONENTS 4096
+
+/* Vapour components of the current state, for the bubble-departure readout of Section 4.3: a
+   departed bubble is a component that touches neither the heated wall nor the vapour above the
+   pool.  The vapour nodes are those of rows [y_lo, y_hi) whose density, summed in the working
+   precision as in lbm_read_fields, is below rho_threshold when compared in FP64 (so exactly the
+   nodes where the density lbm_read_fields returns is below it).  Labelled on the device by
+   union-find; the result does not depend on the order of execution.  *n_total receives the
+   number of components; the first min(n_total, max_out) of them in increasing root order are
+   written to the caller-owned host array out[max_out].  The labels use the buffers the next step
+   overwrites before reading them, so the state is not changed.  Synchronising.
+   LBM_E_INVAL for an empty or out-of-grid row range, a non-finite threshold, max_out < 0 or NULL
+   pointers, and for more than LBM_MAX_COMPONENTS components (possible only where the rows hold
+   more than about 16 000 nodes; *n_total is still set); LBM_E_STATE before lbm_init
+   or for a batch member whose steps lbm_batch_sync has not yet brought up to date. */
+lbm_status lbm_vapour_components(lbm_ctx* h, double rho_threshold, int y_lo, int y_hi, lbm_component* out,
+                                 int max_out, int* n_total);
+
 /* Raw state to / from a caller-owned host buffer of lbm_state_bytes() bytes: f[9][ny][nx],
    g[Q][ny][nx] (Q = 5 or 9, the thermal lattice), history[2][ny][nx] in the context's precision,
    then a 64-byte trailer: magic "LBM2D", format version, precision, nx, ny, Q, the step count
@@ -261,7 +289,11 @@ size_t lbm_batch_footprint_bytes(int n);
    (their lbm_init, for instance), so a context may be initialised on a stream of its own.
    While the batch exists its members are advanced only through it.  Once lbm_batch_sync has
    returned, a member may be used on its own stream (lbm_read_fields, lbm_step, ...) or
-   destroyed.  LBM_E_DEVICE if the stream ordering cannot be set up. */
+   destroyed.  Between an lbm_batch_step that advanced a member and the next lbm_batch_sync, the
+   calls that read, write or advance that member's state on its own (lbm_init, lbm_step,
+   lbm_read_fields, lbm_read_state, lbm_diagnostics, lbm_vapour_rows, lbm_vapour_components,
+   lbm_save_state, lbm_load_state, and lbm_batch_create with it as a member) return LBM_E_STATE.
+   LBM_E_DEVICE if the stream ordering cannot be set up. */
 lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t bytes, void* hip_stream,
                             lbm_batch** out);
 

@@ -212,6 +212,19 @@ class Solver:
                                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), self.handle)
         return out
 
+    def vapour_components(self, rho_threshold: float, y_lo: int = 0, y_hi: int = None) -> list:
+        """Connected vapour components (8-connected, periodic in x) of rows [y_lo, y_hi), labelled
+        on the device: a list of dicts (root, area, y_min, y_max, x_min, x_max, y_sum) in
+        increasing order of root, the smallest node index y * nx + x of each component."""
+        y_hi = self.ny if y_hi is None else int(y_hi)
+        cap = _native.LBM_MAX_COMPONENTS
+        out = (_native.LbmComponent * cap)()
+        n = ctypes.c_int()
+        _check(_native.lib().lbm_vapour_components(self.handle, float(rho_threshold), int(y_lo), y_hi, out, cap,
+                                                   ctypes.byref(n)), self.handle)
+        names = [f[0] for f in _native.LbmComponent._fields_]
+        return [{k: int(getattr(out[i], k)) for k in names} for i in range(n.value)]
+
     def diagnostics(self):
         m, e = ctypes.c_double(), ctypes.c_double()
         _check(_native.lib().lbm_diagnostics(self.handle, ctypes.byref(m), ctypes.byref(e)), self.handle)
@@ -330,9 +343,14 @@ class Batch:
         return list(st)
 
     def close(self):
+        """Release the batch.  While every member is still open, their steps are first brought up
+        to date (lbm_batch_sync), so they can go on alone."""
         if getattr(self, "handle", None):
+            L = _native.lib()
+            if all(getattr(s, "handle", None) for s in self.solvers):
+                L.lbm_batch_sync(self.handle, None)  # a failure stays recorded in each member
             self.stream.synchronize()
-            rc = _native.lib().lbm_batch_destroy(self.handle)
+            rc = L.lbm_batch_destroy(self.handle)
             self.handle = None
             _check(rc)
 

@@ -21,7 +21,7 @@ EXPORTS = (
     "lbm_params_default", "lbm_validate", "lbm_footprint_bytes", "lbm_create", "lbm_init", "lbm_step",
     "lbm_steps_done", "lbm_shape_count", "lbm_shape_info", "lbm_shape_fits", "lbm_set_shape", "lbm_get_shape",
     "lbm_set_tile_order", "lbm_get_tile_order",
-    "lbm_sync", "lbm_read_fields", "lbm_vapour_rows", "lbm_diagnostics", "lbm_set_diagnostics_interval",
+    "lbm_sync", "lbm_read_fields", "lbm_vapour_rows", "lbm_vapour_components", "lbm_diagnostics", "lbm_set_diagnostics_interval",
     "lbm_read_diagnostics_log", "lbm_state_bytes", "lbm_save_state",
     "lbm_load_state", "lbm_read_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
     "lbm_last_error", "lbm_device_copy", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
@@ -48,6 +48,16 @@ class Lbm3dParams(ctypes.Structure):
         ("thermal_box", ctypes.c_int32), ("z_chunk", ctypes.c_int32), ("T_box", ctypes.c_double),
         ("flags", ctypes.c_uint32), ("path", ctypes.c_uint32),
     ]
+
+
+class LbmComponent(ctypes.Structure):
+    """Mirror of lbm_component (include/lbm.h)."""
+    _fields_ = [("root", ctypes.c_int32), ("area", ctypes.c_int32), ("y_min", ctypes.c_int32),
+                ("y_max", ctypes.c_int32), ("x_min", ctypes.c_int32), ("x_max", ctypes.c_int32),
+                ("y_sum", ctypes.c_int64)]
+
+
+LBM_MAX_COMPONENTS = 4096
 
 
 class LbmParams(ctypes.Structure):
@@ -107,6 +117,8 @@ def lib():
         "lbm_sync": ([vp], st),
         "lbm_read_fields": ([vp, dp, dp, dp, dp], st),
         "lbm_vapour_rows": ([vp, d, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int32)], st),
+        "lbm_vapour_components": ([vp, d, ctypes.c_int, ctypes.c_int, ctypes.POINTER(LbmComponent), ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_int)], st),
         "lbm_diagnostics": ([vp, dp, dp], st),
         "lbm_set_diagnostics_interval": ([vp, i64], st),
         "lbm_read_diagnostics_log": ([vp, ctypes.POINTER(ctypes.c_int64), dp, dp, ctypes.c_int, ip], st),

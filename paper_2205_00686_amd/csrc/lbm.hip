@@ -117,6 +117,7 @@ struct lbm_ctx {
   bool initialised = false;
   bool failed = false;
   int64_t steps = 0;
+  int64_t batch_unsynced = 0;  // steps a batch has enqueued for this member since its last lbm_batch_sync
   int gen = 0;           // 1 if the current state is in the B buffers
   int hgen = 0;          // 1 if the temperature history is in ThB (it moves only on two-step launches)
   long long clock = 0;   // host mirror of the context's device clock (advanced by its own launches)
@@ -197,6 +198,12 @@ static int batch_default_shape(int precision, const std::vector<lbm_ctx*>& ctx) 
 static lbm_status fail(lbm_ctx* h, lbm_status s, const std::string& msg) {
   if (h) h->last_error = msg;
   return s;
+}
+
+// A member of a batch whose steps have not been brought up to date by lbm_batch_sync: its buffer
+// parities are not known on the host, so nothing may read or advance it on its own.
+static lbm_status unsynced(lbm_ctx* h, const char* call) {
+  return fail(h, LBM_E_STATE, std::string(call) + ": the context has batched steps not yet synchronised (lbm_batch_sync)");
 }
 
 #define HIP_OR_FAIL(h, call)                                                               \
@@ -599,6 +606,7 @@ static lbm_status write_clock(lbm_ctx* h) {
 
 lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const double* uy, const double* T) {
   if (!h || !rho || !ux || !uy || !T) return LBM_E_INVAL;
+  if (h->batch_unsynced) return unsynced(h, "lbm_init");
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
   const size_t N = h->N;
   double sum = 0.0, sumT = 0.0, rmin = std::numeric_limits<double>::infinity();
@@ -760,6 +768,7 @@ static lbm_status enqueue_diagnostics(lbm_ctx* h, DiagRecord* rec);
 lbm_status lbm_step(lbm_ctx* h, int64_t n) {
   if (!h || n < 0) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_step before lbm_init");
+  if (h->batch_unsynced) return unsynced(h, "lbm_step");
   if (h->failed) return fail(h, LBM_E_STATE, "context has failed: " + h->last_error);
   if (n == 0) return LBM_OK;
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
@@ -866,6 +875,7 @@ static void* current_history(lbm_ctx* h) { return (h->hgen & 1) ? h->ThB : h->Th
 lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, double* T) {
   if (!h) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_read_fields before lbm_init");
+  if (h->batch_unsynced) return unsynced(h, "lbm_read_fields");
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
   lbm_status s = check_device_error(h);
   if (s != LBM_OK) return s;
@@ -912,6 +922,7 @@ static lbm_status enqueue_diagnostics(lbm_ctx* h, DiagRecord* rec) {
 lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy) {
   if (!h) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_diagnostics before lbm_init");
+  if (h->batch_unsynced) return unsynced(h, "lbm_diagnostics");
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
   lbm_status st = enqueue_diagnostics(h, nullptr);
   if (st != LBM_OK) return st;
@@ -956,6 +967,7 @@ lbm_status lbm_read_diagnostics_log(lbm_ctx* h, int64_t* steps, double* mass, do
 lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi, int32_t* counts) {
   if (!h || !counts || !std::isfinite(rho_threshold) || x_hi <= x_lo || x_hi - x_lo > h->prm.nx) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_vapour_rows before lbm_init");
+  if (h->batch_unsynced) return unsynced(h, "lbm_vapour_rows");
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
   void *f, *g, *fo;
   current_buffers(h, f, g, fo);
@@ -973,6 +985,62 @@ lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi,
     HIP_OR_FAIL(h, hipGetLastError());
     HIP_OR_FAIL(h, hipMemcpyAsync(counts + y0, dcount, rows * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  }
+  return check_device_error(h);
+}
+
+lbm_status lbm_vapour_components(lbm_ctx* h, double rho_threshold, int y_lo, int y_hi, lbm_component* out,
+                                 int max_out, int* n_total) {
+  if (!h || !n_total || max_out < 0 || (max_out > 0 && !out) || !std::isfinite(rho_threshold)) return LBM_E_INVAL;
+  if (y_lo < 0 || y_hi > h->prm.ny || y_hi <= y_lo) return LBM_E_INVAL;
+  *n_total = 0;
+  if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_vapour_components before lbm_init");
+  if (h->batch_unsynced) return unsynced(h, "lbm_vapour_components");
+  if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
+  void *f, *g, *fo;
+  current_buffers(h, f, g, fo);
+  // Scratch: the labels (4 bytes per node of the rows) in the other f copy, which the next step
+  // overwrites before reading it; the table after them if it has room for as many entries as the
+  // partials area, else in the partials area; the counter at the start of the partials area.
+  const int nx = h->prm.nx, n = nx * (y_hi - y_lo);
+  int* lab = (int*)fo;
+  int* dcount = (int*)h->d_part;
+  const size_t lab_bytes = ((size_t)n * sizeof(int) + 255) & ~(size_t)255;
+  const size_t room = 9 * h->N * h->rsz - lab_bytes;  // >= 32 N - 255 bytes, since n <= N
+  const size_t part_cap = (partial_bytes() - 256) / sizeof(CompStat);
+  CompStat* tab = (CompStat*)((char*)h->d_part + 256);
+  size_t cap = part_cap;
+  if (room / sizeof(CompStat) > part_cap) {
+    tab = (CompStat*)((char*)fo + lab_bytes);
+    cap = std::min<size_t>(LBM_MAX_COMPONENTS, room / sizeof(CompStat));
+  }
+  const int nb = (n + CC_NT - 1) / CC_NT;
+  if (h->prm.precision == LBM_FP64)
+    cc_init_kernel<double><<<nb, CC_NT, 0, h->stream>>>((const double*)f, nx, h->N, y_lo, n, rho_threshold, lab);
+  else
+    cc_init_kernel<float><<<nb, CC_NT, 0, h->stream>>>((const float*)f, nx, h->N, y_lo, n, rho_threshold, lab);
+  cc_union_kernel<<<nb, CC_NT, 0, h->stream>>>(lab, nx, y_hi - y_lo);
+  cc_flatten_kernel<<<nb, CC_NT, 0, h->stream>>>(lab, n);
+  HIP_OR_FAIL(h, hipMemsetAsync(dcount, 0, sizeof(int), h->stream));
+  cc_number_kernel<<<nb, CC_NT, 0, h->stream>>>(lab, n, y_lo * nx, dcount, tab, (int)cap);
+  cc_stats_kernel<<<nb, CC_NT, 0, h->stream>>>(lab, nx, n, y_lo, tab, (int)cap);
+  HIP_OR_FAIL(h, hipGetLastError());
+  int total = 0;
+  HIP_OR_FAIL(h, hipMemcpyAsync(&total, dcount, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  *n_total = total;
+  if ((size_t)total > cap)
+    return fail(h, LBM_E_INVAL, "more vapour components than the table holds (" + std::to_string(cap) +
+                                    "); narrow the rows or change the threshold");
+  std::vector<CompStat> all((size_t)total);
+  if (total > 0) {
+    HIP_OR_FAIL(h, hipMemcpyAsync(all.data(), tab, (size_t)total * sizeof(CompStat), hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(h, hipStreamSynchronize(h->stream));
+  }
+  std::sort(all.begin(), all.end(), [](const CompStat& a, const CompStat& b) { return a.root < b.root; });
+  for (int i = 0; i < std::min(total, max_out); ++i) {
+    const CompStat& c = all[(size_t)i];
+    out[i] = lbm_component{c.root, c.area, c.y_min, c.y_max, c.x_min, c.x_max, (int64_t)c.y_sum};
   }
   return check_device_error(h);
 }
@@ -1005,6 +1073,7 @@ size_t lbm_state_bytes(const lbm_ctx* h) { return h ? planes_bytes(h) + sizeof(S
 lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
   if (!h || !host) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_save_state before lbm_init");
+  if (h->batch_unsynced) return unsynced(h, "lbm_save_state");
   if (bytes < lbm_state_bytes(h)) return fail(h, LBM_E_INVAL, "host buffer smaller than lbm_state_bytes");
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
   void *f, *g, *fo;
@@ -1036,6 +1105,7 @@ lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
 
 lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
   if (!h || !host) return LBM_E_INVAL;
+  if (h->batch_unsynced) return unsynced(h, "lbm_load_state");
   if (bytes != lbm_state_bytes(h)) return fail(h, LBM_E_INVAL, "buffer size differs from lbm_state_bytes");
   const char* q = (const char*)host;
   StateTrailer t;
@@ -1076,6 +1146,7 @@ lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
 lbm_status lbm_read_state(lbm_ctx* h, double* f, double* g, double* hist) {
   if (!h) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_read_state before lbm_init");
+  if (h->batch_unsynced) return unsynced(h, "lbm_read_state");
   std::vector<char> raw;
   try {
     raw.resize(lbm_state_bytes(h));
@@ -1230,6 +1301,8 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   for (int i = 0; i < n; ++i)
     if (!ctxs[i] || !ctxs[i]->initialised || ctxs[i]->prm.precision != prec || qg_of(&ctxs[i]->prm) != qg)
       return LBM_E_INVAL;
+  for (int i = 0; i < n; ++i)
+    if (ctxs[i]->batch_unsynced) return unsynced(ctxs[i], "lbm_batch_create");
   lbm_batch* b = new (std::nothrow) lbm_batch();
   if (!b) return LBM_E_NOMEM;
   b->ctx.assign(ctxs, ctxs + n);
@@ -1447,6 +1520,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
   for (size_t i = 0; i < b->ctx.size(); ++i) {
     const int64_t ran = std::min<int64_t>(todo, b->remaining[i]);
     b->pending[i] += ran;
+    b->ctx[i]->batch_unsynced += ran;
     b->pending_launches[i] += (ran + d - 1) / d;
     b->pending_hmoves[i] += history_moves(ran, d);
     b->remaining[i] -= ran;
@@ -1462,6 +1536,7 @@ lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status) {
   for (size_t i = 0; i < n; ++i) {
     lbm_ctx* h = b->ctx[i];
     h->steps += b->pending[i];
+    h->batch_unsynced = 0;
     h->gen ^= (int)(b->pending_launches[i] & 1);
     h->hgen ^= (int)(b->pending_hmoves[i] & 1);
     b->pending[i] = 0;

@@ -142,6 +142,124 @@ __global__ __launch_bounds__(VAP_NT) void vapour_rows_kernel(const real* __restr
   }
 }
 
+// Vapour components for the bubble-departure readout of Section 4.3: the connected sets of
+// nodes in rows [y_lo, y_lo + rows) whose density (summed in the working precision as for the
+// field readout, compared in FP64) is below a threshold, 8-connected, periodic in x.  The label
+// array has one int per node of the rows, indexed k = (y - y_lo) nx + x:
+//   -1            not vapour;
+//   0 <= p <= k   a vapour node whose parent is p (p = k: a root).
+// Union-find: every link goes from a root to a smaller index with an atomic minimum, so a root is
+// always the smallest index of its tree and the final roots do not depend on the order in which
+// the links were made.  Parents only decrease, so every walk to a root ends.
+constexpr int CC_NT = 256;
+
+struct CompStat {  // per component: integer sums and bounds, so atomics give order-free results
+  int root, area, y_min, y_max, x_min, x_max;
+  unsigned long long y_sum;
+};
+
+__device__ __forceinline__ int cc_load(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int cc_find(const int* lab, int k) {
+  int p = cc_load(lab + k);
+  while (p != k) {
+    k = p;
+    p = cc_load(lab + k);
+  }
+  return k;
+}
+
+// Join the trees of vapour nodes a and b.  A failed link (the root a got a parent meanwhile)
+// retries from that parent, so the larger root strictly decreases from one try to the next.
+__device__ void cc_union(int* lab, int a, int b) {
+  for (;;) {
+    a = cc_find(lab, a);
+    b = cc_find(lab, b);
+    if (a == b) return;
+    if (a < b) {
+      const int t = a;
+      a = b;
+      b = t;
+    }
+    const int old = atomicMin(lab + a, b);
+    if (old == a) return;
+    a = old;
+  }
+}
+
+template <typename real>
+__global__ __launch_bounds__(CC_NT) void cc_init_kernel(const real* __restrict__ f, int nx, size_t N, int y_lo,
+                                                        int n, double thr, int* __restrict__ lab) {
+  const int k = blockIdx.x * CC_NT + threadIdx.x;
+  if (k >= n) return;
+  const int o = y_lo * nx + k;
+  const real rho = ((f[o] + f[N + o]) + (f[2 * N + o] + f[3 * N + o])) +
+                   ((f[4 * N + o] + f[5 * N + o]) + (f[6 * N + o] + f[7 * N + o])) + f[8 * N + o];
+  lab[k] = (double)rho < thr ? k : -1;
+}
+
+// Each vapour node joins its vapour neighbours east, north-west, north and north-east (the other
+// four directions are the same pairs seen from the other node).
+__global__ __launch_bounds__(CC_NT) void cc_union_kernel(int* __restrict__ lab, int nx, int rows) {
+  const int k = blockIdx.x * CC_NT + threadIdx.x;
+  if (k >= nx * rows || cc_load(lab + k) < 0) return;
+  const int x = k % nx, r = k / nx;
+  const int xe = x + 1 == nx ? 0 : x + 1, xw = x == 0 ? nx - 1 : x - 1;
+  const int nb[4] = {r * nx + xe, (r + 1) * nx + xw, (r + 1) * nx + x, (r + 1) * nx + xe};
+  const int cnt = r + 1 < rows ? 4 : 1;
+  for (int j = 0; j < cnt; ++j)
+    if (cc_load(lab + nb[j]) >= 0) cc_union(lab, k, nb[j]);
+}
+
+// Every vapour node points at its root.
+__global__ __launch_bounds__(CC_NT) void cc_flatten_kernel(int* __restrict__ lab, int n) {
+  const int k = blockIdx.x * CC_NT + threadIdx.x;
+  if (k >= n || cc_load(lab + k) < 0) return;
+  __hip_atomic_store(lab + k, cc_find(lab, k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Each root takes a slot of the table (in no particular order; the host sorts by root) and
+// stores -2 - slot in its label; slots beyond cap are counted but not kept.
+__global__ __launch_bounds__(CC_NT) void cc_number_kernel(int* __restrict__ lab, int n, int y_lo_nx,
+                                                          int* __restrict__ count, CompStat* __restrict__ tab,
+                                                          int cap) {
+  const int k = blockIdx.x * CC_NT + threadIdx.x;
+  if (k >= n || lab[k] != k) return;
+  const int id = atomicAdd(count, 1);
+  if (id < cap) {
+    CompStat c;
+    c.root = y_lo_nx + k;
+    c.area = 0;
+    c.y_min = 0x7fffffff;
+    c.y_max = -1;
+    c.x_min = 0x7fffffff;
+    c.x_max = -1;
+    c.y_sum = 0ull;
+    tab[id] = c;
+  }
+  lab[k] = -2 - (id < cap ? id : cap);
+}
+
+__global__ __launch_bounds__(CC_NT) void cc_stats_kernel(const int* __restrict__ lab, int nx, int n, int y_lo,
+                                                         CompStat* __restrict__ tab, int cap) {
+  const int k = blockIdx.x * CC_NT + threadIdx.x;
+  if (k >= n) return;
+  const int v = lab[k];
+  if (v == -1) return;
+  const int id = v <= -2 ? -2 - v : -2 - lab[v];
+  if (id >= cap) return;
+  const int x = k % nx, y = y_lo + k / nx;
+  CompStat& c = tab[id];
+  atomicAdd(&c.area, 1);
+  atomicMin(&c.y_min, y);
+  atomicMax(&c.y_max, y);
+  atomicMin(&c.x_min, x);
+  atomicMax(&c.x_max, x);
+  atomicAdd(&c.y_sum, (unsigned long long)y);
+}
+
 // Deterministic FP64 sums of rho and rho c_v T (mass and thermal energy).  Three levels, each in a
 // fixed order: a thread adds its nodes of the workgroup's contiguous range; a wavefront adds its
 // 64 lanes by a butterfly of cross-lane shuffles (every lane ends with the same sum, the two

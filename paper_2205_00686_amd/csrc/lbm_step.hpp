@@ -385,7 +385,7 @@ struct LdsState {
 // a two-step launch) instead of the global source buffers.
 template <typename real, class S, int V, bool FROM_LDS, int QG = 5>
 __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real, S::EYW, QG>& L, bool odd, bool hodd,
-                                          int x0, int y0, const LdsState<real, S>& st, unsigned& err) {
+                                          int x0, int y0, const LdsState<real, S>& st, unsigned& err, int tid) {
   static_assert(!FROM_LDS || QG == 5, "the two-step state in LDS holds D2Q5 thermal populations");
   constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, RING = S::RING, URING = S::URING, EYW = S::EYW;
   const int nx = D.nx, ny = D.ny;
@@ -409,7 +409,6 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   const bool freeze = (p.flags & FL_FREEZE_FLOW) != 0;
   const bool tiny = nx < EXW + 1 || ny < EYW + 1;  // periodic images closer than one halo
 
-  const int tid = threadIdx.x;
   const int tx = tid & (TX - 1);
   const int ty = tid >> 6;
 
@@ -678,7 +677,7 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
 // leave that region are dropped; every kept slot is written exactly once.
 template <typename real, class S, int V>
 __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<real, S>& L, bool odd, bool hodd, int x0,
-                                           int y0, real (&Tn1)[S::RPT], real (&Tn2)[S::RPT], unsigned& err) {
+                                           int y0, real (&Tn1)[S::RPT], real (&Tn2)[S::RPT], unsigned& err, int tid) {
   constexpr int NT = S::NT, RPT = S::RPT, WAVES = S::WAVES, MX = S::MX, MY = S::MY, MXH = S::MXH, MYH = S::MYH;
   constexpr int MRING = MX * MY - TX * S::TY;
   constexpr int RPN = (MRING + NT - 1) / NT;
@@ -696,7 +695,6 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
   const bool freeze = (p.flags & FL_FREEZE_FLOW) != 0;
   const bool tiny = nx < MX + 1 || ny < MY + 1;
 
-  const int tid = threadIdx.x;
   const int tx = tid & (TX - 1);
   const int ty = tid >> 6;
 
@@ -880,7 +878,7 @@ using TileLds = typename std::conditional<S::DEPTH == 2, Step2Lds<real, S>, Step
 // workgroup).
 template <typename real, class S, int QG>
 __device__ __forceinline__ void step_tile(const InstDesc<real>* __restrict__ table, int ninst, long long t,
-                                          const LaunchWin& w, int bid, TileLds<real, S, QG>& lds) {
+                                          const LaunchWin& w, int bid, TileLds<real, S, QG>& lds, int tid) {
   int lo = 0, hi = ninst - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -913,19 +911,19 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>* __restrict__ tab
       real Tn1[S::RPT], Tn2[S::RPT];
       const bool interior2 =
           x0 >= S::MXH && x0 + TX + S::MXH <= D.nx && y0 >= S::MYH && y0 + S::TY + S::MYH <= D.ny;
-      if (interior2) first_step<real, S, 0>(D, L2, odd, hodd, x0, y0, Tn1, Tn2, err);
-      else with_general_variant(gv, [&](auto v) { first_step<real, S, decltype(v)::value>(D, L2, odd, hodd, x0, y0, Tn1, Tn2, err); });
+      if (interior2) first_step<real, S, 0>(D, L2, odd, hodd, x0, y0, Tn1, Tn2, err, tid);
+      else with_general_variant(gv, [&](auto v) { first_step<real, S, decltype(v)::value>(D, L2, odd, hodd, x0, y0, Tn1, Tn2, err, tid); });
       const LdsState<real, S> st{L2.sf, L2.sg, Tn1, Tn2};
-      if (interior) step_body<real, S, 0, true>(D, L2.m2, odd, hodd, x0, y0, st, err);
-      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, true>(D, L2.m2, odd, hodd, x0, y0, st, err); });
+      if (interior) step_body<real, S, 0, true>(D, L2.m2, odd, hodd, x0, y0, st, err, tid);
+      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, true>(D, L2.m2, odd, hodd, x0, y0, st, err, tid); });
     } else {
-      if (interior) step_body<real, S, 0, false>(D, L2.m2, odd, hodd, x0, y0, none, err);
-      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false>(D, L2.m2, odd, hodd, x0, y0, none, err); });
+      if (interior) step_body<real, S, 0, false>(D, L2.m2, odd, hodd, x0, y0, none, err, tid);
+      else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false>(D, L2.m2, odd, hodd, x0, y0, none, err, tid); });
     }
   } else {
     StepLds<real, S::EYW, QG>& L = lds;
-    if (interior) step_body<real, S, 0, false, QG>(D, L, odd, hodd, x0, y0, none, err);
-    else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false, QG>(D, L, odd, hodd, x0, y0, none, err); });
+    if (interior) step_body<real, S, 0, false, QG>(D, L, odd, hodd, x0, y0, none, err, tid);
+    else with_general_variant(gv, [&](auto v) { step_body<real, S, decltype(v)::value, false, QG>(D, L, odd, hodd, x0, y0, none, err, tid); });
   }
   // A failing simulation flags every node.  One atomic per thread, or even per wavefront, on one
   // word would serialise the launch, so a wavefront ORs its flags with ballots and sets only the
@@ -956,7 +954,7 @@ __global__ __launch_bounds__(S::NT) void step_kernel(const InstDesc<real>* __res
   const int bid = xcd * per + (xcd < rem ? xcd : rem) + blockIdx.x / NXCD;
   const long long t = (w.use ? w.t : *clock) + (long long)k * S::DEPTH;
   __shared__ TileLds<real, S, QG> lds;
-  step_tile<real, S, QG>(table, ninst, t, w, bid, lds);
+  step_tile<real, S, QG>(table, ninst, t, w, bid, lds, (int)threadIdx.x);
 }
 
 // Tile shapes compiled into the library, per precision: (tile height, wavefronts, steps per
@@ -1076,6 +1074,7 @@ __global__ __launch_bounds__(OPEN_NT) void open_top_kernel(const InstDesc<real>*
 struct GridBar {
   unsigned count;
   unsigned abort;
+  unsigned ticket[NXCD];  // tiles handed out so far to the workgroups of each XCD's band
 };
 
 __device__ __forceinline__ bool grid_barrier(GridBar* bar, unsigned target, unsigned spin_limit) {
@@ -1105,6 +1104,7 @@ __global__ void grid_bar_reset_kernel(GridBar* bar) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     bar->count = 0u;
     bar->abort = 0u;
+    for (int x = 0; x < NXCD; ++x) bar->ticket[x] = 0u;
   }
 }
 
@@ -1112,25 +1112,42 @@ __global__ void grid_bar_reset_kernel(GridBar* bar) {
 // the 8 XCDs) loop over the tiles of every active instance for one launch's steps, meet at a grid
 // barrier, run the open-top pass of the entries that have one (then meet again), and go on with the
 // next launch.  Each XCD's workgroups take a contiguous band of tiles, as the remap of step_kernel
-// does.  Every node's arithmetic is that of step_kernel, so results are bit-identical to nlaunch
-// launches of it.
+// does, one tile at a time from a counter of the band (tiles cost unequally -- boundary tiles take
+// the general path -- so a fixed share per workgroup would leave the barrier waiting for the
+// workgroups that hold the slow ones).  In launch L every workgroup of the band draws until it gets
+// a ticket past the band, so the band hands out exactly (band length + its workgroups) tickets per
+// launch and launch L starts from L times that.  Every node's arithmetic is that of step_kernel, so
+// results are bit-identical to nlaunch launches of it.
 template <typename real, class S, int QG>
 __global__ __launch_bounds__(S::NT) void persist_kernel(const InstDesc<real>* __restrict__ table, int ninst,
                                                         const long long* __restrict__ clock, int total_tiles,
                                                         int nlaunch, int open, GridBar* bar, unsigned spin_limit) {
   __shared__ TileLds<real, S, QG> lds;
   __shared__ double part[OPEN_NT / 64];
+  __shared__ int drawn;
   const long long c0 = *clock;
   const int G = gridDim.x;
-  const int xcd = blockIdx.x % NXCD, slot = blockIdx.x / NXCD, gx = G / NXCD;
+  const int xcd = blockIdx.x % NXCD, gx = G / NXCD;
   const int band = (total_tiles + NXCD - 1) / NXCD;
-  const int b0 = xcd * band, b1 = min(total_tiles, b0 + band);
+  const int b0 = min(total_tiles, xcd * band), b1 = min(total_tiles, b0 + band);
+  const unsigned per_launch = (unsigned)(b1 - b0 + gx);
   const LaunchWin w{0, 0, 0, 0, 0, 0};
   unsigned nbar = 0u;
   for (int L = 0; L < nlaunch; ++L) {
     const long long t = c0 + (long long)L * S::DEPTH;
-    for (int bid = b0 + slot; bid < b1; bid += gx) {
-      step_tile<real, S, QG>(table, ninst, t, w, bid, lds);
+    for (;;) {
+      if (threadIdx.x == 0)
+        drawn = (int)(__hip_atomic_fetch_add(&bar->ticket[xcd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                      (unsigned)L * per_launch);
+      __syncthreads();
+      const int k = drawn;
+      __syncthreads();  // every thread has read the ticket before the next draw
+      if (k >= b1 - b0) break;
+      // the thread index enters the tile as an opaque value, so that the compiler derives the
+      // per-thread addresses inside the loop instead of keeping them live across it (which spilled)
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+      step_tile<real, S, QG>(table, ninst, t, w, b0 + k, lds, tid);
       __syncthreads();  // the next tile reuses the LDS
     }
     if (!grid_barrier(bar, (unsigned)G * ++nbar, spin_limit)) return;

@@ -10,9 +10,10 @@ Measurement (every instance of the sweep runs in one batched launch per step):
 - Every `check_every` steps the device counts, per row, the vapour nodes (rho below the mean of
   the coexistence densities) in a window around the hot spot (lbm_vapour_rows).
 - A vapour row above a liquid gap, below the pool surface, triggers the measurement.
-- The density field is then read back and its vapour components are labelled (8-connected,
-  periodic in x).  A component that touches neither the wall nor the vapour above the pool is a
-  departed bubble; D = 2 sqrt(A / pi) from its area A.
+- The vapour components of the rows up to the surface are then labelled on the device
+  (8-connected, periodic in x; lbm_vapour_components), and only their areas and bounds come
+  back.  A component that touches neither the wall nor the vapour above the pool is a departed
+  bubble; D = 2 sqrt(A / pi) from its area A.
 - The first departure of each instance is kept.  The slope of log D_d against log g is fitted
   by least squares.
 
@@ -30,51 +31,15 @@ import numpy as np
 from . import LBM_FP32, Batch, Solver
 
 
-def label_vapour(vapour: np.ndarray) -> tuple[np.ndarray, int]:
-    """8-connected components of a boolean [ny][nx] mask, periodic in x (labels 1..n)."""
-    from scipy import ndimage
-
-    lab, n = ndimage.label(vapour, structure=np.ones((3, 3), dtype=bool))
-    if n == 0:
-        return lab, 0
-    # join components across the periodic x boundary (diagonal neighbours included)
-    parent = list(range(n + 1))
-
-    def find(a):
-        while parent[a] != a:
-            parent[a] = parent[parent[a]]
-            a = parent[a]
-        return a
-
-    ny, nx = vapour.shape
-    for y in range(ny):
-        a = lab[y, nx - 1]
-        if not a:
-            continue
-        for dy in (-1, 0, 1):
-            yy = y + dy
-            if 0 <= yy < ny and lab[yy, 0]:
-                ra, rb = find(a), find(lab[yy, 0])
-                if ra != rb:
-                    parent[max(ra, rb)] = min(ra, rb)
-    roots = np.array([find(i) for i in range(n + 1)])
-    lab = roots[lab]
-    uniq = np.unique(lab[lab > 0])
-    remap = np.zeros(n + 1, dtype=lab.dtype)
-    remap[uniq] = np.arange(1, len(uniq) + 1)
-    return remap[lab], len(uniq)
-
-
-def departed_bubbles(rho: np.ndarray, rho_mid: float, y_surface: int, min_area: int = 12):
-    """Vapour components that touch neither the bottom row nor any row at or above y_surface:
-    [(area, y_centroid, x_extent)] sorted by area, largest first."""
-    lab, n = label_vapour(rho < rho_mid)
+def departed(components, y_surface: int, min_area: int = 12):
+    """Departed bubbles among vapour components (dicts as Solver.vapour_components returns):
+    those that touch neither the bottom row nor any row at or above y_surface and hold at least
+    min_area nodes, as [(area, y_centroid, x_extent)], largest first."""
     out = []
-    for k in range(1, n + 1):
-        ys, xs = np.nonzero(lab == k)
-        if ys.min() == 0 or ys.max() >= y_surface or len(ys) < min_area:
+    for c in components:
+        if c["y_min"] == 0 or c["y_max"] >= y_surface or c["area"] < min_area:
             continue
-        out.append((int(len(ys)), float(ys.mean()), int(xs.max() - xs.min() + 1)))
+        out.append((c["area"], c["y_sum"] / c["area"], c["x_max"] - c["x_min"] + 1))
     out.sort(reverse=True)
     return out
 
@@ -141,8 +106,10 @@ def sweep(workloads, rho_l: float, rho_g: float, max_steps: int = 60000, check_e
                 res[i].profile_checks += 1
                 if not gap_above_vapour(rows, y_surface):
                     continue
-                rho = s.fields()[0]
-                found = departed_bubbles(rho, rho_mid, y_surface, min_area)
+                # components of the rows up to the surface, labelled on the device: one that reaches
+                # row y_surface is excluded whether or not it continues above
+                comps = s.vapour_components(rho_mid, 0, min(ny, y_surface + 1))
+                found = departed(comps, y_surface, min_area)
                 if not found:
                     continue
                 area, yc, xext = found[0]

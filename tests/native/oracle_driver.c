@@ -1,0 +1,42 @@
+/* Test driver of the oracle built with AddressSanitizer and UndefinedBehaviorSanitizer: the oracle's
+   source is compiled into this program.  Reads [orc_params][int64 steps][rho, ux, uy, T as
+   double[ny][nx] each] from argv[1], runs the steps, writes [int32 status][rho, ux, uy, T][f, g,
+   history] to argv[2].  Exit status 0 unless the files cannot be read or written (a sanitizer
+   finding aborts the program). */
+#include "../../oracle/lbm_oracle.c"
+
+#include <stdio.h>
+
+static int read_all(FILE* fp, void* dst, size_t bytes) { return fread(dst, 1, bytes, fp) == bytes; }
+
+int main(int argc, char** argv) {
+  if (argc != 3) return 2;
+  FILE* in = fopen(argv[1], "rb");
+  if (!in) return 2;
+  orc_params p;
+  int64_t steps = 0;
+  if (!read_all(in, &p, sizeof(p)) || !read_all(in, &steps, sizeof(steps))) return 2;
+  const size_t n = (size_t)p.nx * (size_t)p.ny;
+  double* fields = (double*)malloc(4 * n * sizeof(double));
+  if (!fields || !read_all(in, fields, 4 * n * sizeof(double))) return 2;
+  fclose(in);
+  orc_state* s = orc_new(&p);
+  if (!s) return 3;
+  orc_init(s, fields, fields + n, fields + 2 * n, fields + 3 * n);
+  int32_t status = (int32_t)orc_step(s, (long)steps);
+  if (status == 0) status = (int32_t)orc_fields(s, fields, fields + n, fields + 2 * n, fields + 3 * n);
+  const int q = p.thermal_q == 9 ? 9 : 5;
+  double* st = (double*)malloc((9 + (size_t)q + 2) * n * sizeof(double));
+  if (!st) return 2;
+  orc_get_state(s, st, st + 9 * n, st + (9 + (size_t)q) * n);
+  FILE* out = fopen(argv[2], "wb");
+  if (!out) return 2;
+  fwrite(&status, sizeof(status), 1, out);
+  fwrite(fields, sizeof(double), 4 * n, out);
+  fwrite(st, sizeof(double), (9 + (size_t)q + 2) * n, out);
+  fclose(out);
+  orc_free(s);
+  free(st);
+  free(fields);
+  return 0;
+}

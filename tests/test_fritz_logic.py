@@ -1,9 +1,11 @@
-"""Host side of the bubble-departure readout: labelling of vapour components (8-connected,
-periodic in x), selection of departed bubbles, the row-profile trigger, and the power-law fit."""
+"""Host side of the bubble-departure readout: selection of departed bubbles among vapour
+components (labelled on the device; here by the oracle's labelling of the same rows), the
+row-profile trigger, and the power-law fit."""
 import math
 
 import numpy as np
 
+from oracle.components import vapour_components
 from paper_2205_00686_amd import fritz
 
 RL, RG = 6.5, 0.38
@@ -24,33 +26,40 @@ def _disk(rho, x0, y0, r):
     return rho
 
 
+def _departed(rho, y_surface, min_area=12):
+    # the components as the device returns them, here from the oracle's labelling of the same rows
+    comps = vapour_components(rho, MID, 0, y_surface + 1)
+    return fritz.departed(comps, y_surface, min_area)
+
+
 def test_departed_bubble_area_and_exclusions():
     rho = _disk(_pool(), 60, 80, 10.0)
-    found = fritz.departed_bubbles(rho, MID, y_surface=150)
+    found = _departed(rho, y_surface=150)
     assert len(found) == 1
     area, yc, xext = found[0]
     assert abs(area - math.pi * 100) < 0.05 * math.pi * 100 and abs(yc - 80) < 0.5 and xext == 21
     # attached to the wall: not departed
-    assert fritz.departed_bubbles(_disk(_pool(), 60, 8, 10.0), MID, y_surface=150) == []
+    assert _departed(_disk(_pool(), 60, 8, 10.0), y_surface=150) == []
     # merged with the vapour above the pool: not departed
-    assert fritz.departed_bubbles(_disk(_pool(), 60, 155, 10.0), MID, y_surface=150) == []
+    assert _departed(_disk(_pool(), 60, 155, 10.0), y_surface=150) == []
     # two bubbles: largest first; one below the area cut
     rho = _disk(_disk(_pool(), 30, 60, 8.0), 90, 100, 2.0)
-    found = fritz.departed_bubbles(rho, MID, y_surface=150, min_area=20)
+    found = _departed(rho, y_surface=150, min_area=20)
     assert len(found) == 1 and abs(found[0][1] - 60) < 0.5
+    found = _departed(rho, y_surface=150, min_area=1)
+    assert len(found) == 2 and found[0][0] > found[1][0]
 
 
-def test_components_join_across_the_periodic_boundary():
-    rho = _disk(_pool(), 0, 80, 8.0)  # centred on x = 0: split in two by the array edge
-    lab, n = fritz.label_vapour(rho[:150] < MID)
-    assert n == 1
-    found = fritz.departed_bubbles(rho, MID, y_surface=150)
-    assert len(found) == 1 and abs(found[0][0] - math.pi * 64) < 0.06 * math.pi * 64
-    # diagonal contact across the edge joins too
-    m = np.zeros((6, 10), dtype=bool)
-    m[2, 0] = True
-    m[3, 9] = True
-    assert fritz.label_vapour(m)[1] == 1
+def test_rows_up_to_the_surface_give_the_departures_of_the_whole_field():
+    # a component that reaches the surface row is excluded whether or not the labelled rows
+    # continue above it, so labelling rows [0, y_surface] finds what labelling every row finds
+    rng = np.random.default_rng(8)
+    for _ in range(5):
+        rho = _pool(nx=60, ny=80, surface=70)
+        for _ in range(6):
+            rho = _disk(rho, rng.uniform(0, 60), rng.uniform(0, 80), rng.uniform(1, 9))
+        whole = fritz.departed(vapour_components(rho, MID), 64)
+        assert _departed(rho, y_surface=64) == whole
 
 
 def test_row_profile_trigger():
