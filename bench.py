@@ -44,9 +44,9 @@ TRAFFIC3D = {(256, 0, 0): 3986283140}
 # HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by the
 # same counters read for a plain copy of known size (profiles/): (workload, nx, ny, shape, dtype) ->
 # bytes and the digest of the kernel sources profiled (reported only while the sources match)
-TRAFFIC = {("boiling", 1024, 2048, 2, "f32"): {"bytes": 272039872, "kernel_sha": "ecce28044270a8a8"},
-           ("evaporation", 4096, 4096, 6, "f32"): {"bytes": 2300824416, "kernel_sha": "ecce28044270a8a8"},
-           ("evaporation", 4096, 4096, 2, "f32"): {"bytes": 2323528384, "kernel_sha": "ecce28044270a8a8"}}
+TRAFFIC = {("boiling", 1024, 2048, 2, "f32"): {"bytes": 271963648, "kernel_sha": "9e6b69e849a6542b"},
+           ("evaporation", 4096, 4096, 6, "f32"): {"bytes": 2301203558, "kernel_sha": "9e6b69e849a6542b"},
+           ("evaporation", 4096, 4096, 2, "f32"): {"bytes": 2322731110, "kernel_sha": "9e6b69e849a6542b"}}
 
 
 def build_workload(nx=512, ny=512, steps=20000, kind="evaporation"):
