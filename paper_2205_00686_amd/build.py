@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", n) for n in ("lbm.hip", "lbm3d.hip", "hbm_copy.hip")]
-HEADERS = [os.path.join(HERE, "csrc", n) for n in ("lbm_device.hpp", "lbm_step.hpp", "lbm_aux.hpp")] + \
+HEADERS = [os.path.join(HERE, "csrc", n) for n in ("lbm_device.hpp", "lbm_step.hpp", "lbm_aux.hpp", "host_range.hpp")] + \
           [os.path.join(ROOT, "include", n) for n in ("lbm.h", "lbm3d.h")]
 OUT = os.path.join(HERE, "liblbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -18,7 +18,9 @@ FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          "-ffp-contract=on",
          # no packed FP32 instructions (v_pk_*_f32) anywhere in the device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I" + os.path.join(ROOT, "include")]
+         "-I" + os.path.join(ROOT, "include"),
+         # host ranges in the profiler's marker trace (csrc/host_range.hpp)
+         "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 def build(verbose: bool = False) -> str:

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "host_range.hpp"
 #include "lbm_aux.hpp"
 #include "lbm_step.hpp"
 
@@ -605,6 +606,7 @@ static lbm_status write_clock(lbm_ctx* h) {
 }
 
 lbm_status lbm_init(lbm_ctx* h, const double* rho, const double* ux, const double* uy, const double* T) {
+  lbm::HostRange range_("lbm_init");
   if (!h || !rho || !ux || !uy || !T) return LBM_E_INVAL;
   if (h->batch_unsynced) return unsynced(h, "lbm_init");
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
@@ -766,6 +768,7 @@ static lbm_status step_window(lbm_ctx* h, int64_t n) {
 static lbm_status enqueue_diagnostics(lbm_ctx* h, DiagRecord* rec);
 
 lbm_status lbm_step(lbm_ctx* h, int64_t n) {
+  lbm::HostRange range_("lbm_step");
   if (!h || n < 0) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_step before lbm_init");
   if (h->batch_unsynced) return unsynced(h, "lbm_step");
@@ -873,6 +876,7 @@ static void current_buffers(lbm_ctx* h, void*& f, void*& g, void*& fo) {
 static void* current_history(lbm_ctx* h) { return (h->hgen & 1) ? h->ThB : h->ThA; }
 
 lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, double* T) {
+  lbm::HostRange range_("lbm_read_fields");
   if (!h) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_read_fields before lbm_init");
   if (h->batch_unsynced) return unsynced(h, "lbm_read_fields");
@@ -920,6 +924,7 @@ static lbm_status enqueue_diagnostics(lbm_ctx* h, DiagRecord* rec) {
 }
 
 lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy) {
+  lbm::HostRange range_("lbm_diagnostics");
   if (!h) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_diagnostics before lbm_init");
   if (h->batch_unsynced) return unsynced(h, "lbm_diagnostics");
@@ -965,6 +970,7 @@ lbm_status lbm_read_diagnostics_log(lbm_ctx* h, int64_t* steps, double* mass, do
 }
 
 lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi, int32_t* counts) {
+  lbm::HostRange range_("lbm_vapour_rows");
   if (!h || !counts || !std::isfinite(rho_threshold) || x_hi <= x_lo || x_hi - x_lo > h->prm.nx) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_vapour_rows before lbm_init");
   if (h->batch_unsynced) return unsynced(h, "lbm_vapour_rows");
@@ -991,6 +997,7 @@ lbm_status lbm_vapour_rows(lbm_ctx* h, double rho_threshold, int x_lo, int x_hi,
 
 lbm_status lbm_vapour_components(lbm_ctx* h, double rho_threshold, int y_lo, int y_hi, lbm_component* out,
                                  int max_out, int* n_total) {
+  lbm::HostRange range_("lbm_vapour_components");
   if (!h || !n_total || max_out < 0 || (max_out > 0 && !out) || !std::isfinite(rho_threshold)) return LBM_E_INVAL;
   if (y_lo < 0 || y_hi > h->prm.ny || y_hi <= y_lo) return LBM_E_INVAL;
   *n_total = 0;
@@ -1071,6 +1078,7 @@ static size_t planes_bytes(const lbm_ctx* h) { return state_planes(h) * h->N * h
 size_t lbm_state_bytes(const lbm_ctx* h) { return h ? planes_bytes(h) + sizeof(StateTrailer) : 0; }
 
 lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
+  lbm::HostRange range_("lbm_save_state");
   if (!h || !host) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_save_state before lbm_init");
   if (h->batch_unsynced) return unsynced(h, "lbm_save_state");
@@ -1104,6 +1112,7 @@ lbm_status lbm_save_state(lbm_ctx* h, void* host, size_t bytes) {
 }
 
 lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
+  lbm::HostRange range_("lbm_load_state");
   if (!h || !host) return LBM_E_INVAL;
   if (h->batch_unsynced) return unsynced(h, "lbm_load_state");
   if (bytes != lbm_state_bytes(h)) return fail(h, LBM_E_INVAL, "buffer size differs from lbm_state_bytes");
@@ -1144,6 +1153,7 @@ lbm_status lbm_load_state(lbm_ctx* h, const void* host, size_t bytes) {
 }
 
 lbm_status lbm_read_state(lbm_ctx* h, double* f, double* g, double* hist) {
+  lbm::HostRange range_("lbm_read_state");
   if (!h) return LBM_E_INVAL;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_read_state before lbm_init");
   if (h->batch_unsynced) return unsynced(h, "lbm_read_state");
@@ -1479,6 +1489,7 @@ static lbm_status batch_launch(lbm_batch* b, int nl) {
 }
 
 lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
+  lbm::HostRange range_("lbm_batch_step");
   if (!b || k < 0) return LBM_E_INVAL;
   if (k == 0) return LBM_OK;
   lbm_ctx* h0 = b->ctx[0];
@@ -1529,6 +1540,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
 }
 
 lbm_status lbm_batch_sync(lbm_batch* b, lbm_status* status) {
+  lbm::HostRange range_("lbm_batch_sync");
   if (!b) return LBM_E_INVAL;
   const size_t n = b->ctx.size();
   // The launches already enqueued have advanced the members (their buffer parities and step

@@ -25,6 +25,7 @@
 
 #include "lbm3d.h"
 #include "lbm_device.hpp"
+#include "host_range.hpp"
 
 namespace lbm3 {
 using lbm::DevParams;
@@ -1113,6 +1114,7 @@ lbm_status lbm3d_create(const lbm3d_params* p, void* dev_mem, size_t bytes, void
 
 lbm_status lbm3d_init(lbm3d_ctx* h, const double* rho, const double* ux, const double* uy, const double* uz,
                       const double* T) {
+  lbm::HostRange range_("lbm3d_init");
   if (!h || !rho || !ux || !uy || !uz || !T) return LBM_E_INVAL;
   const size_t N = h->N;
   double sumT = 0.0, rmin = std::numeric_limits<double>::infinity();
@@ -1147,6 +1149,7 @@ lbm_status lbm3d_init(lbm3d_ctx* h, const double* rho, const double* ux, const d
 }
 
 lbm_status lbm3d_step(lbm3d_ctx* h, int64_t n) {
+  lbm::HostRange range_("lbm3d_step");
   if (!h || n < 0) return LBM_E_INVAL;
   if (!h->initialised) return fail3(h, LBM_E_STATE, "lbm3d_step before lbm3d_init");
   if (h->failed) return fail3(h, LBM_E_STATE, "context has failed: " + h->last_error);
@@ -1166,6 +1169,7 @@ lbm_status lbm3d_sync(lbm3d_ctx* h) {
 }
 
 lbm_status lbm3d_read_fields(lbm3d_ctx* h, double* rho, double* ux, double* uy, double* uz, double* T) {
+  lbm::HostRange range_("lbm3d_read_fields");
   if (!h) return LBM_E_INVAL;
   if (!h->initialised) return fail3(h, LBM_E_STATE, "read before init");
   if (h->prm.precision == LBM_FP64) launch_fields<double>(h);

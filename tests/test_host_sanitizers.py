@@ -54,7 +54,8 @@ def host_driver(build_dir):
     drv = str(build_dir / "host_abi_driver.o")
     _run([HIPCC, *common, "-c", os.path.join(NATIVE, "host_abi_driver.cpp"), "-o", drv])
     exe = str(build_dir / "host_abi_driver")
-    _run([HIPCC, "-fgpu-rdc", "--offload-arch=gfx950", *HOST_SAN, "-o", exe, drv, *objs])
+    _run([HIPCC, "-fgpu-rdc", "--offload-arch=gfx950", *HOST_SAN, "-o", exe, drv, *objs,
+          "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"])
     return exe
 
 
