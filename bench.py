@@ -234,6 +234,11 @@ def run_serve_mode(args):
                           keep_results=False)
     _, served = server.run(mk())
     print(f"[bench] served: {json.dumps(served)}", file=sys.stderr, flush=True)
+    # the same stream with shortest-work-first admission (the oldest request goes first after max_wait)
+    shortest = serve.Server(hbm_budget=int(args.hbm_budget_gb * 2**30), max_slots=args.slots, chunk=args.chunk,
+                            keep_results=False, policy="shortest", max_wait=args.max_wait)
+    _, served_sw = shortest.run(mk())
+    print(f"[bench] served, shortest work first: {json.dumps(served_sw)}", file=sys.stderr, flush=True)
     _, base_line = serve.fifo(mk(), keep_results=False)
     out = {"metric": METRIC, "mode": "served (continuous batching) vs FIFO plain", "unit": "MLUPS", "n_gpus": 1,
            "dtype": "f32",
@@ -241,7 +246,7 @@ def run_serve_mode(args):
                                   f"{args.rate} req/s, grids log-uniform 128x128..1024x2048, steps uniform "
                                   f"[{args.min_steps}, {args.max_steps}]",
                       "hbm_budget_gb": args.hbm_budget_gb, "slots": args.slots, "chunk": args.chunk},
-           "served": served, "fifo": base_line}
+           "served": served, "served_shortest_first": dict(served_sw, max_wait_s=args.max_wait), "fifo": base_line}
     print(json.dumps(out), flush=True)
 
 
@@ -812,6 +817,8 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=8.0)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--chunk", type=int, default=512)
+    ap.add_argument("--max-wait", type=float, default=5.0,
+                    help="serve: seconds after which the oldest queued request is admitted first (shortest-work policy)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 2000; 10000 with --mode batch)")
     ap.add_argument("--warmup", type=int, default=100)

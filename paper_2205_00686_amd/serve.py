@@ -8,6 +8,13 @@ per step (graph-replayed), each stopping at its own step count; between chunks f
 are read back and retired and newly arrived ones join.  A request's result is bit-identical to
 running it alone (the batched launch executes the same kernel on every node).
 
+Admission order: "arrival" (the default) admits queued requests strictly in arrival order, so a
+request that does not fit holds back the ones behind it.  "shortest" admits, among the queued
+requests whose fields are ready, the one with the least work (nodes x steps) first, and lets a
+smaller one pass a larger one that does not fit yet; once the oldest queued request has waited
+`max_wait` seconds it is admitted next regardless of its size, which bounds how long the largest
+requests can be passed over.
+
 `fifo()` is the baseline: one request at a time, in arrival order, each with its own plain
 lbm_step launches.
 """
@@ -60,7 +67,12 @@ def summarize(reqs, t0, t1):
 
 class Server:
     def __init__(self, hbm_budget: int, max_slots: int = 64, chunk: int = 512, precision: int = LBM_FP32,
-                 keep_results: bool = True, prepare_workers: int = 4, streams: int = 4):
+                 keep_results: bool = True, prepare_workers: int = 4, streams: int = 4, policy: str = "arrival",
+                 max_wait: float = 5.0):
+        if policy not in ("arrival", "shortest"):
+            raise ValueError(f"unknown admission policy {policy!r}")
+        self.policy = policy
+        self.max_wait = float(max_wait)
         self.hbm_budget = int(hbm_budget)
         self.max_slots = int(max_slots)
         self.chunk = int(chunk)
@@ -114,20 +126,19 @@ class Server:
                     log(r)
             finishing = []
             while queued and len(running) + len(ready) < self.max_slots:
-                r = queued[0]
-                fut = prep[r.rid]
-                if not fut.done():
+                r = self._next(queued, prep, now())
+                if r is None:
                     break
-                w = fut.result()
+                w = prep[r.rid].result()
                 need = footprint_bytes(w.params, self.precision)
                 if used + need > self.hbm_budget:
                     if not (running or ready or inflight) and need > self.hbm_budget:
-                        queued.popleft()
+                        queued.remove(r)
                         r.error = "footprint exceeds the HBM budget"
                         r.t_done = now()
                         continue
-                    break
-                queued.popleft()
+                    break  # wait for room (under "shortest" nothing smaller is ready either)
+                queued.remove(r)
                 del prep[r.rid]
                 try:
                     st = req_streams[admitted % len(req_streams)]
@@ -183,6 +194,27 @@ class Server:
             batch.close()
         torch.cuda.synchronize()
         return reqs, summarize(reqs, 0.0, now())
+
+
+    def _next(self, queued, prep, t):
+        """The queued request to admit next, or None while its fields are still being prepared."""
+        if self.policy == "arrival":
+            r = queued[0]
+            return r if prep[r.rid].done() else None
+        # shortest: a request that has waited max_wait seconds goes first (in arrival order)
+        head = queued[0]
+        if t - head.t_arrive >= self.max_wait:
+            return head if prep[head.rid].done() else None
+        best, work = None, None
+        for r in queued:
+            fut = prep[r.rid]
+            if not fut.done():
+                continue
+            w = fut.result()
+            wk = w.nodes * r.steps
+            if best is None or wk < work:
+                best, work = r, wk
+        return best
 
 
 def _new_stream():

@@ -1,6 +1,6 @@
 """Continuous-batching server: every request's result is bit-identical to running it alone, also
-when admission is limited by the HBM budget and requests join while others run; a failing request
-does not disturb the others."""
+when admission is limited by the HBM budget and requests join while others run, under either
+admission order; a failing request does not disturb the others."""
 import numpy as np
 import pytest
 
@@ -32,7 +32,8 @@ def _mix(lbm):
     ]
 
 
-def test_served_results_equal_alone(lbm):
+@pytest.mark.parametrize("policy", ["arrival", "shortest"])
+def test_served_results_equal_alone(lbm, policy):
     from paper_2205_00686_amd import serve
     mix = _mix(lbm)
     alone = []
@@ -44,10 +45,10 @@ def test_served_results_equal_alone(lbm):
         s.close()
     # budget for about three of these at once: admission waits, later requests join mid-run
     fp = max(lbm.footprint_bytes(make().params) for _, _, make in mix)
-    server = serve.Server(hbm_budget=3 * fp, max_slots=3, chunk=64)
+    server = serve.Server(hbm_budget=3 * fp, max_slots=3, chunk=64, policy=policy)
     reqs = [serve.Request(rid=i, arrival=a, steps=n, make=m) for i, (a, n, m) in enumerate(mix)]
     done, summary = server.run(reqs, realtime=False)
-    print("\n[case] serve mix:", summary, flush=True)
+    print(f"\n[case] serve mix, {policy} admission:", summary, flush=True)
     assert summary["completed"] == len(mix)
     for r in done:
         for got, exp in zip(r.result, alone[r.rid]):
