@@ -342,7 +342,7 @@ lbm_status lbm_batch_destroy(lbm_batch* b);
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
    loops, harnesses that forbid allocation): lbm_batch_create without the caller's table memory.
    The batch's instance table and clock live in a static device array of the library instead, one
-   per device, sized for LBM_BATCH_NOALLOC_MAX instances (about 120 KiB, held by each device the
+   per device, sized for LBM_BATCH_NOALLOC_MAX instances (about 130 KiB, held by each device the
    library runs on until the process ends).  Everything else is as lbm_batch_create, and the batch
    gives the same results.  The members must be on the current device.  One such batch may exist
    per device at a time: LBM_E_STATE while another one does (lbm_batch_destroy releases it).  The

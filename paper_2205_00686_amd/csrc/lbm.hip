@@ -317,6 +317,10 @@ static InstDesc<real> make_desc(lbm_ctx* h, int shape) {
   D.ntx = (h->prm.nx + TX - 1) / TX;
   D.nty = (h->prm.ny + ty - 1) / ty;
   D.strip = tile_strip(h, D.ntx, shape);
+  const int nstrips = (D.ntx + D.strip - 1) / D.strip;
+  D.div_band = make_fast_div((unsigned)(D.strip * D.nty));
+  D.div_strip = make_fast_div((unsigned)D.strip);
+  D.div_last = make_fast_div((unsigned)(D.ntx - (nstrips - 1) * D.strip));
   D.tile_begin = 0;
   D.b_base = 0;
   D.h_base = 0;

@@ -93,6 +93,30 @@ struct InstLive {
   double rho_ave;  // mass / (nx ny)
 };
 
+// Division by a constant that is fixed per instance, as a multiply-high, an add and two shifts
+// (Granlund and Montgomery, division by invariant integers using multiplication, 1994: the
+// round-up method for N = 32 bits).  Exact for every 32-bit unsigned numerator; the constants
+// come from make_fast_div on the host.  Used where the tile index is split into the tile's column
+// and row, which a generic integer division would do with a few dozen scalar instructions.
+struct FastDiv {
+  unsigned m, s1, s2;
+};
+
+__host__ __device__ __forceinline__ unsigned fast_div(unsigned n, FastDiv d) {
+  const unsigned t = (unsigned)(((unsigned long long)d.m * n) >> 32);
+  return (t + ((n - t) >> d.s1)) >> d.s2;
+}
+
+// l = ceil(log2 d); m = floor(2^32 (2^l - d) / d) + 1 (taken modulo 2^32); s1 = min(l, 1);
+// s2 = max(l - 1, 0).  d >= 1.
+inline FastDiv make_fast_div(unsigned d) {
+  unsigned l = 0;
+  while (l < 32 && (1ull << l) < d) ++l;
+  const unsigned long long two_l = 1ull << l;
+  const unsigned m = (unsigned)(((two_l - d) << 32) / d + 1);
+  return FastDiv{m, l < 1 ? l : 1u, l > 1 ? l - 1 : 0u};
+}
+
 // One simulation as seen by the step kernel.  The step kernel serves single runs (a one-entry
 // table) and batches (many entries) with the same code.
 template <typename real>
@@ -107,6 +131,9 @@ struct InstDesc {
   int nx, ny;
   int ntx, nty;        // tiles along x and y
   int strip;           // tile order: strips of this many tile columns (>= ntx: whole rows)
+  FastDiv div_band;    // division by strip * nty (tiles in one strip)
+  FastDiv div_strip;   // division by the strip width, and by the width of the last strip
+  FastDiv div_last;
   int tile_begin;      // first workgroup index of this instance in the launch
   int b_base;          // 1 if the current state is in the B buffers at clock t_base
   int h_base;          // 1 if the temperature history is in ThB at clock t_base

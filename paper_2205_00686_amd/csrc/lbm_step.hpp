@@ -858,12 +858,14 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
 // whose rows it reads as halo, are processed shortly before and after it on the same XCD, and its
 // halo reads hit that XCD's L2; with whole rows in order they are a grid row of tiles away, which on
 // grids beyond the Infinity Cache is too far for the L2 to keep them.
-__device__ __forceinline__ void tile_position(int tile, int ntx, int nty, int strip, int& bx, int& by) {
-  const int per_strip = strip * nty;
-  const int s = tile / per_strip;
-  const int local = tile - s * per_strip;
-  const int w = min(strip, ntx - s * strip);  // the last strip may be narrower
-  by = local / w;
+template <typename real>
+__device__ __forceinline__ void tile_position(int tile, const InstDesc<real>& D, int& bx, int& by) {
+  const int strip = D.strip;
+  const int s = (int)fast_div((unsigned)tile, D.div_band);  // tile / (strip * nty)
+  const int local = tile - s * strip * D.nty;
+  const bool last = D.ntx - s * strip < strip;  // the last strip may be narrower
+  const int w = last ? D.ntx - s * strip : strip;
+  by = (int)fast_div((unsigned)local, last ? D.div_last : D.div_strip);
   bx = s * strip + (local - by * w);
 }
 
@@ -893,7 +895,7 @@ __device__ __forceinline__ void step_tile(const InstDesc<real>* __restrict__ tab
   const int tile = bid - D.tile_begin;
   if (tile < 0 || tile >= D.ntx * D.nty) return;
   int bx, by;
-  tile_position(tile, D.ntx, D.nty, D.strip, bx, by);
+  tile_position(tile, D, bx, by);
   const int x0 = bx * TX, y0 = by * S::TY;
   const bool odd = ((b_base + (t - t_base) / S::DEPTH) & 1) != 0;
   // the history changes copy once per launch that does two steps (every launch of a two-step
@@ -1140,7 +1142,7 @@ __global__ __launch_bounds__(S::NT) void persist_kernel(const InstDesc<real>* __
         drawn = (int)(__hip_atomic_fetch_add(&bar->ticket[xcd], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
                       (unsigned)L * per_launch);
       __syncthreads();
-      const int k = drawn;
+      const int k = __builtin_amdgcn_readfirstlane(drawn);  // uniform: keeps the tile's indexing scalar
       __syncthreads();  // every thread has read the ticket before the next draw
       if (k >= b1 - b0) break;
       // the thread index enters the tile as an opaque value, so that the compiler derives the

@@ -6,6 +6,9 @@
   (compared with the regular build bit for bit), error strings, and every context and batch call
   given invalid arguments.  Leak detection is off for this program: the HIP runtime it links
   keeps allocations of its own until exit.
+* The exact division by per-instance constants that the step kernel uses for tile positions
+  (tests/native/fastdiv_check.cpp), against integer division on every divisor up to 70 000 and on
+  large ones, at and around multiples and at the extremes.
 * Both oracles compiled into tests/native/oracle_driver.c and oracle3d_driver.c, run over every
   boundary kind and thermal lattice on small grids, leak detection on; their results equal the
   regular oracle builds bit for bit (same source, no contraction, only the optimisation level
@@ -73,6 +76,18 @@ def test_host_runtime_under_sanitizers(host_driver):
     assert len(rows) == 8
     for ratio, rl, rg, ps in rows:
         assert (rl, rg, ps) == tuple(lbm.coexistence(base, ratio * Tc))
+
+
+def test_fast_division_is_exact(build_dir):
+    """The multiply-high division the step kernel uses for tile positions, compiled for the host
+    from the same header, against integer division."""
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(build_dir / "fastdiv_check")
+    _run([HIPCC, "--offload-host-only", "-x", "hip", "-std=c++17", "-O1", "-g", *HOST_SAN,
+          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-o", exe, os.path.join(NATIVE, "fastdiv_check.cpp")])
+    r = _run([exe], env=dict(ENV, ASAN_OPTIONS="halt_on_error=1"), timeout=300)
+    assert "mismatches 0" in r.stdout, r.stdout
 
 
 def _gcc(build_dir, src, name):
