@@ -44,9 +44,9 @@ TRAFFIC3D = {(256, 0, 0): 3986283140}
 # HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by the
 # same counters read for a plain copy of known size (profiles/): (workload, nx, ny, shape, dtype) ->
 # bytes and the digest of the kernel sources profiled (reported only while the sources match)
-TRAFFIC = {("boiling", 1024, 2048, 2, "f32"): {"bytes": 271963648, "kernel_sha": "9e6b69e849a6542b"},
-           ("evaporation", 4096, 4096, 6, "f32"): {"bytes": 2301203558, "kernel_sha": "9e6b69e849a6542b"},
-           ("evaporation", 4096, 4096, 2, "f32"): {"bytes": 2322731110, "kernel_sha": "9e6b69e849a6542b"}}
+TRAFFIC = {("boiling", 1024, 2048, 2, "f32"): {"bytes": 272054272, "kernel_sha": "9cb3f38c50adbcfa"},
+           ("evaporation", 4096, 4096, 6, "f32"): {"bytes": 2300995072, "kernel_sha": "9cb3f38c50adbcfa"},
+           ("evaporation", 4096, 4096, 2, "f32"): {"bytes": 2328884531, "kernel_sha": "9cb3f38c50adbcfa"}}
 
 
 def build_workload(nx=512, ny=512, steps=20000, kind="evaporation"):
