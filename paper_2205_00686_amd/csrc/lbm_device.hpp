@@ -184,6 +184,18 @@ __device__ __forceinline__ T opaque(T v) {
   asm volatile("" : "+s"(v));
   return v;
 }
+// Successive planes of one array, first to last: each step adds the (opaque) plane stride to a
+// running base, one 64-bit scalar add per plane where base + i * stride takes a 64-bit multiply.
+template <typename T>
+struct PlaneWalk {
+  gptr<T> p;
+  ptrdiff_t stride;
+  __device__ __forceinline__ gptr<T> next() {
+    const gptr<T> b = sbase(p);
+    p = p + opaque(stride);
+    return b;
+  }
+};
 template <typename real>
 __device__ __forceinline__ real ldb(gptr<const char> base, unsigned off) {
   return *(gptr<const real>)(base + off);

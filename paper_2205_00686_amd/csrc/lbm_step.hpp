@@ -415,10 +415,7 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
   auto wx = [&](int v) { return INTERIOR ? v : wrapi(v, nx, tiny); };
   auto wy = [&](int v) { return (INTERIOR || walls) ? v : wrapi(v, ny, tiny); };
   auto fluid_row = [&](int y) { return INTERIOR || row_kind(y, ny, walls) == 0; };
-  auto fsp = [&](int i) { return sbase(fs + i * opaque(PB)); };
-  auto gsp = [&](int i) { return sbase(gs + i * opaque(PB)); };
-  auto fdp = [&](int i) { return sbase(fd + i * opaque(PB)); };
-  auto gdp = [&](int i) { return sbase(gd + i * opaque(PB)); };
+  auto gdp = [&](int i) { return sbase(gd + i * opaque(PB)); };  // D2Q9 thermal stores
 
   // ---- phase 1: every global load of the tile is issued first (own nodes with their T
   // history, then the halo ring), so that the workgroup waits for memory once.  Own nodes keep
@@ -444,10 +441,11 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
         T1[r] = st.T1[r];
         T2[r] = st.T2[r];
       } else {
+        PlaneWalk<const char> wf{fs, PB}, wg{gs, PB};
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[r][i] = ldb<real>(fsp(i), ob[r]);
+        for (int i = 0; i < 9; ++i) f[r][i] = ldb<real>(wf.next(), ob[r]);
 #pragma unroll
-        for (int i = 0; i < QG; ++i) g[r][i] = ldb<real>(gsp(i), ob[r]);
+        for (int i = 0; i < QG; ++i) g[r][i] = ldb<real>(wg.next(), ob[r]);
         T1[r] = ldb<real>(Ths, ob[r]);
         T2[r] = ldb<real>(sbase(Ths + opaque(PB)), ob[r]);
       }
@@ -477,10 +475,11 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
         for (int i = 0; i < QG; ++i) gr[q][i] = st.sg[i][rey[q]][rex[q]];
       } else {
         const unsigned o = (unsigned)(wy(yg) * nx + wx(x0 - HXW + rex[q])) * (unsigned)SZ;
+        PlaneWalk<const char> wf{fs, PB}, wg{gs, PB};
 #pragma unroll
-        for (int i = 0; i < 9; ++i) fr[q][i] = ldb<real>(fsp(i), o);
+        for (int i = 0; i < 9; ++i) fr[q][i] = ldb<real>(wf.next(), o);
 #pragma unroll
-        for (int i = 0; i < QG; ++i) gr[q][i] = ldb<real>(gsp(i), o);
+        for (int i = 0; i < QG; ++i) gr[q][i] = ldb<real>(wg.next(), o);
       }
     }
   }
@@ -562,34 +561,48 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
     };
     unsigned off;
 
-    // f: push to x + c_i, halfway bounce-back through the walls (Eq. 6)
+    // f: push to x + c_i, halfway bounce-back through the walls (Eq. 6).  The destination planes
+    // are written in order, each receiving the push of its own population and, at a wall, the
+    // bounce-back of the opposite one.  At the top wall the upward populations bounce back; under
+    // an open top they leave instead: the boundary pass after the step reads them from these slots
+    // as the outflow of the top row, then replaces them by the populations that enter from outside.
+    PlaneWalk<char> wd{fd, PB};
     if (freeze) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) stb(fdp(i), o, fs_[i]);
+      for (int i = 0; i < 9; ++i) stb(wd.next(), o, fs_[i]);
     } else {
-      stb(fdp(0), o, fs_[0]);
-      { auto b = dst(fdp(1), 1, 0, off); stb(b, off, fs_[1]); }
-      { auto b = dst(fdp(3), -1, 0, off); stb(b, off, fs_[3]); }
-      if (wall_n) {
-        // bounce-back.  Under an open top the upward populations leave instead: the boundary pass
-        // after the step reads them from these slots as the outflow of the top row, then
-        // replaces them by the populations that enter from outside
-        stb(fdp(4), o, fs_[2]);
-        stb(fdp(7), o, fs_[5]);
-        stb(fdp(8), o, fs_[6]);
-      } else {
-        { auto b = dst(fdp(2), 0, 1, off); stb(b, off, fs_[2]); }
-        { auto b = dst(fdp(5), 1, 1, off); stb(b, off, fs_[5]); }
-        { auto b = dst(fdp(6), -1, 1, off); stb(b, off, fs_[6]); }
+      stb(wd.next(), o, fs_[0]);
+      { const auto pl = wd.next(); const auto b = dst(pl, 1, 0, off); stb(b, off, fs_[1]); }
+      {
+        const auto pl = wd.next();
+        if (!wall_n) { const auto b = dst(pl, 0, 1, off); stb(b, off, fs_[2]); }
+        if (wall_s) stb(pl, o, fs_[4]);
       }
-      if (wall_s) {
-        stb(fdp(2), o, fs_[4]);
-        stb(fdp(5), o, fs_[7]);
-        stb(fdp(6), o, fs_[8]);
-      } else {
-        { auto b = dst(fdp(4), 0, -1, off); stb(b, off, fs_[4]); }
-        { auto b = dst(fdp(7), -1, -1, off); stb(b, off, fs_[7]); }
-        { auto b = dst(fdp(8), 1, -1, off); stb(b, off, fs_[8]); }
+      { const auto pl = wd.next(); const auto b = dst(pl, -1, 0, off); stb(b, off, fs_[3]); }
+      {
+        const auto pl = wd.next();
+        if (!wall_s) { const auto b = dst(pl, 0, -1, off); stb(b, off, fs_[4]); }
+        if (wall_n) stb(pl, o, fs_[2]);
+      }
+      {
+        const auto pl = wd.next();
+        if (!wall_n) { const auto b = dst(pl, 1, 1, off); stb(b, off, fs_[5]); }
+        if (wall_s) stb(pl, o, fs_[7]);
+      }
+      {
+        const auto pl = wd.next();
+        if (!wall_n) { const auto b = dst(pl, -1, 1, off); stb(b, off, fs_[6]); }
+        if (wall_s) stb(pl, o, fs_[8]);
+      }
+      {
+        const auto pl = wd.next();
+        if (!wall_s) { const auto b = dst(pl, -1, -1, off); stb(b, off, fs_[7]); }
+        if (wall_n) stb(pl, o, fs_[5]);
+      }
+      {
+        const auto pl = wd.next();
+        if (!wall_s) { const auto b = dst(pl, 1, -1, off); stb(b, off, fs_[8]); }
+        if (wall_n) stb(pl, o, fs_[6]);
       }
     }
 
@@ -625,44 +638,63 @@ __device__ __forceinline__ void step_body(const InstDesc<real>& D, StepLds<real,
         }
       }
     } else {
+      // D2Q5: the destination planes in order, each receiving the push of its own population and,
+      // at a Dirichlet edge, the anti-bounce-back of the opposite one
       const real ircv = L.irc[ey][ex];
-      stb(gdp(0), o, g[r][0] + (gs_[0] - g[r][0]) * ircv);
       const bool out_e = tb && xg == nx - 1, out_w = tb && xg == 0;
       const bool out_n = (walls || tb) && yg == ny - 1, out_s = (walls || tb) && yg == 0;
       const real two_w = p.two_w1h;
-      if (out_e) {
-        const real up = -gs_[1] + two_w * (p.T_box - p.T_ref);
-        stb(gdp(3), o, g[r][3] + (up - g[r][3]) * ircv);
-      } else {
-        const real gold = L.g[0][ey][ex + 1];
-        auto b = dst(gdp(1), 1, 0, off);
-        stb(b, off, gold + (gs_[1] - gold) * L.irc[ey][ex + 1]);
+      PlaneWalk<char> wg{gd, PB};
+      stb(wg.next(), o, g[r][0] + (gs_[0] - g[r][0]) * ircv);
+      {
+        const auto pl = wg.next();
+        if (!out_e) {
+          const real gold = L.g[0][ey][ex + 1];
+          const auto b = dst(pl, 1, 0, off);
+          stb(b, off, gold + (gs_[1] - gold) * L.irc[ey][ex + 1]);
+        }
+        if (out_w) {
+          const real up = -gs_[3] + two_w * (p.T_box - p.T_ref);
+          stb(pl, o, g[r][1] + (up - g[r][1]) * ircv);
+        }
       }
-      if (out_w) {
-        const real up = -gs_[3] + two_w * (p.T_box - p.T_ref);
-        stb(gdp(1), o, g[r][1] + (up - g[r][1]) * ircv);
-      } else {
-        const real gold = L.g[2][ey][ex - 1];
-        auto b = dst(gdp(3), -1, 0, off);
-        stb(b, off, gold + (gs_[3] - gold) * L.irc[ey][ex - 1]);
+      {
+        const auto pl = wg.next();
+        if (!out_n) {
+          const real gold = L.g[1][ey + 1][ex];
+          const auto b = dst(pl, 0, 1, off);
+          stb(b, off, gold + (gs_[2] - gold) * L.irc[ey + 1][ex]);
+        }
+        if (out_s) {
+          const real Ts = tb ? p.T_box : wall_temperature(p, 0, xw);
+          const real up = -gs_[4] + two_w * (Ts - p.T_ref);
+          stb(pl, o, g[r][2] + (up - g[r][2]) * ircv);
+        }
       }
-      if (out_n) {
-        const real Tn = tb ? p.T_box : p.T_top;
-        const real up = -gs_[2] + two_w * (Tn - p.T_ref);
-        stb(gdp(4), o, g[r][4] + (up - g[r][4]) * ircv);
-      } else {
-        const real gold = L.g[1][ey + 1][ex];
-        auto b = dst(gdp(2), 0, 1, off);
-        stb(b, off, gold + (gs_[2] - gold) * L.irc[ey + 1][ex]);
+      {
+        const auto pl = wg.next();
+        if (!out_w) {
+          const real gold = L.g[2][ey][ex - 1];
+          const auto b = dst(pl, -1, 0, off);
+          stb(b, off, gold + (gs_[3] - gold) * L.irc[ey][ex - 1]);
+        }
+        if (out_e) {
+          const real up = -gs_[1] + two_w * (p.T_box - p.T_ref);
+          stb(pl, o, g[r][3] + (up - g[r][3]) * ircv);
+        }
       }
-      if (out_s) {
-        const real Ts = tb ? p.T_box : wall_temperature(p, 0, xw);
-        const real up = -gs_[4] + two_w * (Ts - p.T_ref);
-        stb(gdp(2), o, g[r][2] + (up - g[r][2]) * ircv);
-      } else {
-        const real gold = L.g[3][ey - 1][ex];
-        auto b = dst(gdp(4), 0, -1, off);
-        stb(b, off, gold + (gs_[4] - gold) * L.irc[ey - 1][ex]);
+      {
+        const auto pl = wg.next();
+        if (!out_s) {
+          const real gold = L.g[3][ey - 1][ex];
+          const auto b = dst(pl, 0, -1, off);
+          stb(b, off, gold + (gs_[4] - gold) * L.irc[ey - 1][ex]);
+        }
+        if (out_n) {
+          const real Tn = tb ? p.T_box : p.T_top;
+          const real up = -gs_[2] + two_w * (Tn - p.T_ref);
+          stb(pl, o, g[r][4] + (up - g[r][4]) * ircv);
+        }
       }
     }
   }
@@ -701,8 +733,6 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
   auto wx = [&](int v) { return INTERIOR ? v : wrapi(v, nx, tiny); };
   auto wy = [&](int v) { return (INTERIOR || walls) ? v : wrapi(v, ny, tiny); };
   auto fluid_row = [&](int y) { return INTERIOR || row_kind(y, ny, walls) == 0; };
-  auto fsp = [&](int i) { return sbase(fs + i * opaque(PB)); };
-  auto gsp = [&](int i) { return sbase(gs + i * opaque(PB)); };
   auto in_c = [](int mx, int my) { return mx >= MXH - HXW - 1 && mx < MX - (MXH - HXW - 1) && my >= MYH - HYW - 1 &&
                                           my < MY - (MYH - HYW - 1); };
   auto in_u = [](int mx, int my) { return mx >= MXH - HXW - 2 && mx < MX - (MXH - HXW - 2) && my >= MYH - HYW - 2 &&
@@ -729,10 +759,11 @@ __device__ __forceinline__ void first_step(const InstDesc<real>& D, Step2Lds<rea
     T1[n] = T2[n] = real(0);
     if (fl[n]) {
       const unsigned o = (unsigned)(wy(ygl) * nx + wx(xgl)) * (unsigned)SZ;
+      PlaneWalk<const char> wf{fs, PB}, wg{gs, PB};
 #pragma unroll
-      for (int i = 0; i < 9; ++i) f[n][i] = ldb<real>(fsp(i), o);
+      for (int i = 0; i < 9; ++i) f[n][i] = ldb<real>(wf.next(), o);
 #pragma unroll
-      for (int i = 0; i < 5; ++i) g[n][i] = ldb<real>(gsp(i), o);
+      for (int i = 0; i < 5; ++i) g[n][i] = ldb<real>(wg.next(), o);
       if (in_c(mx_[n], my_[n])) {
         T1[n] = ldb<real>(Th, o);
         T2[n] = ldb<real>(sbase(Th + opaque(PB)), o);
