@@ -44,9 +44,9 @@ TRAFFIC3D = {(256, 0, 0): 3986283140}
 # HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by the
 # same counters read for a plain copy of known size (profiles/): (workload, nx, ny, shape, dtype) ->
 # bytes and the digest of the kernel sources profiled (reported only while the sources match)
-TRAFFIC = {("boiling", 1024, 2048, 2, "f32"): {"bytes": 272054272, "kernel_sha": "9cb3f38c50adbcfa"},
-           ("evaporation", 4096, 4096, 6, "f32"): {"bytes": 2300995072, "kernel_sha": "9cb3f38c50adbcfa"},
-           ("evaporation", 4096, 4096, 2, "f32"): {"bytes": 2328884531, "kernel_sha": "9cb3f38c50adbcfa"}}
+TRAFFIC = {("boiling", 1024, 2048, 2, "f32"): {"bytes": 272318464, "kernel_sha": "966eada17f7c47e0"},
+           ("evaporation", 4096, 4096, 6, "f32"): {"bytes": 2300944589, "kernel_sha": "966eada17f7c47e0"},
+           ("evaporation", 4096, 4096, 2, "f32"): {"bytes": 2326350336, "kernel_sha": "966eada17f7c47e0"}}
 
 
 def build_workload(nx=512, ny=512, steps=20000, kind="evaporation"):
