@@ -40,7 +40,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LU = {"f32": 128, "f64": 256}  # f 9+9, g 5+5, history 2+2 values per node update
 # Measured HBM bytes per launch of the fused 3-D kernel (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a
 # plain copy): (edge, path, z_chunk) -> bytes, for the kernel as profiled
-TRAFFIC3D = {(256, 0, 0): 3986283140}
+TRAFFIC3D = {(256, 0, 0): {"bytes": 3976907571, "kernel_sha": "dd5e74b3f1075cb1"}}
+KERNEL3D_SOURCES = ("lbm3d.hip", "lbm_device.hpp")
 # HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by the
 # same counters read for a plain copy of known size (profiles/): (workload, nx, ny, shape, dtype) ->
 # bytes and the digest of the kernel sources profiled (reported only while the sources match)
@@ -478,13 +479,15 @@ def run_3d_mode(args):
         s.sync()
         ms = e0.elapsed_time(e1) / steps
         mass, _ = s.diagnostics()
-        traffic = TRAFFIC3D.get((n, path, args.z_chunk))
+        prof = TRAFFIC3D.get((n, path, args.z_chunk))
+        traffic = prof["bytes"] if prof and prof["kernel_sha"] == _kernel_source_sha(KERNEL3D_SOURCES) else None
         achieved = w.nodes * 224 / (ms * 1e-3) / 1e9  # algorithmic GB/s (one launch per step on the fused path)
         rows.append({"grid": f"{n}^3", "path": "fused" if path == 0 else "per-node", "steps": steps,
                      "us_per_step": round(ms * 1e3, 2),
                      "mlups": round(w.nodes / (ms * 1e-3) / 1e6, 1),
                      "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                  "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
+                                  "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                                  "kernel_sha": _kernel_source_sha(KERNEL3D_SOURCES)},
                      "mass_drift": abs(mass / float(w.rho.sum()) - 1.0)})
         print(f"[bench] 3d {rows[-1]}", file=sys.stderr, flush=True)
         s.close()
@@ -544,11 +547,13 @@ def calibration_copy(lbm, mib):
     del src, dst
 
 
-def _kernel_source_sha() -> str:
-    """Digest of the step kernel's sources: a profile's traffic figure applies to this build only."""
+def _kernel_source_sha(names=("lbm_step.hpp", "lbm_device.hpp")) -> str:
+    """Digest of a kernel's sources (default: the two-dimensional step kernel; the fused
+    three-dimensional kernel is lbm3d.hip with lbm_device.hpp): a profile's traffic figure applies
+    to this build only."""
     import hashlib
     h = hashlib.sha1()
-    for name in ("lbm_step.hpp", "lbm_device.hpp"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2205_00686_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

@@ -562,19 +562,27 @@ __global__ __launch_bounds__(64 * TY) void fused3_kernel(Dev3<real> p, Bufs3<rea
   auto st = [](real* base, size_t off, uint32_t byte, real v) {
     lbm::stb<real>(lbm::sbase(lbm::to_global((char*)(base + off))), byte, v);
   };
+  // the planes of one array in order, one 64-bit scalar add per plane (base + i N would multiply)
+  auto walk = [&](const real* base) {
+    return lbm::PlaneWalk<const char>{lbm::to_global((const char*)base), (ptrdiff_t)(stride() * sizeof(real))};
+  };
+  auto walk_out = [&](real* base) {
+    return lbm::PlaneWalk<char>{lbm::to_global((char*)base), (ptrdiff_t)(stride() * sizeof(real))};
+  };
   auto load_plane = [&](uint32_t zb, real(&ff)[19], real(&gg)[7], real(&hff)[19], real(&hgg)[7]) {
-    const size_t N = stride();
     if (own) {
+      auto wf = walk(b.fs), wg = walk(b.gs);
 #pragma unroll
-      for (int i = 0; i < 19; ++i) ff[i] = ld(b.fs, i * N, zb + o_b);
+      for (int i = 0; i < 19; ++i) ff[i] = lbm::ldb<real>(wf.next(), zb + o_b);
 #pragma unroll
-      for (int i = 0; i < 7; ++i) gg[i] = ld(b.gs, i * N, zb + o_b);
+      for (int i = 0; i < 7; ++i) gg[i] = lbm::ldb<real>(wg.next(), zb + o_b);
     }
     if (helper) {
+      auto wf = walk(b.fs), wg = walk(b.gs);
 #pragma unroll
-      for (int i = 0; i < 19; ++i) hff[i] = ld(b.fs, i * N, zb + h_b);
+      for (int i = 0; i < 19; ++i) hff[i] = lbm::ldb<real>(wf.next(), zb + h_b);
 #pragma unroll
-      for (int i = 0; i < 7; ++i) hgg[i] = ld(b.gs, i * N, zb + h_b);
+      for (int i = 0; i < 7; ++i) hgg[i] = lbm::ldb<real>(wg.next(), zb + h_b);
     }
   };
   if (PF) load_plane((uint32_t)wrap1(z0 - 2, nz) * plane_b, fn, gn, hf, hg);
@@ -661,7 +669,6 @@ __global__ __launch_bounds__(64 * TY) void fused3_kernel(Dev3<real> p, Bufs3<rea
         if (flow_now) {
           const int q = pz - 1;
           const uint32_t zq_b = (uint32_t)q * plane_b;
-          const size_t N = stride();
           real fq[19];  // f of plane q
           if constexpr (PF) {
 #pragma unroll
@@ -670,9 +677,10 @@ __global__ __launch_bounds__(64 * TY) void fused3_kernel(Dev3<real> p, Bufs3<rea
 #pragma unroll
             for (int i = 0; i < 19; ++i) fq[i] = f1[i];
           }
+          auto wd = walk_out(b.fd);
           if (freeze) {
 #pragma unroll
-            for (int i = 0; i < 19; ++i) st(b.fd, i * N, zq_b + o_b, fq[i]);
+            for (int i = 0; i < 19; ++i) lbm::stb<real>(wd.next(), zq_b + o_b, fq[i]);
           } else {
             real fs[19];
             flow_collide3(p, fq, rho1, uqx, uqy, uqz, Fx, Fy, Fz, S2, fs);
@@ -683,7 +691,7 @@ __global__ __launch_bounds__(64 * TY) void fused3_kernel(Dev3<real> p, Bufs3<rea
               const uint32_t zz = cz19(i) > 0 ? zp_b : (cz19(i) < 0 ? zm_b : zq_b);
               const uint32_t rr = cy19(i) > 0 ? rp_b : (cy19(i) < 0 ? rm_b : r0_b);
               const uint32_t xx = cx19(i) > 0 ? xp_b : (cx19(i) < 0 ? xm_b : x0_b);
-              st(b.fd, i * N, zz + rr + xx, fs[i]);
+              lbm::stb<real>(wd.next(), zz + rr + xx, fs[i]);
             }
           }
         }
@@ -718,9 +726,11 @@ __global__ __launch_bounds__(64 * TY) void fused3_kernel(Dev3<real> p, Bufs3<rea
       const size_t N = stride();
       const uint32_t zz_b = (uint32_t)zt * plane_b;
       const int sd = (it + 2) & 3;  // staging slot of plane zt
-      st(b.gd, 0, zz_b + o_b, g2[0] + (gs[0] - g2[0]) * ir2);
+      auto wd = walk_out(b.gd);
+      lbm::stb<real>(wd.next(), zz_b + o_b, g2[0] + (gs[0] - g2[0]) * ir2);
 #pragma unroll
       for (int i = 1; i < 7; ++i) {
+        const auto pl = wd.next();  // plane i
         const int dx = cx19(i), dy = cy19(i), dz = cz19(i);
         const int opp = (i & 1) ? i + 1 : i - 1;
         const bool out = p.thermal_box && (gx + dx < 0 || gx + dx >= nx || gy + dy < 0 || gy + dy >= ny ||
@@ -743,7 +753,7 @@ __global__ __launch_bounds__(64 * TY) void fused3_kernel(Dev3<real> p, Bufs3<rea
             ird = L.st[sd][0][ly + 1 + dy][lx + 1 + dx];
             dst = zz_b + (dy > 0 ? rp_b : (dy < 0 ? rm_b : r0_b)) + (dx > 0 ? xp_b : (dx < 0 ? xm_b : x0_b));
           }
-          st(b.gd, i * N, dst, gold + (gs[i] - gold) * ird);
+          lbm::stb<real>(pl, dst, gold + (gs[i] - gold) * ird);
         }
       }
       st(b.Th, N, zz_b + o_b, T1);
