@@ -550,7 +550,7 @@ def calibration_copy(lbm, mib):
 def _kernel_source_sha(names=("lbm_step.hpp", "lbm_device.hpp")) -> str:
     """Digest of a kernel's sources (default: the two-dimensional step kernel; the fused
     three-dimensional kernel is lbm3d.hip with lbm_device.hpp): a profile's traffic figure applies
-    to this build only."""
+    only to sources with the digest it was taken with."""
     import hashlib
     h = hashlib.sha1()
     for name in names:
