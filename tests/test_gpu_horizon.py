@@ -56,8 +56,10 @@ def _area(rho, rl, rg):
     return float(np.clip((rho - rv) / (rl - rv), 0.0, 1.0).sum())
 
 
-def _compare(lbm, orc, w, checkpoints, rl, rg, label):
+def _compare(lbm, orc, w, checkpoints, rl, rg, label, shape=None):
     s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    if shape is not None:
+        s.set_shape(shape)
     o = orc.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
     done, rows = 0, []
     t0 = time.perf_counter()
@@ -146,8 +148,10 @@ def test_boiling_config_fp32_first_steps(lbm, orc):
         assert r["rho"] <= 1e-4 and r["T"] <= 1e-4, r
     fill = head_limited_fill(rl, rg, ps, 2e-5, 2048)
     w = boiling(Tc, rl, rg, nx=1024, ny=2048, gravity=2e-5, seed=1, fill=fill)
-    print(f"[case] boiling 1024x2048 head-limited fill {fill:.3f} fp32 vs oracle", flush=True)
-    for r in _compare(lbm, orc, w, (500, 1000, 2000), rl, rg, "boiling head-limited"):
+    # the benchmark's configuration: this workload, FP32, the 64 x 8 one-step tile shape its autotuner
+    # picks (every shape gives the same bits, test_gpu_shapes.py)
+    print(f"[case] boiling 1024x2048 head-limited fill {fill:.3f} fp32 (shape 2) vs oracle", flush=True)
+    for r in _compare(lbm, orc, w, (500, 1000, 2000), rl, rg, "boiling head-limited", shape=2):
         assert r["rho"] <= 1e-4 and r["T"] <= 1e-4, r
 
 
