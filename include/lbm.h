@@ -291,8 +291,9 @@ size_t lbm_batch_footprint_bytes(int n);
    returned, a member may be used on its own stream (lbm_read_fields, lbm_step, ...) or
    destroyed.  Between an lbm_batch_step that advanced a member and the next lbm_batch_sync, the
    calls that read, write or advance that member's state on its own (lbm_init, lbm_step,
-   lbm_read_fields, lbm_read_state, lbm_diagnostics, lbm_vapour_rows, lbm_vapour_components,
-   lbm_save_state, lbm_load_state, and lbm_batch_create with it as a member) return LBM_E_STATE.
+   lbm_read_fields, lbm_read_state, lbm_diagnostics, lbm_read_diagnostics_log, lbm_vapour_rows,
+   lbm_vapour_components, lbm_save_state, lbm_load_state, and lbm_batch_create with it as a
+   member) return LBM_E_STATE.
    LBM_E_DEVICE if the stream ordering cannot be set up. */
 lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t bytes, void* hip_stream,
                             lbm_batch** out);
@@ -324,6 +325,18 @@ int lbm_batch_get_shape(const lbm_batch* b);
    leaves the kernel; lbm_batch_sync then marks every member failed with LBM_E_DEVICE.
    LBM_E_INVAL for on other than 0 or 1. */
 lbm_status lbm_batch_set_persistent(lbm_batch* b, int on, uint32_t spin_limit);
+
+/* Diagnostics of the members every k steps of the batch (the A12 reduction of lbm_diagnostics,
+   Section 4: FP64 mass and thermal energy), counted over lbm_batch_step calls from this call on:
+   lbm_batch_step splits its launches at every k-th batch step and enqueues, on the batch's stream,
+   the reduction of each member that advanced since its previous record into that member's
+   diagnostics log, tagged with the member's own step count (a member whose budget ended inside
+   the interval is recorded at the step where it stopped).  When every budget runs out inside an
+   interval, the members that advanced are recorded there and the count starts again.  The records are read with
+   lbm_read_diagnostics_log on the member once lbm_batch_sync has returned; they equal
+   lbm_diagnostics of the member at that step bit for bit, and the simulations' results do not
+   change.  k = 0 stops.  LBM_E_INVAL for k < 0. */
+lbm_status lbm_batch_set_diagnostics_interval(lbm_batch* b, int64_t k);
 
 /* Wait for the batch's stream; report per-instance failures in status[n] (may be NULL):
    LBM_E_NUMERIC for a member whose device error word is set (it is parked; returns LBM_E_NUMERIC),

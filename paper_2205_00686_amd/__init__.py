@@ -331,6 +331,12 @@ class Batch:
         _check(_native.lib().lbm_batch_set_persistent(self.handle, 1 if on else 0, int(spin_limit)))
         return self
 
+    def set_diagnostics_interval(self, k: int):
+        """Every k batch steps, each member that advanced gets a (step, mass, energy) record in its
+        own diagnostics log (Solver.diagnostics_log, readable after sync); 0 stops."""
+        _check(_native.lib().lbm_batch_set_diagnostics_interval(self.handle, int(k)))
+        return self
+
     def sync(self):
         """Wait for the batch; per-member status (0, or -4 for a member parked after a numerical
         failure).  Raises LbmError if the wait itself failed or a persistent launch's barrier timed

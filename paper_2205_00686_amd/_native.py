@@ -26,7 +26,7 @@ EXPORTS = (
     "lbm_load_state", "lbm_read_state", "lbm_eos_coexistence", "lbm_critical_temperature", "lbm_destroy", "lbm_strerror",
     "lbm_last_error", "lbm_device_copy", "lbm_batch_footprint_bytes", "lbm_batch_create", "lbm_batch_set_budget", "lbm_batch_step",
     "lbm_batch_remaining", "lbm_batch_set_shape", "lbm_batch_get_shape", "lbm_batch_sync", "lbm_batch_destroy",
-    "lbm_batch_create_noalloc", "lbm_batch_set_persistent",
+    "lbm_batch_create_noalloc", "lbm_batch_set_persistent", "lbm_batch_set_diagnostics_interval",
     "lbm3d_params_default", "lbm3d_validate", "lbm3d_footprint_bytes", "lbm3d_create", "lbm3d_init", "lbm3d_step",
     "lbm3d_sync", "lbm3d_read_fields", "lbm3d_diagnostics", "lbm3d_steps_done", "lbm3d_state_bytes",
     "lbm3d_save_state", "lbm3d_load_state", "lbm3d_destroy",
@@ -140,6 +140,7 @@ def lib():
         "lbm_batch_set_shape": ([vp, ctypes.c_int], st),
         "lbm_batch_get_shape": ([vp], ctypes.c_int),
         "lbm_batch_sync": ([vp, ctypes.POINTER(ctypes.c_int)], st),
+        "lbm_batch_set_diagnostics_interval": ([vp, ctypes.c_int64], st),
         "lbm_batch_destroy": ([vp], st),
         "lbm_batch_create_noalloc": ([ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(vp)], st),
         "lbm_batch_set_persistent": ([vp, ctypes.c_int, ctypes.c_uint32], st),

@@ -162,6 +162,9 @@ struct lbm_batch {
   bool persistent_used = false;        // a persistent launch has been enqueued since the last sync
   unsigned spin_limit = 1u << 24;      // bounded wait of the persistent kernel's grid barrier
   int pgrid = 0, pgrid_shape = -1;     // resident workgroups of the persistent kernel (for shape)
+  int64_t diag_every = 0;              // members' diagnostics every this many batch steps (0: none)
+  int64_t diag_since = 0;              // batch steps since the last such record
+  std::vector<char> moved;             // per member: advanced since its last such record
 };
 
 // Orders the batch stream after every member's stream: one event recorded on each distinct
@@ -909,22 +912,27 @@ lbm_status lbm_read_fields(lbm_ctx* h, double* rho, double* ux, double* uy, doub
 
 // The FP64 mass and energy reduction of the current state on the context's stream: result in
 // d_diag and, if rec is not null, as a record of the current step count at *rec.
-static lbm_status enqueue_diagnostics(lbm_ctx* h, DiagRecord* rec) {
-  void *f, *g, *fo;
-  current_buffers(h, f, g, fo);
+static lbm_status enqueue_diagnostics_of(lbm_ctx* h, hipStream_t stream, const void* f, const void* g,
+                                         DiagRecord* rec, long long step) {
   const size_t N = h->N;
   size_t per = (N + MAX_RED_BLOCKS - 1) / MAX_RED_BLOCKS;
   per = std::max<size_t>(per, RED_NT);
   const int nparts = (int)((N + per - 1) / per);
   if (h->prm.precision == LBM_FP64)
-    diag_partial_kernel<double><<<nparts, RED_NT, 0, h->stream>>>(
+    diag_partial_kernel<double><<<nparts, RED_NT, 0, stream>>>(
         (const double*)f, (const double*)g, N, qg_of(&h->prm), h->prm.cv, h->T_ref, per, h->d_part);
   else
-    diag_partial_kernel<float><<<nparts, RED_NT, 0, h->stream>>>(
+    diag_partial_kernel<float><<<nparts, RED_NT, 0, stream>>>(
         (const float*)f, (const float*)g, N, qg_of(&h->prm), h->prm.cv, h->T_ref, per, h->d_part);
-  diag_final_kernel<<<1, RED_NT, 0, h->stream>>>(h->d_part, nparts, h->d_diag, rec, (long long)h->steps);
+  diag_final_kernel<<<1, RED_NT, 0, stream>>>(h->d_part, nparts, h->d_diag, rec, step);
   HIP_OR_FAIL(h, hipGetLastError());
   return LBM_OK;
+}
+
+static lbm_status enqueue_diagnostics(lbm_ctx* h, DiagRecord* rec) {
+  void *f, *g, *fo;
+  current_buffers(h, f, g, fo);
+  return enqueue_diagnostics_of(h, h->stream, f, g, rec, (long long)h->steps);
 }
 
 lbm_status lbm_diagnostics(lbm_ctx* h, double* mass, double* energy) {
@@ -955,6 +963,7 @@ lbm_status lbm_read_diagnostics_log(lbm_ctx* h, int64_t* steps, double* mass, do
   if (!h || !count || max < 0 || (max > 0 && (!steps || !mass || !energy))) return LBM_E_INVAL;
   *count = 0;
   if (!h->initialised) return fail(h, LBM_E_STATE, "lbm_read_diagnostics_log before lbm_init");
+  if (h->batch_unsynced) return unsynced(h, "lbm_read_diagnostics_log");
   if (!set_device(h)) return fail(h, LBM_E_DEVICE, "hipSetDevice failed");
   DiagRecord ring[DIAG_RING];
   HIP_OR_FAIL(h, hipMemcpyAsync(ring, h->d_ring, sizeof(ring), hipMemcpyDeviceToHost, h->stream));
@@ -1324,6 +1333,7 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int n, void* dev_mem, size_t b
   b->pending.assign(n, 0);
   b->pending_launches.assign(n, 0);
   b->pending_hmoves.assign(n, 0);
+  b->moved.assign(n, 0);
   b->stream = (hipStream_t)hip_stream;
   b->precision = prec;
   b->qg = qg;
@@ -1492,16 +1502,17 @@ static lbm_status batch_launch(lbm_batch* b, int nl) {
   return LBM_OK;
 }
 
-lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
-  lbm::HostRange range_("lbm_batch_step");
-  if (!b || k < 0) return LBM_E_INVAL;
-  if (k == 0) return LBM_OK;
+// Up to k steps of every instance with budget left (each stops at its own budget); *advanced
+// receives the batch steps taken (0 once no instance has budget left).
+static lbm_status batch_advance(lbm_batch* b, int64_t k, int64_t* advanced) {
+  *advanced = 0;
   lbm_ctx* h0 = b->ctx[0];
   // a member that failed was parked by lbm_batch_sync (budget 0): the others go on
   int64_t maxrem = 0;
   for (int64_t r : b->remaining) maxrem = std::max(maxrem, r);
   const int64_t todo = std::min(k, maxrem);
   if (todo == 0) return LBM_OK;
+  *advanced = todo;
   lbm_status st = batch_upload(b, todo);  // every call: the step window of each instance
   if (st != LBM_OK) return st;
   if (b->total_tiles == 0) return LBM_OK;
@@ -1539,7 +1550,58 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
     b->pending_launches[i] += (ran + d - 1) / d;
     b->pending_hmoves[i] += history_moves(ran, d);
     b->remaining[i] -= ran;
+    if (ran > 0) b->moved[i] = 1;
   }
+  return LBM_OK;
+}
+
+// The FP64 mass and energy of member i after the launches enqueued so far, as the next record of
+// its diagnostics log, on the batch's stream (its buffers are those after its pending launches).
+static lbm_status enqueue_member_diagnostics(lbm_batch* b, size_t i) {
+  lbm_ctx* h = b->ctx[i];
+  const bool odd = ((h->gen ^ (int)(b->pending_launches[i] & 1)) & 1) != 0;
+  const void* f = odd ? h->fB : h->fA;
+  const void* g = odd ? h->gB : h->gA;
+  lbm_status s = enqueue_diagnostics_of(h, b->stream, f, g, h->d_ring + h->diag_enqueued % DIAG_RING,
+                                        (long long)(h->steps + b->pending[i]));
+  if (s == LBM_OK) ++h->diag_enqueued;
+  return s;
+}
+
+lbm_status lbm_batch_step(lbm_batch* b, int64_t k) {
+  lbm::HostRange range_("lbm_batch_step");
+  if (!b || k < 0) return LBM_E_INVAL;
+  if (k == 0) return LBM_OK;
+  int64_t adv = 0;
+  if (b->diag_every <= 0) return batch_advance(b, k, &adv);
+  // diagnostics every diag_every batch steps: the launches are split there and each member that
+  // advanced since its last record gets one
+  while (k > 0) {
+    const int64_t seg = std::min(k, b->diag_every - b->diag_since);
+    lbm_status st = batch_advance(b, seg, &adv);
+    if (st != LBM_OK) return st;
+    if (adv == 0) break;
+    k -= seg;
+    b->diag_since += adv;
+    // a record at every k-th batch step, and where the last budget ran out inside an interval
+    if (b->diag_since >= b->diag_every || adv < seg) {
+      for (size_t i = 0; i < b->ctx.size(); ++i)
+        if (b->moved[i]) {
+          st = enqueue_member_diagnostics(b, i);
+          if (st != LBM_OK) return st;
+          b->moved[i] = 0;
+        }
+      b->diag_since = 0;
+    }
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_diagnostics_interval(lbm_batch* b, int64_t k) {
+  if (!b || k < 0) return LBM_E_INVAL;
+  b->diag_every = k;
+  b->diag_since = 0;
+  std::fill(b->moved.begin(), b->moved.end(), (char)0);
   return LBM_OK;
 }
 

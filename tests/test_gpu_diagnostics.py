@@ -68,3 +68,40 @@ def test_every_k_diagnostics(lbm, orc, k, calls, kind):
     assert s.diagnostics_log() == []
     s.close()
     t.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_diagnostics_every_k(lbm, orc, persistent):
+    """Every-k diagnostics of batch members: records at multiples of k batch steps, where a member's
+    budget ends inside an interval, and where the last budget ends; each equals lbm_diagnostics of
+    the member run alone to that step, bit for bit; the members' results are unchanged."""
+    base = Params()
+    Tc = orc.Tc(base)
+    rl, rg, _ = orc.maxwell(base, 0.86 * Tc)
+    ws = [boiling(Tc, rl, rg, nx=96, ny=80, gravity=5e-5, hot_width=6.0, seed=3),
+          heated_droplet(Tc, rl, rg, nx=80, ny=48, R=14.0, T_h_rel=0.95, gy=-5e-5),
+          boiling(Tc, rl, rg, nx=130, ny=70, gravity=3e-5, hot_width=5.0, seed=5)]
+    budgets, k = (260, 123, 310), 50
+    print(f"\n[case] batch diagnostics every {k}, budgets {budgets}, persistent {persistent}", flush=True)
+    sols = [lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T) for w in ws]
+    b = lbm.Batch(sols).set_persistent(persistent).set_diagnostics_interval(k)
+    for i, n in enumerate(budgets):
+        b.set_budget(i, n)
+    b.step(70)
+    b.step(max(budgets))
+    assert b.sync() == [0, 0, 0]
+    for i, (w, n) in enumerate(zip(ws, budgets)):
+        log = sols[i].diagnostics_log()
+        expect = list(range(k, n + 1, k)) + ([n] if n % k else [])
+        assert [r[0] for r in log] == expect, (i, [r[0] for r in log])
+        alone = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+        done = 0
+        for step, m, e in log:
+            alone.step(step - done)
+            done = step
+            assert (m, e) == alone.diagnostics(), (i, step)
+        assert np.array_equal(_raw(alone), _raw(sols[i]))
+        alone.close()
+    b.close()
+    for s in sols:
+        s.close()
