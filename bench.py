@@ -721,6 +721,12 @@ def run_headline(args):
         calibration_copy(lbm, args.calibration_copy_mib)
     tune = choose_shape(s, args.shape)
     print(f"[bench] tile shape {s.shape}: {tune}", file=sys.stderr, flush=True)
+    # untimed steps until the GPU has run settle_ms of them: after the autotuner's short calls and
+    # host work the first launches run 8-10 % slower than in steady operation (clocks ramping up)
+    settle_ms, settle_steps = 0.0, 0
+    while settle_ms < args.settle_ms:
+        settle_ms += _timed_steps(s, 64)
+        settle_steps += 64
     s.step(args.warmup)
     s.sync()
     # ---- the timed region: exactly K steps in one call
@@ -778,6 +784,7 @@ def run_headline(args):
                      "kernel_ms_per_launch": round(ms_per_launch, 6),
                      "measured_hbm_gbs": round(traffic / (ms_per_launch * 1e-3) / 1e9, 1) if traffic else None,
                      "kernel_sha": sha},
+        "settle": {"steps": settle_steps, "gpu_ms": round(settle_ms, 1)},
         "repeats": {"calls": args.repeats, "steps_each": args.steps,
                     "mlups_p50": round(rep[len(rep) // 2], 1) if rep else None,
                     "mlups_min": round(rep[0], 1) if rep else None, "mlups_max": round(rep[-1], 1) if rep else None},
@@ -827,6 +834,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 2000; 10000 with --mode batch)")
     ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--settle-ms", type=float, default=200.0,
+                    help="plain mode: untimed steps for this much GPU time before the warm-up steps")
     ap.add_argument("--workload", choices=["evaporation", "boiling"], default="boiling",
                     help="plain mode: the boiling pool (default) or the evaporation workload")
     ap.add_argument("--nx", type=int, default=1024)
