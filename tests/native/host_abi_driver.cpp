@@ -149,6 +149,7 @@ int main() {
   EXPECT(lbm_batch_remaining(nullptr, 0) < 0);
   EXPECT(lbm_batch_set_shape(nullptr, 0) == LBM_E_INVAL);
   EXPECT(lbm_batch_set_persistent(nullptr, 1, 0) == LBM_E_INVAL);
+  EXPECT(lbm_batch_set_diagnostics_interval(nullptr, 10) == LBM_E_INVAL);
   EXPECT(lbm_batch_sync(nullptr, nullptr) == LBM_E_INVAL);
   EXPECT(lbm_batch_destroy(nullptr) == LBM_E_INVAL);
 
