@@ -1,0 +1,121 @@
+"""GPU runs at the largest grid the library accepts: one FP32 population plane of 65535 x 16383
+nodes is 4 294 639 620 bytes, 320 KiB under the 2^32 - 1 bytes that the step kernel's 32-bit
+byte offsets can address (the limit lbm_validate enforces).  Both tile dimensions are ragged
+(65535 = 1023 x 64 + 63 columns, 16383 = 1023 x 16 + 15 rows).
+
+The oracle cannot run 1.07e9 nodes, so the test uses a property that holds at any size: the
+update of a node depends only on its neighbourhood, so on a grid tiled with copies of a pattern
+(periodic in x, and in y where the grid is periodic) the result is the same tiling of the
+pattern's own result.  The pattern is run twice more, on the GPU and in the FP64 oracle:
+  - the full grid must equal the tiled GPU pattern bit for bit, at every node (each node's
+    arithmetic is fixed by the source, whatever the tile, shape or position);
+  - the GPU pattern must match the oracle within the FP32 bounds of the parity tests.
+The two global scalars of the state are made equal on both grids: the densities and temperatures
+are multiples of 2^-19 and 2^-24, so the FP64 sums behind the mean density (buoyancy, Section 4.3)
+and the temperature storage offset are exact and their means identical.
+
+Each case steps twice with the two-step tile shape (one launch) and twice with a one-step shape,
+so both kernels address the highest offsets.  It needs about 140 GB of device memory and 70 GB of
+host memory.
+"""
+import numpy as np
+import pytest
+
+from workloads import Params, Workload
+
+pytestmark = pytest.mark.gpu
+
+NX, NY = 65535, 16383        # 255 x 257 columns, 127 x 129 rows
+PX, PY = 255, 127            # pattern periods
+STEPS_TWO, STEPS_ONE = 2, 2
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_00686_amd as lbm
+    return lbm
+
+
+def _quantise(a, bits):
+    return np.round(a * 2.0 ** bits) / 2.0 ** bits
+
+
+def _pattern(orc, walls: bool):
+    """Seeded pattern of PX columns: a periodic droplet cell (PY rows) or a full-height walled pool."""
+    base = Params()
+    Tc = orc.Tc(base)
+    rl, rg, _ = orc.maxwell(base, 0.86 * Tc)
+    ny = NY if walls else PY
+    rng = np.random.default_rng(2205 + int(walls))
+    y, x = np.mgrid[0:ny, 0:PX].astype(np.float64)
+    if walls:
+        rho = rg + 0.5 * (rl - rg) * (1.0 - np.tanh((y - 40.0) / 2.5))
+        T = 0.9 * Tc - 0.04 * Tc * y / (ny - 1)
+        p = Params(nx=PX, ny=ny, y_walls=1, T_bot=0.9 * Tc, T_top=0.86 * Tc, theta_bot_deg=75.0,
+                   theta_top_deg=90.0, gy=-2e-5)
+    else:
+        dx = np.minimum(np.abs(x - PX / 2), PX - np.abs(x - PX / 2))
+        dy = np.minimum(np.abs(y - PY / 2), PY - np.abs(y - PY / 2))
+        rho = rg + 0.5 * (rl - rg) * (1.0 - np.tanh((np.hypot(dx, dy) - 30.0) / 2.5))
+        T = 0.88 * Tc + 0.01 * Tc * np.sin(2 * np.pi * x / PX) + 0.005 * Tc * np.cos(2 * np.pi * y / PY)
+        p = Params(nx=PX, ny=ny, gy=-2e-5)
+    rho = _quantise(rho * (1.0 + 1e-3 * rng.uniform(-1, 1, rho.shape)), 19)
+    T = _quantise(T * (1.0 + 1e-4 * rng.uniform(-1, 1, T.shape)), 24)
+    ux = 1e-3 * rng.standard_normal(rho.shape)
+    uy = 1e-3 * rng.standard_normal(rho.shape)
+    return Workload("max-grid pattern", p, rho, ux, uy, T, STEPS_TWO + STEPS_ONE), rl
+
+
+def _run(lbm, w, rows_rep, cols_rep, name):
+    """Solver on the pattern tiled rows_rep x cols_rep times; the two-step shape, then shape 1."""
+    p = w.params.replace(nx=w.params.nx * cols_rep, ny=w.params.ny * rows_rep)
+    s = lbm.Solver(p)
+    s.init(*(np.tile(a, (rows_rep, cols_rep)) for a in (w.rho, w.ux, w.uy, w.T)))
+    two = next(k for k, sh in enumerate(lbm.shapes(lbm.LBM_FP32)) if sh[3] == 2)
+    assert lbm.shape_fits(p, two) and lbm.shape_fits(p, 1)
+    s.set_shape(two).step(STEPS_TWO)
+    s.set_shape(1).step(STEPS_ONE)
+    print(f"   {name} {p.nx}x{p.ny}: stepped", flush=True)
+    out = s.fields()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("walls", [False, True], ids=["periodic", "walled"])
+def test_largest_grid_equals_tiled_pattern(lbm, orc, walls):
+    import torch
+
+    assert NX == PX * 257 and NY == PY * 129
+    # the plane is within 320 KiB of the limit; 65541 columns (4 bytes more per row) are rejected
+    assert 2**32 - 1 - 2**19 < NX * NY * 4 <= 2**32 - 1
+    assert lbm.footprint_bytes(Params(nx=NX, ny=NY)) > 0
+    assert lbm.footprint_bytes(Params(nx=65541, ny=NY)) == 0
+    w, rl = _pattern(orc, walls)
+    print(f"\n[case] largest grid {NX}x{NY} fp32 {'walled' if walls else 'periodic'}", flush=True)
+
+    small = _run(lbm, w, 1, 1, "pattern")
+    ref = orc.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
+    ref.step(STEPS_TWO + STEPS_ONE)
+    exp = ref.fields()
+    err = [float(np.abs(a - b).max()) for a, b in zip(small, exp)]
+    print(f"   pattern vs oracle: rho={err[0]:.3e} ux={err[1]:.3e} uy={err[2]:.3e} T={err[3]:.3e}", flush=True)
+    assert err[0] <= 2e-4 * rl
+    assert err[3] <= 2e-6 * float(np.abs(exp[3]).max())
+    assert max(err[1], err[2]) <= 1e-5
+
+    torch.cuda.empty_cache()
+    rows_rep = 1 if walls else NY // PY
+    big = _run(lbm, w, rows_rep, NX // PX, "full grid")
+    torch.cuda.empty_cache()
+    for name, b, s in zip(("rho", "ux", "uy", "T"), big, small):
+        tiled = b.reshape(rows_rep, w.params.ny, NX // PX, PX)
+        same = tiled == s[None, :, None, :]
+        if not same.all():
+            k = np.argwhere(~same)[0]
+            raise AssertionError(f"{name} differs from the tiled pattern at tile ({k[0]}, {k[2]}), "
+                                 f"pattern node ({k[3]}, {k[1]}): {tiled[tuple(k)]!r} vs {s[k[1], k[3]]!r}")
+        del tiled, same
+    print("   full grid equals the tiled pattern at every node", flush=True)
