@@ -45,9 +45,9 @@ KERNEL3D_SOURCES = ("lbm3d.hip", "lbm_device.hpp")
 # HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes, scaled by the
 # same counters read for a plain copy of known size (profiles/): (workload, nx, ny, shape, dtype) ->
 # bytes and the digest of the kernel sources profiled (reported only while the sources match)
-TRAFFIC = {("boiling", 1024, 2048, 2, "f32"): {"bytes": 272318464, "kernel_sha": "966eada17f7c47e0"},
-           ("evaporation", 4096, 4096, 6, "f32"): {"bytes": 2300944589, "kernel_sha": "966eada17f7c47e0"},
-           ("evaporation", 4096, 4096, 2, "f32"): {"bytes": 2326350336, "kernel_sha": "966eada17f7c47e0"}}
+TRAFFIC = {("boiling", 1024, 2048, 2, "f32"): {"bytes": 272334848, "kernel_sha": "d5db904e983c3fd3"},
+           ("evaporation", 4096, 4096, 6, "f32"): {"bytes": 2301070336, "kernel_sha": "d5db904e983c3fd3"},
+           ("evaporation", 4096, 4096, 2, "f32"): {"bytes": 2325466624, "kernel_sha": "d5db904e983c3fd3"}}
 
 
 def build_workload(nx=512, ny=512, steps=20000, kind="evaporation"):

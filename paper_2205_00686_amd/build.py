@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = [os.path.join(HERE, "csrc", n) for n in ("lbm.hip", "lbm3d.hip", "hbm_copy.hip")]
-HEADERS = [os.path.join(HERE, "csrc", n) for n in ("lbm_device.hpp", "lbm_step.hpp", "lbm_aux.hpp", "host_range.hpp")] + \
+HEADERS = [os.path.join(HERE, "csrc", n) for n in ("lbm_device.hpp", "lbm_step.hpp", "lbm_persist.hpp", "lbm_aux.hpp", "host_range.hpp")] + \
           [os.path.join(ROOT, "include", n) for n in ("lbm.h", "lbm3d.h")]
 OUT = os.path.join(HERE, "liblbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

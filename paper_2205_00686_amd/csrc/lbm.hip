@@ -15,6 +15,7 @@
 #include "host_range.hpp"
 #include "lbm_aux.hpp"
 #include "lbm_step.hpp"
+#include "lbm_persist.hpp"
 
 using namespace lbm;
 
