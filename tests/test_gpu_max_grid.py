@@ -1,7 +1,8 @@
 """GPU runs at the largest grids.  Two dimensions: the largest grid the library accepts, one FP32
 population plane of 65535 x 16383 nodes is 4 294 639 620 bytes, 320 KiB under the 2^32 - 1 bytes
 that the step kernel's 32-bit byte offsets can address (the limit lbm_validate enforces).  Both
-tile dimensions are ragged (65535 = 1023 x 64 + 63 columns, 16383 = 1023 x 16 + 15 rows).  Three
+tile dimensions are ragged (65535 = 1023 x 64 + 63 columns, 16383 = 1023 x 16 + 15 rows).  In FP64
+the same bytes hold 32767 x 16383 nodes (384 KiB under the limit, 511 x 64 + 63 columns).  Three
 dimensions: a grid whose plane is above 2^31 bytes and whose state takes 184 GB (below).
 
 The oracle cannot run 1.07e9 nodes, so the test uses a property that holds at any size: the
@@ -15,8 +16,9 @@ The two global scalars of the state are made equal on both grids: the densities 
 are multiples of 2^-19 and 2^-24, so the FP64 sums behind the mean density (buoyancy, Section 4.3)
 and the temperature storage offset are exact and their means identical.
 
-Each two-dimensional case steps twice with the two-step tile shape (one launch) and twice with a
-one-step shape, so both kernels address the highest offsets; each three-dimensional case runs one
+Each two-dimensional FP32 case steps twice with the two-step tile shape (one launch) and twice
+with a one-step shape, so both kernels address the highest offsets (FP64, which has one-step
+shapes only: 64 x 16 tiles, then 64 x 8); each three-dimensional case runs one
 step path (fused or per-node) for four steps.  The largest case needs 184 GB of device memory and
 about 70 GB of host memory.
 """
@@ -27,8 +29,9 @@ from workloads import Params, Workload
 
 pytestmark = pytest.mark.gpu
 
-NX, NY = 65535, 16383        # 255 x 257 columns, 127 x 129 rows
+NX, NY = 65535, 16383        # FP32: 255 x 257 columns, 127 x 129 rows
 PX, PY = 255, 127            # pattern periods
+NX64, PX64 = 32767, 217      # FP64 (8-byte values): 217 x 151 columns, 384 KiB under the limit
 STEPS_TWO, STEPS_ONE = 2, 2
 
 
@@ -45,7 +48,7 @@ def _quantise(a, bits):
     return np.round(a * 2.0 ** bits) / 2.0 ** bits
 
 
-def _pattern(orc, walls: bool):
+def _pattern(orc, walls: bool, PX: int = PX):
     """Seeded pattern of PX columns: a periodic droplet cell (PY rows) or a full-height walled pool."""
     base = Params()
     Tc = orc.Tc(base)
@@ -71,14 +74,17 @@ def _pattern(orc, walls: bool):
     return Workload("max-grid pattern", p, rho, ux, uy, T, STEPS_TWO + STEPS_ONE), rl
 
 
-def _run(lbm, w, rows_rep, cols_rep, name):
-    """Solver on the pattern tiled rows_rep x cols_rep times; the two-step shape, then shape 1."""
+def _run(lbm, w, rows_rep, cols_rep, name, precision):
+    """Solver on the pattern tiled rows_rep x cols_rep times.  FP32: the two-step shape, then shape 1;
+    FP64 (one-step shapes only): shape 0 (64 x 16 tiles), then shape 1 (64 x 8)."""
     p = w.params.replace(nx=w.params.nx * cols_rep, ny=w.params.ny * rows_rep)
-    s = lbm.Solver(p)
+    s = lbm.Solver(p, precision=precision)
     s.init(*(np.tile(a, (rows_rep, cols_rep)) for a in (w.rho, w.ux, w.uy, w.T)))
-    two = next(k for k, sh in enumerate(lbm.shapes(lbm.LBM_FP32)) if sh[3] == 2)
-    assert lbm.shape_fits(p, two) and lbm.shape_fits(p, 1)
-    s.set_shape(two).step(STEPS_TWO)
+    first = 0
+    if precision == lbm.LBM_FP32:
+        first = next(k for k, sh in enumerate(lbm.shapes(lbm.LBM_FP32)) if sh[3] == 2)
+    assert lbm.shape_fits(p, first, precision) and lbm.shape_fits(p, 1, precision)
+    s.set_shape(first).step(STEPS_TWO)
     s.set_shape(1).step(STEPS_ONE)
     print(f"   {name} {p.nx}x{p.ny}: stepped", flush=True)
     out = s.fields()
@@ -86,34 +92,41 @@ def _run(lbm, w, rows_rep, cols_rep, name):
     return out
 
 
+@pytest.mark.parametrize("fp64", [False, True], ids=["fp32", "fp64"])
 @pytest.mark.parametrize("walls", [False, True], ids=["periodic", "walled"])
-def test_largest_grid_equals_tiled_pattern(lbm, orc, walls):
+def test_largest_grid_equals_tiled_pattern(lbm, orc, walls, fp64):
     import torch
 
-    assert NX == PX * 257 and NY == PY * 129
-    # the plane is within 320 KiB of the limit; 65541 columns (4 bytes more per row) are rejected
-    assert 2**32 - 1 - 2**19 < NX * NY * 4 <= 2**32 - 1
-    assert lbm.footprint_bytes(Params(nx=NX, ny=NY)) > 0
-    assert lbm.footprint_bytes(Params(nx=65541, ny=NY)) == 0
-    w, rl = _pattern(orc, walls)
-    print(f"\n[case] largest grid {NX}x{NY} fp32 {'walled' if walls else 'periodic'}", flush=True)
+    nx, px, vb = (NX64, PX64, 8) if fp64 else (NX, PX, 4)
+    precision = lbm.LBM_FP64 if fp64 else lbm.LBM_FP32
+    assert nx % px == 0 and NY == PY * 129
+    # the planes are within 384 KiB of the limit; a few more columns are rejected
+    assert 2**32 - 1 - 2**19 < nx * NY * vb <= 2**32 - 1
+    assert lbm.footprint_bytes(Params(nx=nx, ny=NY), precision) > 0
+    assert lbm.footprint_bytes(Params(nx=(2**32 - 1) // (vb * NY) + 1, ny=NY), precision) == 0
+    w, rl = _pattern(orc, walls, px)
+    print(f"\n[case] largest grid {nx}x{NY} {'fp64' if fp64 else 'fp32'} {'walled' if walls else 'periodic'}",
+          flush=True)
 
-    small = _run(lbm, w, 1, 1, "pattern")
+    small = _run(lbm, w, 1, 1, "pattern", precision)
     ref = orc.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
     ref.step(STEPS_TWO + STEPS_ONE)
     exp = ref.fields()
     err = [float(np.abs(a - b).max()) for a, b in zip(small, exp)]
     print(f"   pattern vs oracle: rho={err[0]:.3e} ux={err[1]:.3e} uy={err[2]:.3e} T={err[3]:.3e}", flush=True)
-    assert err[0] <= 2e-4 * rl
-    assert err[3] <= 2e-6 * float(np.abs(exp[3]).max())
-    assert max(err[1], err[2]) <= 1e-5
+    if fp64:  # rounding level, as the other FP64 parity tests
+        assert err[0] <= 1e-11 and err[3] <= 1e-13 and max(err[1], err[2]) <= 1e-13
+    else:
+        assert err[0] <= 2e-4 * rl
+        assert err[3] <= 2e-6 * float(np.abs(exp[3]).max())
+        assert max(err[1], err[2]) <= 1e-5
 
     torch.cuda.empty_cache()
     rows_rep = 1 if walls else NY // PY
-    big = _run(lbm, w, rows_rep, NX // PX, "full grid")
+    big = _run(lbm, w, rows_rep, nx // px, "full grid", precision)
     torch.cuda.empty_cache()
     for name, b, s in zip(("rho", "ux", "uy", "T"), big, small):
-        tiled = b.reshape(rows_rep, w.params.ny, NX // PX, PX)
+        tiled = b.reshape(rows_rep, w.params.ny, nx // px, px)
         same = tiled == s[None, :, None, :]
         if not same.all():
             k = np.argwhere(~same)[0]
