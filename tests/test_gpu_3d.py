@@ -2,9 +2,9 @@
 through the C ABI: a static droplet (periodic cube), an evaporating droplet in a Dirichlet
 temperature box, a ragged random case, the test flags; FP64 to rounding, FP32 after 100 steps
 within the two-dimensional bounds (rho within 2e-4 rho_l, T within 2e-6 relative, u within 1e-5);
-mass conservation of the FP64 diagnostics.  Both step paths: the fused kernel (default) on grids
-spanning several column tiles (64 x 8) with ragged edges and several z chunks, its results
-bit-identical for every chunking, and the per-node kernels."""
+mass conservation of the FP64 diagnostics; device-side failure detection.  Both step paths: the
+fused kernel (default) on grids spanning several column tiles (64 x 8) with ragged edges and
+several z chunks, its results bit-identical for every chunking, and the per-node kernels."""
 import numpy as np
 import pytest
 
@@ -269,3 +269,29 @@ def test_3d_fused_shear_wave_at_full_size(lbm3, orc):
     print(f"   rate {rate:.6e} against nu k^2 = {nu * k * k:.6e}", flush=True)
     assert rate == pytest.approx(nu * k * k, rel=1e-2)
     s.close()
+
+
+@pytest.mark.parametrize("path", [0, 1], ids=["fused", "per_node"])
+def test_3d_density_above_eos_limit_is_reported(lbm3, orc, path):
+    """A node whose density lies beyond the EOS limit (p_EOS > rho/3: no pseudopotential) is
+    flagged by the device on the first step; the context then refuses to step, and a healthy
+    context on the same device is unaffected."""
+    Tc, rl, rg = _sat(orc)
+    w = droplet3d(Tc, rl, rg, n=20, R=6.5)
+    p = w.params.replace(path=path)
+    rho = w.rho.copy()
+    rho[10, 10, 10] = 9.5
+    print(f"\n[case] 3d failure detection path={path}", flush=True)
+    s = lbm3.Solver3D(p).init(rho, w.ux, w.uy, w.uz, w.T)
+    s.step(1)
+    with pytest.raises(Exception) as e:
+        s.sync()
+    assert e.value.status == -4
+    with pytest.raises(Exception) as e:
+        s.step(1)
+    assert e.value.status == -5
+    s.close()
+    t = lbm3.Solver3D(p).init(w.rho, w.ux, w.uy, w.uz, w.T)
+    t.step(3)
+    t.sync()
+    t.close()
