@@ -131,12 +131,13 @@ class Server:
                     break
                 w = prep[r.rid].result()
                 need = footprint_bytes(w.params, self.precision)
+                if need > self.hbm_budget:  # can never fit: reject it now instead of blocking the queue
+                    queued.remove(r)
+                    del prep[r.rid]
+                    r.error = "footprint exceeds the HBM budget"
+                    r.t_done = now()
+                    continue
                 if used + need > self.hbm_budget:
-                    if not (running or ready or inflight) and need > self.hbm_budget:
-                        queued.remove(r)
-                        r.error = "footprint exceeds the HBM budget"
-                        r.t_done = now()
-                        continue
                     break  # wait for room (under "shortest" nothing smaller is ready either)
                 queued.remove(r)
                 del prep[r.rid]

@@ -124,6 +124,18 @@ def test_oversize_and_failing_requests_are_isolated(fake):
     assert FakeSolver.live == 0
 
 
+def test_oversize_request_does_not_block_the_queue(fake):
+    # request 1 can never fit; it is rejected when it reaches the head of the queue, while request 0
+    # runs, so request 2 is admitted next to request 0 instead of waiting for the server to drain
+    reqs = [_req(0, 640, 30), _req(1, 64, 1000), _req(2, 64, 10)]
+    done, summary = fake.Server(hbm_budget=50, max_slots=4, chunk=64).run(reqs, realtime=False)
+    by = {r.rid: r for r in done}
+    assert by[1].error == "footprint exceeds the HBM budget"
+    assert by[1].t_done <= by[0].t_done
+    assert by[2].t_admit <= by[0].t_done and by[2].t_done <= by[0].t_done
+    assert summary["completed"] == 2 and summary["failed"] == 1
+
+
 def test_fifo_baseline_runs_one_at_a_time(fake, monkeypatch):
     class Plain(FakeSolver):
         def step(self, n):
