@@ -129,8 +129,15 @@ class Server:
                 r = self._next(queued, prep, now())
                 if r is None:
                     break
-                w = prep[r.rid].result()
-                need = footprint_bytes(w.params, self.precision)
+                try:
+                    w = prep[r.rid].result()
+                    need = footprint_bytes(w.params, self.precision)
+                except Exception as e:  # noqa: BLE001 -- a request that cannot be prepared fails alone
+                    queued.remove(r)
+                    del prep[r.rid]
+                    r.error = f"preparing the request failed: {e}"
+                    r.t_done = now()
+                    continue
                 if need > self.hbm_budget:  # can never fit: reject it now instead of blocking the queue
                     queued.remove(r)
                     del prep[r.rid]
@@ -211,6 +218,8 @@ class Server:
             fut = prep[r.rid]
             if not fut.done():
                 continue
+            if fut.exception() is not None:
+                return r  # the caller records its failure and removes it
             w = fut.result()
             wk = w.nodes * r.steps
             if best is None or wk < work:
@@ -247,9 +256,9 @@ def fifo(requests, precision: int = LBM_FP32, realtime: bool = True, keep_result
         while realtime and r.arrival > now():
             time.sleep(min(0.05, r.arrival - now()))
         submit_arrived()
-        w = futs[r.rid].result()
         r.t_admit = now()
         try:
+            w = futs[r.rid].result()
             s = Solver(w.params, precision=precision).init(w.rho, w.ux, w.uy, w.T)
             r.nodes = w.nodes
             s.step(r.steps)

@@ -136,6 +136,34 @@ def test_oversize_request_does_not_block_the_queue(fake):
     assert summary["completed"] == 2 and summary["failed"] == 1
 
 
+@pytest.mark.parametrize("policy", ["arrival", "shortest"])
+def test_request_whose_fields_cannot_be_built_fails_alone(fake, policy):
+    def broken():
+        raise ValueError("no such workload")
+    reqs = [_req(0, 128, 10), serve.Request(rid=1, arrival=0.0, steps=64, make=broken), _req(2, 64, 10)]
+    done, summary = fake.Server(hbm_budget=50, max_slots=4, chunk=64, policy=policy).run(reqs, realtime=False)
+    by = {r.rid: r for r in done}
+    assert "no such workload" in by[1].error
+    assert by[0].result == (128,) and by[2].result == (64,)
+    assert summary["completed"] == 2 and summary["failed"] == 1
+
+
+def test_fifo_isolates_a_request_whose_fields_cannot_be_built(fake, monkeypatch):
+    class Plain(FakeSolver):
+        def step(self, n):
+            self.steps += n
+
+    def broken():
+        raise ValueError("no such workload")
+    monkeypatch.setattr(serve, "Solver", Plain)
+    reqs = [_req(0, 50, 10), serve.Request(rid=1, arrival=0.0, steps=64, make=broken), _req(2, 70, 10)]
+    done, summary = fake.fifo(reqs, realtime=False)
+    by = {r.rid: r for r in done}
+    assert "no such workload" in by[1].error
+    assert by[0].result == (50,) and by[2].result == (70,)
+    assert summary["completed"] == 2 and summary["failed"] == 1
+
+
 def test_fifo_baseline_runs_one_at_a_time(fake, monkeypatch):
     class Plain(FakeSolver):
         def step(self, n):
