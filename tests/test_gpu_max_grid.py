@@ -3,7 +3,7 @@ population plane of 65535 x 16383 nodes is 4 294 639 620 bytes, 320 KiB under th
 that the step kernel's 32-bit byte offsets can address (the limit lbm_validate enforces).  Both
 tile dimensions are ragged (65535 = 1023 x 64 + 63 columns, 16383 = 1023 x 16 + 15 rows).  In FP64
 the same bytes hold 32767 x 16383 nodes (384 KiB under the limit, 511 x 64 + 63 columns).  Three
-dimensions: a grid whose plane is above 2^31 bytes and whose state takes 184 GB (below).
+dimensions: grids whose planes are above 2^31 bytes, FP32 (184 GB of state) and FP64 (149 GB).
 
 The oracle cannot run 1.07e9 nodes, so the test uses a property that holds at any size: the
 update of a node depends only on its neighbourhood, so on a grid tiled with copies of a pattern
@@ -142,32 +142,33 @@ def test_largest_grid_equals_tiled_pattern(lbm, orc, walls, fp64):
 # cell.  Ragged column tiles in x (15 x 64 + 60) and y (127 x 8 + 4).
 NX3, NY3, NZ3 = 1020, 1020, 640
 PX3, PY3, PZ3 = 60, 51, 40
+NZ3_64, PZ3_64 = 260, 52  # FP64 (552 bytes per node): plane 2 163 968 000 bytes, state 149 GB
 
 
-def _pattern3(orc):
+def _pattern3(orc, pz: int = PZ3):
     from workloads import Params3D, Workload3D
     base = Params()
     Tc = orc.Tc(base)
     rl, rg, _ = orc.maxwell(base, 0.86 * Tc)
     rng = np.random.default_rng(22053)
-    z, y, x = np.mgrid[0:PZ3, 0:PY3, 0:PX3].astype(np.float64)
+    z, y, x = np.mgrid[0:pz, 0:PY3, 0:PX3].astype(np.float64)
 
     def per(a, n):
         return np.minimum(np.abs(a - n / 2), n - np.abs(a - n / 2))
 
-    r = np.sqrt(per(x, PX3) ** 2 + per(y, PY3) ** 2 + per(z, PZ3) ** 2)
+    r = np.sqrt(per(x, PX3) ** 2 + per(y, PY3) ** 2 + per(z, pz) ** 2)
     rho = rg + 0.5 * (rl - rg) * (1.0 - np.tanh((r - 12.0) / 2.5))
-    T = 0.88 * Tc + 0.01 * Tc * np.sin(2 * np.pi * x / PX3) + 0.005 * Tc * np.cos(2 * np.pi * z / PZ3)
+    T = 0.88 * Tc + 0.01 * Tc * np.sin(2 * np.pi * x / PX3) + 0.005 * Tc * np.cos(2 * np.pi * z / pz)
     rho = _quantise(rho * (1.0 + 1e-3 * rng.uniform(-1, 1, rho.shape)), 19)
     T = _quantise(T * (1.0 + 1e-4 * rng.uniform(-1, 1, T.shape)), 24)
     u = [1e-3 * rng.standard_normal(rho.shape) for _ in range(3)]
-    return Workload3D("max-grid pattern 3d", Params3D(nx=PX3, ny=PY3, nz=PZ3), rho, *u, T, 4), rl
+    return Workload3D("max-grid pattern 3d", Params3D(nx=PX3, ny=PY3, nz=pz), rho, *u, T, 4), rl
 
 
-def _run3(w, rep, path, name):
+def _run3(w, rep, path, name, precision=0):
     from paper_2205_00686_amd import three_d
     p = w.params.replace(nx=w.params.nx * rep[2], ny=w.params.ny * rep[1], nz=w.params.nz * rep[0], path=path)
-    s = three_d.Solver3D(p)
+    s = three_d.Solver3D(p, precision=precision)
     s.init(*(np.tile(a, rep) for a in (w.rho, w.ux, w.uy, w.uz, w.T)))
     s.step(w.steps)
     print(f"   {name} {p.nx}x{p.ny}x{p.nz} path {path}: stepped", flush=True)
@@ -176,35 +177,40 @@ def _run3(w, rep, path, name):
     return out
 
 
+@pytest.mark.parametrize("fp64", [False, True], ids=["fp32", "fp64"])
 @pytest.mark.parametrize("path", [0, 1], ids=["fused", "per_node"])
-def test_largest_3d_grid_equals_tiled_pattern(lbm, orc, path):
+def test_largest_3d_grid_equals_tiled_pattern(lbm, orc, path, fp64):
     import torch
     from oracle import o3d
     from paper_2205_00686_amd import three_d
     from workloads import Params3D
 
-    rep = (NZ3 // PZ3, NY3 // PY3, NX3 // PX3)
-    assert (rep[0] * PZ3, rep[1] * PY3, rep[2] * PX3) == (NZ3, NY3, NX3)
-    assert 2**31 < NX3 * NY3 * NZ3 * 4 <= 2**32 - 1
-    assert three_d.footprint_bytes3(Params3D(nx=NX3, ny=NY3, nz=NZ3)) < 190e9
-    w, rl = _pattern3(orc)
-    print(f"\n[case] largest 3d grid {NX3}x{NY3}x{NZ3} fp32 path {path}", flush=True)
+    nz, pz, vb = (NZ3_64, PZ3_64, 8) if fp64 else (NZ3, PZ3, 4)
+    rep = (nz // pz, NY3 // PY3, NX3 // PX3)
+    assert (rep[0] * pz, rep[1] * PY3, rep[2] * PX3) == (nz, NY3, NX3)
+    assert 2**31 < NX3 * NY3 * nz * vb <= 2**32 - 1
+    assert three_d.footprint_bytes3(Params3D(nx=NX3, ny=NY3, nz=nz), int(fp64)) < 190e9
+    w, rl = _pattern3(orc, pz)
+    print(f"\n[case] largest 3d grid {NX3}x{NY3}x{nz} {'fp64' if fp64 else 'fp32'} path {path}", flush=True)
 
-    small = _run3(w, (1, 1, 1), path, "pattern")
+    small = _run3(w, (1, 1, 1), path, "pattern", int(fp64))
     ref = o3d.Oracle3D(w.params).init(w.rho, w.ux, w.uy, w.uz, w.T)
     ref.step(w.steps)
     exp = ref.fields()
     err = [float(np.abs(a - b).max()) for a, b in zip(small, exp)]
     print("   pattern vs oracle: " + " ".join(f"{v:.3e}" for v in err), flush=True)
-    assert err[0] <= 2e-4 * rl
-    assert err[4] <= 2e-6 * float(np.abs(exp[4]).max())
-    assert max(err[1:4]) <= 1e-5
+    if fp64:
+        assert err[0] <= 1e-11 and err[4] <= 1e-13 and max(err[1:4]) <= 1e-13
+    else:
+        assert err[0] <= 2e-4 * rl
+        assert err[4] <= 2e-6 * float(np.abs(exp[4]).max())
+        assert max(err[1:4]) <= 1e-5
 
     torch.cuda.empty_cache()
-    big = _run3(w, rep, path, "full grid")
+    big = _run3(w, rep, path, "full grid", int(fp64))
     torch.cuda.empty_cache()
     for name, b, s in zip(("rho", "ux", "uy", "uz", "T"), big, small):
-        tiled = b.reshape(rep[0], PZ3, rep[1], PY3, rep[2], PX3)
+        tiled = b.reshape(rep[0], pz, rep[1], PY3, rep[2], PX3)
         same = tiled == s[None, :, None, :, None, :]
         if not same.all():
             k = np.argwhere(~same)[0]
