@@ -23,6 +23,7 @@ the same workload.
   python bench.py --mode heated                                  droplet evaporation on a heated surface
   python bench.py --mode 3d                                      three-dimensional extension (D3Q19 + D3Q7)
   python bench.py --mode ceiling                                 HBM copy ceiling (hand-written copy kernel)
+  python bench.py --mode cpu-baseline                            the FP64 oracle timed on the parity configurations
 """
 from __future__ import annotations
 
@@ -101,6 +102,56 @@ def cpu_baseline(w, steps):
                       f"({dt:.1f} s)",
             "single_core": {"value": w.nodes * steps1 / dt1 / 1e6, "steps": steps1, "seconds": round(dt1, 2)},
             "host": {"cpu": _host_cpu(), "logical_cpus": os.cpu_count()}}
+
+
+def run_cpu_baseline_mode(args):
+    """The FP64 oracle timed on the configurations of the parity tests, as a CPU reference: the
+    static droplet (64 x 64, 2000 steps) and the evaporation box (512 x 512, 20 000 steps) in full,
+    the boiling pool (1024 x 2048) over its first 2000 steps with the time for 50 000 steps
+    extrapolated; each on all host cores (OpenMP) and, for a stated sample, on one core."""
+    import oracle
+    import paper_2205_00686_amd as lbm
+    from workloads import Params, droplet
+
+    oracle.build(force=False)
+    base = Params()
+    Tc = lbm.critical_temperature(base)
+    rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
+    full = args.cpu_scale
+    cases = [
+        ("static droplet 64x64, FP64", droplet(Tc, rl, rg, nx=64, ny=64, R=16.0), int(2000 * full), 2000,
+         int(2000 * full)),
+        ("evaporation 512x512, FP64", build_workload(512, 512, 20000, "evaporation"), int(20000 * full), 20000,
+         max(1, int(200 * full))),
+        ("boiling 1024x2048 (head-limited fill), FP64", build_workload(1024, 2048, 50000, "boiling"),
+         max(2, int(2000 * full)), 50000, max(1, int(20 * full))),
+    ]
+    cores = oracle.num_threads()
+    runs = []
+    for name, w, steps, horizon, steps1 in cases:
+        o = oracle.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+        oracle.set_threads(1)
+        try:
+            o1 = oracle.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
+            t1 = time.perf_counter()
+            o1.step(steps1)
+            dt1 = time.perf_counter() - t1
+        finally:
+            oracle.set_threads(cores)
+        run = {"config": name, "nodes": w.nodes, "steps": steps, "seconds": round(dt, 2),
+               "mlups": round(w.nodes * steps / dt / 1e6, 2), "horizon_steps": horizon,
+               "horizon_seconds": round(dt * horizon / steps, 1) if steps else None,
+               "horizon_measured": steps == horizon,
+               "single_core": {"steps": steps1, "seconds": round(dt1, 2),
+                               "mlups": round(w.nodes * steps1 / dt1 / 1e6, 2)}}
+        runs.append(run)
+        print(f"[bench] {json.dumps(run)}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "FP64 oracle MLUPS on the host (CPU reference)", "unit": "MLUPS", "kind": "oracle",
+                      "cores": cores, "host": {"cpu": _host_cpu(), "logical_cpus": os.cpu_count()},
+                      "runs": runs}))
 
 
 def shape_text(lbm, precision, k):
@@ -806,8 +857,10 @@ def run_headline(args):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--mode", choices=["plain", "batch", "serve", "fritz", "lattice", "heated", "3d", "ceiling"],
-                    default="plain")
+    ap.add_argument("--mode", choices=["plain", "batch", "serve", "fritz", "lattice", "heated", "3d", "ceiling",
+                                       "cpu-baseline"], default="plain")
+    ap.add_argument("--cpu-scale", type=float, default=1.0,
+                    help="cpu-baseline: fraction of each configuration's timed steps (1: as documented)")
     ap.add_argument("--gravities", default="1e-5,1.5e-5,2e-5,3e-5,4e-5,6e-5")
     ap.add_argument("--dT-rel", type=float, default=0.19)
     ap.add_argument("--hot-width", type=float, default=8.0)
@@ -869,6 +922,8 @@ def main():
         return run_3d_mode(args)
     if args.mode == "ceiling":
         return run_ceiling_mode(args)
+    if args.mode == "cpu-baseline":
+        return run_cpu_baseline_mode(args)
     if args.mode == "heated":
         args.steps = args.steps or 400000
         if args.check_every == 250:
