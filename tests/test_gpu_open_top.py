@@ -1,9 +1,9 @@
 """GPU parity of the open top boundary (outflow condition of the paper's open-top problems,
 Sections 4.2-4.3) against the FP64 oracle through the C ABI: the heated-surface droplet and an
 open-top boiling pool, FP64 to rounding and FP32 to the bounds of the other parity tests (rho
-within 2e-4 rho_l after 300 steps, T within 2e-6 relative, u within 1e-5); every one-step tile
-shape gives the same bits; save/load resumes bit for bit; a batch with open-top members equals
-their single runs."""
+within 2e-4 rho_l after 300 steps, T within 2e-6 relative, u within 1e-5); the smallest and
+ragged grids from random fields in FP64; every one-step tile shape gives the same bits; save/load
+resumes bit for bit; a batch with open-top members equals their single runs."""
 import numpy as np
 import pytest
 
@@ -124,3 +124,21 @@ def test_batch_with_open_top_members_equals_alone(lbm, orc):
         for got, e in zip(s.fields(), exp):
             assert np.array_equal(got, e)
         s.close()
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (5, 4), (65, 17), (200, 3), (130, 23)])
+def test_open_top_fp64_small_and_ragged_grids(lbm, orc, nx, ny):
+    """Open top on the smallest grids (three rows: the wall row, one fluid row, the open row) and on
+    ragged multi-tile grids, from random fields with gravity and a hot spot: FP64 to rounding."""
+    Tc, rl, rg = _sat(orc)
+    rng = np.random.default_rng(nx * 1000 + ny)
+    rho = rg + (rl - rg) * rng.uniform(0.0, 1.0, (ny, nx))
+    T = 0.86 * Tc * (1 + 0.01 * rng.uniform(-1, 1, (ny, nx)))
+    ux = 0.01 * rng.standard_normal((ny, nx))
+    uy = 0.01 * rng.standard_normal((ny, nx))
+    p = Params(nx=nx, ny=ny, y_walls=1, open_top=1, T_bot=0.9 * Tc, T_top=0.85 * Tc, hot_dT=0.05 * Tc,
+               hot_x0=nx / 3, hot_sigma=2.0, theta_bot_deg=70.0, theta_top_deg=100.0, gy=-1e-4)
+    from workloads import Workload
+    w = Workload("random open top", p, rho, ux, uy, T, 20)
+    _, _, got, exp, err = _run(lbm, orc, w, 20, lbm.LBM_FP64, f"random open top {nx}x{ny}")
+    assert err["rho"] <= 1e-11 and err["T"] <= 1e-13 and max(err["ux"], err["uy"]) <= 1e-12
