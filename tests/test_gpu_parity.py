@@ -96,6 +96,24 @@ def test_fp64_small_and_ragged_grids(lbm, orc, nx, ny, walls):
     assert err["rho"] <= 1e-11 and err["T"] <= 1e-13 and max(err["ux"], err["uy"]) <= 1e-12
 
 
+@pytest.mark.parametrize("nx,ny,walls", [(3, 3, 0), (4, 5, 0), (65, 17, 0), (130, 23, 0), (5, 4, 1), (65, 17, 1)])
+def test_fp64_thermal_box_small_and_ragged_grids(lbm, orc, nx, ny, walls):
+    """Dirichlet temperature box (all four edges, anti-bounce-back), alone and with walls, on the
+    smallest and ragged multi-tile grids from random fields: FP64 to rounding."""
+    Tc, rl, rg = _fixtures(orc)
+    rng = np.random.default_rng(nx * 100 + ny + 7)
+    rho = rg + (rl - rg) * rng.uniform(0.0, 1.0, (ny, nx))
+    T = 0.86 * Tc * (1 + 0.01 * rng.uniform(-1, 1, (ny, nx)))
+    ux = 0.01 * rng.standard_normal((ny, nx))
+    uy = 0.01 * rng.standard_normal((ny, nx))
+    p = Params(nx=nx, ny=ny, thermal_box=1, T_box=0.9 * Tc, y_walls=walls, T_bot=0.9 * Tc, T_top=0.85 * Tc,
+               theta_bot_deg=70.0, theta_top_deg=100.0, gy=-1e-4 if walls else 0.0)
+    from workloads import Workload
+    w = Workload("random box", p, rho, ux, uy, T, 20)
+    _, _, got, exp, err = _case(f"random thermal box walls={walls}", w, 20, lbm.LBM_FP64, lbm, orc)
+    assert err["rho"] <= 1e-11 and err["T"] <= 1e-13 and max(err["ux"], err["uy"]) <= 1e-12
+
+
 @pytest.mark.parametrize("flags", [FREEZE_FLOW, FREEZE_FLOW | NO_S, NO_S])
 def test_fp64_test_flags(lbm, orc, flags):
     Tc, rl, rg = _fixtures(orc)
