@@ -114,6 +114,30 @@ def test_fp64_thermal_box_small_and_ragged_grids(lbm, orc, nx, ny, walls):
     assert err["rho"] <= 1e-11 and err["T"] <= 1e-13 and max(err["ux"], err["uy"]) <= 1e-12
 
 
+@pytest.mark.parametrize("nx,ny,kind", [(3, 3, "periodic"), (5, 3, "walls"), (4, 5, "box"), (5, 4, "open"),
+                                        (65, 17, "walls"), (130, 23, "box+walls"), (200, 3, "open")])
+def test_fp32_small_and_ragged_grids(lbm, orc, nx, ny, kind):
+    """Every boundary kind on the smallest and ragged grids in FP32, from random fields: within the
+    FP32 bounds of the other parity tests (rho 2e-4 rho_l, T 2e-6 relative, u 1e-5)."""
+    Tc, rl, rg = _fixtures(orc)
+    rng = np.random.default_rng(nx * 100 + ny + 11)
+    # densities up to 0.85 of the liquid's, so that the wetting ghost (Eq. 54) of a random field stays
+    # below the density where the EOS leaves the pseudopotential undefined
+    rho = rg + (rl - rg) * rng.uniform(0.0, 0.85, (ny, nx))
+    T = 0.86 * Tc * (1 + 0.01 * rng.uniform(-1, 1, (ny, nx)))
+    ux = 0.01 * rng.standard_normal((ny, nx))
+    uy = 0.01 * rng.standard_normal((ny, nx))
+    walls = int(kind in ("walls", "box+walls", "open"))
+    p = Params(nx=nx, ny=ny, y_walls=walls, thermal_box=int("box" in kind), T_box=0.9 * Tc, open_top=int(kind == "open"),
+               T_bot=0.9 * Tc, T_top=0.85 * Tc, hot_dT=0.05 * Tc if walls else 0.0, hot_x0=nx / 3, hot_sigma=2.0,
+               theta_bot_deg=70.0, theta_top_deg=100.0, gy=-1e-4 if walls else 0.0)
+    from workloads import Workload
+    w = Workload("random", p, rho, ux, uy, T, 20)
+    _, _, got, exp, err = _case(f"random fp32 {kind}", w, 20, lbm.LBM_FP32, lbm, orc)
+    assert err["rho"] <= 2e-4 * rl and err["T"] <= 2e-6 * float(np.abs(exp[3]).max())
+    assert max(err["ux"], err["uy"]) <= 1e-5
+
+
 @pytest.mark.parametrize("flags", [FREEZE_FLOW, FREEZE_FLOW | NO_S, NO_S])
 def test_fp64_test_flags(lbm, orc, flags):
     Tc, rl, rg = _fixtures(orc)
