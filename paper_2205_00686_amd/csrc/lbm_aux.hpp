@@ -162,13 +162,18 @@ __device__ __forceinline__ int cc_load(const int* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ int cc_find(const int* lab, int k) {
-  int p = cc_load(lab + k);
-  while (p != k) {
-    k = p;
-    p = cc_load(lab + k);
+// Root of node k, halving the path on the way: each visited node is pointed at its grandparent (an
+// ancestor, so the node stays in its tree; an atomic minimum, so parents still only decrease).
+// Every iteration moves k to a strictly smaller index, so the walk ends.
+__device__ __forceinline__ int cc_find(int* lab, int k) {
+  for (;;) {
+    const int p = cc_load(lab + k);
+    if (p == k) return k;
+    const int gp = cc_load(lab + p);
+    if (gp == p) return p;
+    atomicMin(lab + k, gp);
+    k = gp;
   }
-  return k;
 }
 
 // Join the trees of vapour nodes a and b.  A failed link (the root a got a parent meanwhile)
@@ -242,15 +247,52 @@ __global__ __launch_bounds__(CC_NT) void cc_number_kernel(int* __restrict__ lab,
   lab[k] = -2 - (id < cap ? id : cap);
 }
 
+// Per-component statistics.  Integer atomics make the result independent of their order, but many
+// atomics on one address serialise: a component of a million nodes took milliseconds.  So a
+// wavefront whose labelled lanes all belong to one component first combines their values with
+// cross-lane butterflies and one lane updates the table; mixed wavefronts update it lane by lane.
+// Every thread stays to the end (the butterflies read all 64 lanes).
 __global__ __launch_bounds__(CC_NT) void cc_stats_kernel(const int* __restrict__ lab, int nx, int n, int y_lo,
                                                          CompStat* __restrict__ tab, int cap) {
   const int k = blockIdx.x * CC_NT + threadIdx.x;
-  if (k >= n) return;
-  const int v = lab[k];
-  if (v == -1) return;
-  const int id = v <= -2 ? -2 - v : -2 - lab[v];
-  if (id >= cap) return;
-  const int x = k % nx, y = y_lo + k / nx;
+  int id = -1;
+  if (k < n) {
+    const int v = lab[k];
+    if (v != -1) {
+      id = v <= -2 ? -2 - v : -2 - lab[v];
+      if (id >= cap) id = -1;
+    }
+  }
+  const int x = k < n ? k % nx : 0, y = k < n ? y_lo + k / nx : 0;
+  const unsigned long long has = __ballot(id >= 0);
+  if (has == 0ull) return;  // uniform: the whole wavefront leaves together
+  const int lead = __builtin_amdgcn_readlane(id, __builtin_ctzll(has));
+  if (__ballot(id >= 0 && id != lead) == 0ull) {
+    const bool mine = id >= 0;
+    int area = mine ? 1 : 0, y0 = mine ? y : 0x7fffffff, y1 = mine ? y : -1;
+    int x0 = mine ? x : 0x7fffffff, x1 = mine ? x : -1;
+    unsigned long long ys = mine ? (unsigned long long)y : 0ull;
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) {
+      area += __shfl_xor(area, s, 64);
+      y0 = min(y0, __shfl_xor(y0, s, 64));
+      y1 = max(y1, __shfl_xor(y1, s, 64));
+      x0 = min(x0, __shfl_xor(x0, s, 64));
+      x1 = max(x1, __shfl_xor(x1, s, 64));
+      ys += __shfl_xor(ys, s, 64);
+    }
+    if ((int)(threadIdx.x & 63u) == __builtin_ctzll(has)) {
+      CompStat& c = tab[lead];
+      atomicAdd(&c.area, area);
+      atomicMin(&c.y_min, y0);
+      atomicMax(&c.y_max, y1);
+      atomicMin(&c.x_min, x0);
+      atomicMax(&c.x_max, x1);
+      atomicAdd(&c.y_sum, ys);
+    }
+    return;
+  }
+  if (id < 0) return;
   CompStat& c = tab[id];
   atomicAdd(&c.area, 1);
   atomicMin(&c.y_min, y);
