@@ -24,6 +24,7 @@ the same workload.
   python bench.py --mode 3d                                      three-dimensional extension (D3Q19 + D3Q7)
   python bench.py --mode ceiling                                 HBM copy ceiling (hand-written copy kernel)
   python bench.py --mode cpu-baseline                            the FP64 oracle timed on the parity configurations
+  python bench.py --mode readout                                 cost of the readouts (vapour rows and components, fields)
 """
 from __future__ import annotations
 
@@ -128,6 +129,7 @@ def run_cpu_baseline_mode(args):
     ]
     cores = oracle.num_threads()
     runs = []
+    gpu = _gpu_available()
     for name, w, steps, horizon, steps1 in cases:
         o = oracle.Oracle(w.params).init(w.rho, w.ux, w.uy, w.T)
         t0 = time.perf_counter()
@@ -147,11 +149,73 @@ def run_cpu_baseline_mode(args):
                "horizon_measured": steps == horizon,
                "single_core": {"steps": steps1, "seconds": round(dt1, 2),
                                "mlups": round(w.nodes * steps1 / dt1 / 1e6, 2)}}
+        if gpu:  # the same steps on the GPU, the library's default tile shape; FP64 only for the droplet
+            prec = lbm.LBM_FP64 if "droplet" in name else lbm.LBM_FP32
+            sg = lbm.Solver(w.params, precision=prec).init(w.rho, w.ux, w.uy, w.T)
+            sg.step(min(steps, 64))
+            ms = _timed_steps(sg, steps)
+            sg.sync()
+            sg.close()
+            run["gpu"] = {"precision": "fp64" if prec == lbm.LBM_FP64 else "fp32", "steps": steps,
+                          "seconds": round(ms / 1e3, 4), "us_per_step": round(ms * 1e3 / steps, 2),
+                          "horizon_seconds": round(ms / 1e3 * horizon / steps, 3)}
         runs.append(run)
         print(f"[bench] {json.dumps(run)}", file=sys.stderr, flush=True)
     print(json.dumps({"metric": "FP64 oracle MLUPS on the host (CPU reference)", "unit": "MLUPS", "kind": "oracle",
                       "cores": cores, "host": {"cpu": _host_cpu(), "logical_cpus": os.cpu_count()},
                       "runs": runs}))
+
+
+def _gpu_available() -> bool:
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except ImportError:
+        return False
+
+
+def run_readout_mode(args):
+    """Cost of the readouts of a running simulation, on the boiling pool (1024 x 2048, FP32) after
+    args.steps steps: the per-row vapour counts of the departure trigger, the vapour components of
+    the band below the pool surface and of the whole grid (the vapour above the pool is one component
+    of about a million nodes), all fields to the host, and the FP64 diagnostics.  Each call is timed
+    on the host around the synchronising call (median of 5 after one untimed call)."""
+    import paper_2205_00686_amd as lbm
+    from workloads import Params
+
+    base = Params()
+    Tc = lbm.critical_temperature(base)
+    rl, rg, _ = lbm.coexistence(base, 0.86 * Tc)
+    w = build_workload(args.nx, args.ny, args.steps, "boiling")
+    s = lbm.Solver(w.params).init(w.rho, w.ux, w.uy, w.T)
+    s.step(args.steps)
+    s.sync()
+    mid = 0.5 * (rl + rg)
+    y_surface = int(min(w.meta["fill"], 1.0) * args.ny) - 12
+    calls = {
+        "vapour_rows (all rows, all columns)": lambda: s.vapour_rows(mid, 0, args.nx),
+        f"vapour_components rows 0..{y_surface}": lambda: s.vapour_components(mid, 0, y_surface + 1),
+        f"vapour_components rows 0..{args.ny}": lambda: s.vapour_components(mid, 0, args.ny),
+        "read_fields (4 FP64 fields to the host)": lambda: s.fields(),
+        "diagnostics (FP64 mass and energy)": lambda: s.diagnostics(),
+    }
+    out = {}
+    for name, fn in calls.items():
+        res = fn()
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        out[name] = {"ms": round(sorted(ts)[2] * 1e3, 3)}
+        if name.startswith("vapour_components"):
+            out[name]["components"] = len(res)
+            out[name]["largest_area"] = max((c["area"] for c in res), default=0)
+        print(f"[bench] {name}: {json.dumps(out[name])}", file=sys.stderr, flush=True)
+    s.close()
+    print(json.dumps({"metric": "readout cost (ms per call)", "mode": "readouts",
+                      "config": {"workload": f"boiling pool {args.nx}x{args.ny}, FP32, after {args.steps} steps"},
+                      "calls": out}))
 
 
 def shape_text(lbm, precision, k):
@@ -858,7 +922,7 @@ def run_headline(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--mode", choices=["plain", "batch", "serve", "fritz", "lattice", "heated", "3d", "ceiling",
-                                       "cpu-baseline"], default="plain")
+                                       "cpu-baseline", "readout"], default="plain")
     ap.add_argument("--cpu-scale", type=float, default=1.0,
                     help="cpu-baseline: fraction of each configuration's timed steps (1: as documented)")
     ap.add_argument("--gravities", default="1e-5,1.5e-5,2e-5,3e-5,4e-5,6e-5")
@@ -924,6 +988,9 @@ def main():
         return run_ceiling_mode(args)
     if args.mode == "cpu-baseline":
         return run_cpu_baseline_mode(args)
+    if args.mode == "readout":
+        args.steps = args.steps or 2000
+        return run_readout_mode(args)
     if args.mode == "heated":
         args.steps = args.steps or 400000
         if args.check_every == 250:
